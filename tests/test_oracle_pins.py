@@ -1,0 +1,350 @@
+"""Pins for the CPU oracle: facts fixed by the paper or by mathematics, checked
+without the oracle's own formulas.  These run without a GPU.
+
+Each test names the passage of Fercoq, Gramfort & Salmon (ICML 2015) or the
+textbook fact it relies on.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _st(u, x):
+    return np.sign(x) * np.maximum(np.abs(x) - u, 0.0)
+
+
+def _small_c1_like(seed=11, n=72, p=400):
+    rng = np.random.default_rng(seed)
+    X = synth.ar1_columns(rng, n, p, 0.5)
+    X -= X.mean(0)
+    X /= X.std(0)
+    beta = np.zeros(p)
+    idx = rng.choice(p, 8, replace=False)
+    beta[idx] = rng.choice([-1.0, 1.0], 8)
+    s = X @ beta
+    y = s + np.linalg.norm(s) / (3 * np.sqrt(n)) * rng.standard_normal(n)
+    return X.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------- lambda_max
+
+def test_lambda_max_gives_zero(orc):
+    """Sec. 1.2: for lambda >= lambda_max = ||X^T y||_inf, beta = 0 solves the
+    Lasso, and theta = y/lambda makes the gap vanish."""
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    lmax = np.abs(X.T @ y).max()
+    r = orc.lasso_path(X, y, lambdas=[lmax * 2.0, lmax * (1 + 1e-9)])
+    assert np.all(r["beta"] == 0.0)
+    assert np.all(r["epochs"] == 0)
+    assert np.all(np.abs(r["gap"]) <= 1e-12 * (y @ y))
+    # Just below lambda_max the solution is nonzero, on the argmax coordinate.
+    r2 = orc.lasso_path(X, y, lambdas=[lmax * (1 - 1e-3)], eps_rel=1e-14)
+    nz = np.flatnonzero(r2["beta"][0])
+    assert list(nz) == [int(np.argmax(np.abs(X.T @ y)))]
+    # The largest correlation is taken in absolute value: flip y so that the
+    # sign of the extreme correlation changes.
+    for yy in (y, -y):
+        assert np.isclose(orc.precompute(X, yy)["lambda_max"], lmax, rtol=1e-14)
+        rr = orc.lasso_path(X, yy, lambdas=[1.0 + 1e-9], relative=True)
+        assert np.isclose(rr["lambdas"][0], lmax * (1 + 1e-9), rtol=1e-14)
+        assert np.all(rr["beta"] == 0.0)
+
+
+# ----------------------------------------------------- orthonormal closed form
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_orthonormal_soft_threshold(orc, seed):
+    """With X^T X = I the Lasso separates: beta_j = ST(lambda, x_j^T y)
+    (Algorithm 1's update with ||x_j|| = 1 and x_j^T(X beta - y) =
+    beta_j - x_j^T y).  CD reaches it in one epoch; at the solution the sphere
+    test keeps exactly the equicorrelation set {j : |x_j^T y| >= lambda}
+    (Sec. 2, equicorrelation set; Theorem 1).  At the exact solution those
+    coordinates sit on the boundary |x_j^T theta| = 1, so the comparison uses
+    the kept set with the rounding-inflated radius."""
+    d = synth.orthonormal(seed, 60, 25)
+    X, y = d["X"], d["y"]
+    xty = X.T @ y
+    a = np.sort(np.abs(xty))
+    lam = 0.5 * (a[-8] + a[-9])               # 8 active, margin on both sides
+    r = orc.lasso_path(X, y, lambdas=[lam], f=1, eps_rel=1e-13)
+    want = _st(lam, xty)
+    assert r["status"][0] == 0
+    assert r["epochs"][0] == 1
+    np.testing.assert_allclose(r["beta"][0], want, rtol=0, atol=1e-13)
+    s = orc.screen(X, y, r["beta"][0], lam)
+    assert s["gap"] <= 1e-12 * (y @ y)
+    assert set(np.flatnonzero(s["keep_safe"])) == set(np.flatnonzero(np.abs(xty) >= lam))
+
+
+# --------------------------------------------------------------------- KKT
+
+@pytest.mark.parametrize("which", ["c0", "c1small"])
+def test_kkt_at_tight_solution(orc, which):
+    """Sec. 1.2 KKT: x_j^T theta = sign(beta_j) on the support and lies in
+    [-1, 1] elsewhere, with theta = (y - X beta)/lambda (primal-dual link)."""
+    if which == "c0":
+        d = synth.c0()
+        X, y = d["X"], d["y"]
+    else:
+        X, y = _small_c1_like()
+    lmax = np.abs(X.T @ y).max()
+    lams = lmax * np.array([0.5, 0.1, 0.02])
+    r = orc.lasso_path(X, y, lambdas=lams, eps_rel=1e-14)
+    assert np.all(r["status"] == 0)
+    for t, lam in enumerate(lams):
+        b = r["beta"][t]
+        corr = X.T @ (y - X @ b) / lam
+        assert np.abs(corr).max() <= 1 + 1e-6
+        S = b != 0
+        np.testing.assert_allclose(corr[S], np.sign(b[S]), atol=1e-6)
+
+
+# ----------------------------------------------------- brute force, tiny p
+
+def _brute_force_lasso(X, y, lam):
+    """Textbook KKT enumeration: for every sign pattern s in {-1,0,1}^p with
+    support S solve X_S^T X_S b = X_S^T y - lam s_S; accept when signs agree
+    and |x_j^T (y - X_S b)| <= lam off S; return the minimum-objective one."""
+    n, p = X.shape
+    best, best_obj = None, np.inf
+    for s in itertools.product((-1, 0, 1), repeat=p):
+        s = np.array(s, dtype=float)
+        S = np.flatnonzero(s)
+        b = np.zeros(p)
+        if len(S):
+            XS = X[:, S]
+            try:
+                bS = np.linalg.solve(XS.T @ XS, XS.T @ y - lam * s[S])
+            except np.linalg.LinAlgError:
+                continue
+            if np.any(np.sign(bS) != s[S]):
+                continue
+            b[S] = bS
+        r = y - X @ b
+        off = np.setdiff1d(np.arange(p), S)
+        if len(off) and np.abs(X[:, off].T @ r).max() > lam * (1 + 1e-12):
+            continue
+        obj = 0.5 * r @ r + lam * np.abs(b).sum()
+        if obj < best_obj:
+            best, best_obj = b, obj
+    return best
+
+
+@pytest.mark.parametrize("n,p,seed", [(5, 7, 0), (20, 8, 1), (20, 6, 2), (5, 8, 3)])
+def test_brute_force_tiny(orc, n, p, seed):
+    d = synth.gaussian(100 + seed, n, p, k=3, sigma=0.3)
+    X, y = d["X"], d["y"]
+    lmax = np.abs(X.T @ y).max()
+    for ratio in (0.6, 0.25, 0.08):
+        lam = ratio * lmax
+        want = _brute_force_lasso(X, y, lam)
+        r = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-15, K=2_000_000)
+        np.testing.assert_allclose(r["beta"][0], want, rtol=0, atol=1e-7)
+
+
+# -------------------------------------------- independent solver cross-check
+
+def test_sklearn_cross_check(orc):
+    """An independent coordinate-descent implementation (scikit-learn, whose
+    objective is (1/2n)||y - X b||^2 + a||b||_1, so a = lambda/n) agrees at a
+    tight tolerance."""
+    sk = pytest.importorskip("sklearn.linear_model")
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    n = X.shape[0]
+    lam = 0.1 * np.abs(X.T @ y).max()
+    r = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-15, K=10_000_000)
+    m = sk.Lasso(alpha=lam / n, fit_intercept=False, tol=1e-16,
+                 max_iter=10_000_000).fit(X, y)
+    np.testing.assert_allclose(r["beta"][0], m.coef_, atol=1e-7)
+
+
+# ------------------------------------------------------------------ safety
+
+def test_safety_invariant(orc):
+    """Sec. 2, eq. of the safe test: every coordinate screened out at any pass
+    is zero at the optimum.  The optimum is a separate, tighter run."""
+    X, y = _small_c1_like()
+    lmax = np.abs(X.T @ y).max()
+    lams = lmax * np.geomspace(1, 1e-2, 15)
+    r = orc.lasso_path(X, y, lambdas=lams, want_screened=True)
+    tight = orc.lasso_path(X, y, lambdas=lams, eps_rel=1e-14)
+    for t in range(len(lams)):
+        scr = r["screened"][t].astype(bool)
+        assert scr.sum() > 0 or t == 0
+        assert np.all(tight["beta"][t][scr] == 0.0), t
+
+
+def test_finite_identification(orc):
+    """Theorem 1: as the GAP sphere shrinks, the safe active set equals the
+    equicorrelation set {j : |x_j^T theta_hat| = 1}, computed here with numpy
+    from the tight solution."""
+    X, y = _small_c1_like(seed=5)
+    lmax = np.abs(X.T @ y).max()
+    lam = 0.05 * lmax
+    r = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-15, K=10_000_000)
+    b = r["beta"][0]
+    theta = (y - X @ b) / lam
+    E = set(np.flatnonzero(np.abs(X.T @ theta) >= 1 - 1e-7))
+    s = orc.screen(X, y, b, lam)
+    assert set(np.flatnonzero(s["keep_exact"])) == E
+    assert set(np.flatnonzero(b)) <= E
+
+
+# ---------------------------------------------------------- gap and radius
+
+def _feasible_theta(X, rng, scale=0.9):
+    th = rng.standard_normal(X.shape[0])
+    return scale * th / np.abs(X.T @ th).max()
+
+
+def test_weak_duality_random_points(orc):
+    """Sec. 3.2 (proof of Theorem 2): D(theta) <= P(beta) for every beta and
+    every dual-feasible theta."""
+    rng = np.random.default_rng(0)
+    d = synth.gaussian(7, 30, 80)
+    X, y = d["X"], d["y"]
+    for _ in range(50):
+        beta = rng.standard_normal(80) * (rng.random(80) < 0.2)
+        th = _feasible_theta(X, rng, rng.uniform(0.1, 1.0))
+        lam = rng.uniform(0.01, 1.0) * np.abs(X.T @ y).max()
+        g, P, D = orc.gap(X, y, beta, th, lam)
+        assert g >= -1e-12 * max(1.0, abs(P))
+
+
+def test_prop3_sequential_identity(orc):
+    """Proposition 3: r_t^2 = (l_{t-1}/l_t) r_{t-1}^2 + (1 - l_t/l_{t-1})
+    ||(X beta - y)/l_t||^2 - (l_{t-1}/l_t - 1) ||theta||^2, r^2 = 2G/l^2."""
+    rng = np.random.default_rng(1)
+    d = synth.gaussian(8, 40, 120)
+    X, y = d["X"], d["y"]
+    for _ in range(20):
+        beta = rng.standard_normal(120) * (rng.random(120) < 0.1)
+        th = _feasible_theta(X, rng)
+        l0 = rng.uniform(0.1, 1.0) * np.abs(X.T @ y).max()
+        l1 = l0 * rng.uniform(0.3, 0.99)
+        g0 = orc.gap(X, y, beta, th, l0)[0]
+        g1 = orc.gap(X, y, beta, th, l1)[0]
+        lhs = 2 * g1 / l1 ** 2
+        res = X @ beta - y
+        rhs = (l0 / l1) * 2 * g0 / l0 ** 2 + (1 - l1 / l0) * (res @ res) / l1 ** 2 \
+            - (l0 / l1 - 1) * (th @ th)
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
+
+
+def test_pass_gap_matches_definition(orc):
+    """The screening pass's gap equals P(beta) - D(alpha rho) with theta from
+    the rescaled residual (Sec. 2.3), and theta is dual feasible."""
+    rng = np.random.default_rng(2)
+    X, y = _small_c1_like(seed=3)
+    lmax = np.abs(X.T @ y).max()
+    for _ in range(10):
+        beta = 0.3 * rng.standard_normal(X.shape[1]) * (rng.random(X.shape[1]) < 0.05)
+        lam = rng.uniform(0.01, 0.9) * lmax
+        s = orc.screen(X, y, beta, lam)
+        rho = y - X @ beta
+        theta = s["alpha"] * rho
+        assert np.abs(X.T @ theta).max() <= 1 + 1e-12
+        g = orc.gap(X, y, beta, theta, lam)[0]
+        assert abs(s["gap"] - g) <= 1e-9 * max(1.0, abs(g))
+        # theta is the point of Delta along rho closest to y/lambda (Sec. 2.3)
+        ts = np.linspace(-1, 1, 2001) / np.abs(X.T @ rho).max()
+        dist = [np.linalg.norm(a * rho - y / lam) for a in ts]
+        assert np.linalg.norm(theta - y / lam) <= min(dist) + 1e-12
+
+
+def test_radius_bounds_thm2_prop1(orc):
+    """Theorem 2 / Proposition 1: r_tilde = sqrt(R^2 - r_check^2) <= r =
+    sqrt(2G)/lambda, and the ball B(theta, r) contains theta_hat (from a
+    tight solve)."""
+    rng = np.random.default_rng(4)
+    X, y = _small_c1_like(seed=4)
+    lmax = np.abs(X.T @ y).max()
+    lam = 0.1 * lmax
+    tight = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-15, K=10_000_000)
+    th_hat = (y - X @ tight["beta"][0]) / lam
+    for K in (0, 3, 10, 30, 100):
+        r = orc.lasso_path(X, y, lambdas=[lam], K=K, eps_rel=1e-30)
+        b = r["beta"][0]
+        s = orc.screen(X, y, b, lam)
+        theta = s["alpha"] * (y - X @ b)
+        R = np.linalg.norm(theta - y / lam)
+        res = X @ b - y
+        rc2 = max(y @ y - res @ res - 2 * lam * np.abs(b).sum(), 0.0) / lam ** 2
+        # R^2 - r_check^2 cancels: its rounding error scales with R^2 + r_check^2
+        assert R * R - rc2 <= s["radius"] ** 2 * (1 + 1e-9) + 1e-13 * (R * R + rc2)
+        assert np.linalg.norm(theta - th_hat) <= s["radius"] * (1 + 1e-9) + 1e-12
+    # Proposition 2: the radius goes to zero with the iterates.
+    assert s["radius"] < 1e-3
+
+
+def test_inflated_test_is_superset(orc):
+    """The rounding-inflated kept set contains the exact-formula one."""
+    X, y = _small_c1_like(seed=6)
+    rng = np.random.default_rng(6)
+    lmax = np.abs(X.T @ y).max()
+    for _ in range(5):
+        beta = 0.2 * rng.standard_normal(X.shape[1]) * (rng.random(X.shape[1]) < 0.05)
+        s = orc.screen(X, y, beta, rng.uniform(0.05, 0.9) * lmax)
+        assert np.all(s["keep_safe"] >= s["keep_exact"])
+        # Proposition 1's radius sqrt(2G)/lambda, inflated only by rounding.
+        assert s["radius"] <= s["radius_inflated"] <= s["radius"] * (1 + 1e-6) + 1e-9
+
+
+# ----------------------------------------------------------------- the grid
+
+def test_grid(orc):
+    """Sec. 3.3: lambda_t = lambda_max 10^(-delta t/(T-1)), t = 0..T-1."""
+    g = orc.grid(2.5, 100, 3.0)
+    assert g[0] == 2.5
+    assert np.isclose(g[-1], 2.5e-3, rtol=1e-14)
+    ratios = g[1:] / g[:-1]
+    np.testing.assert_allclose(ratios, 10 ** (-3 / 99), rtol=1e-13)
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_zero_column_and_duplicates(orc):
+    """A zero column is always screened and stays zero (its test value is 0).
+    Duplicated columns make beta non-unique but theta unique (Sec. 1.1): the
+    fit X beta and theta agree with the de-duplicated problem."""
+    d = synth.gaussian(9, 30, 40)
+    X, y = d["X"].copy(), d["y"]
+    X[:, 5] = 0.0
+    Xd = np.concatenate([X, X[:, :3]], axis=1)
+    lam = 0.2 * np.abs(X.T @ y).max()
+    r = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-14)
+    assert r["beta"][0][5] == 0.0
+    rd = orc.lasso_path(Xd, y, lambdas=[lam], eps_rel=1e-14)
+    np.testing.assert_allclose(X @ r["beta"][0], Xd @ rd["beta"][0], atol=1e-6)
+    s = orc.screen(X, y, r["beta"][0], lam)
+    assert not s["keep_exact"][5]
+
+
+def test_epoch_budget_not_converged(orc):
+    """With a tiny epoch budget the path reports 'not converged' and a gap that
+    is the true gap of the returned beta (certified)."""
+    X, y = _small_c1_like(seed=8)
+    lam = 0.01 * np.abs(X.T @ y).max()
+    r = orc.lasso_path(X, y, lambdas=[lam], K=5)
+    assert r["status"][0] == 1 and r["rc"] == 1
+    assert r["epochs"][0] == 5
+    s = orc.screen(X, y, r["beta"][0], lam)
+    assert np.isclose(r["gap"][0], s["gap"], rtol=1e-9)
+    assert r["gap"][0] > 1e-8 * (y @ y)
+
+
+def test_invalid_arguments(orc):
+    d = synth.gaussian(1, 10, 12)
+    with pytest.raises(ValueError):
+        orc.lasso_path(d["X"], d["y"], lambdas=[1.0, 2.0])      # increasing grid
+    with pytest.raises(ValueError):
+        orc.lasso_path(d["X"], d["y"], lambdas=[-1.0])          # lambda <= 0
+    with pytest.raises(ValueError):
+        orc.lasso_path(d["X"], d["y"], lambdas=[1.0], f=0)      # f < 1

@@ -214,7 +214,7 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
     if (alpha_s < -1.0 / M_plus) alpha_s = -1.0 / M_plus;
     if (alpha_s > 1.0 / M_plus) alpha_s = 1.0 / M_plus;
   } else {
-    alpha_s = 0.0;
+    alpha_s = (R2 > 0.0) ? Ry / (lambda * R2) : 0.0; /* R8: no column bounds theta */
   }
 
   /* G = 1/2||rho||^2 + lambda||beta||_1 - (1/2||y||^2 - lambda^2/2

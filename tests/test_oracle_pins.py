@@ -348,3 +348,16 @@ def test_invalid_arguments(orc):
         orc.lasso_path(d["X"], d["y"], lambdas=[-1.0])          # lambda <= 0
     with pytest.raises(ValueError):
         orc.lasso_path(d["X"], d["y"], lambdas=[1.0], f=0)      # f < 1
+
+
+def test_all_zero_design(orc):
+    """With X = 0 every beta is optimal at 0 and theta_hat = y/lambda (the dual
+    set is all of R^n): the gap vanishes with no epoch and nothing is kept."""
+    X = np.zeros((12, 9))
+    y = np.random.default_rng(0).standard_normal(12)
+    r = orc.lasso_path(X, y, lambdas=[0.5, 0.1])
+    assert np.all(r["beta"] == 0) and np.all(r["status"] == 0)
+    assert np.all(r["epochs"] == 0)
+    s = orc.screen(X, y, np.zeros(9), 0.1)
+    assert not s["keep_safe"].any()
+    assert abs(s["gap"]) <= 1e-12 * (y @ y)

@@ -1,0 +1,185 @@
+/*
+ * gapsafe.h -- C ABI of the MI355X (gfx950) library for the Lasso solved by
+ * cyclic coordinate descent with dynamic GAP SAFE sphere screening
+ * (Fercoq, Gramfort, Salmon, "Mind the duality gap: safer rules for the
+ * Lasso", ICML 2015).
+ *
+ * Problem (Sec. 1.1, the Lasso):  min_beta 1/2 ||X beta - y||^2 + lambda ||beta||_1,
+ * X in R^{n x p} given column-wise, solved over a non-increasing grid of
+ * lambdas with warm starts (Algorithm 1; grid of Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers marked [device] are caller-owned device memory (for instance a
+ *   torch tensor's data_ptr()); [host] pointers are read during the call only.
+ * - X is column-major: entry (i, j) is X[i + j*ldx], ldx >= n.  X and y
+ *   share the problem's dtype (FP32 or FP64).  Coefficient vectors (beta_init,
+ *   beta_out, screen()'s beta) are always FP64, so that a returned beta is
+ *   exactly the iterate whose gap is reported.  All reductions, the residual,
+ *   the duality gap and the screening radius are FP64 on the device.
+ * - Vectorized 16-byte loads are used when X is 16-byte aligned and
+ *   ldx*sizeof(dtype) is a multiple of 16; otherwise scalar loads.  No entry
+ *   beyond row n-1 of a column is read.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  The
+ *   per-problem ("narrow") schedule is stream-ordered and asynchronous:
+ *   outputs are valid once the caller synchronizes the stream.  The wide
+ *   schedule (one problem spread over the whole GPU) drives its passes from
+ *   the host and returns when the path is finished.
+ * - The library never allocates device memory: every scratch array lives in
+ *   the caller's workspace (size from the *_workspace_size queries, any
+ *   256-byte-aligned device buffer).  Workspace contents need no
+ *   initialisation and are not meaningful after the call.
+ * - Host-side argument checks happen before any launch; on error nothing is
+ *   launched.  Return codes:
+ *     GS_OK             0   every lambda certified (gap <= eps)
+ *     GS_NOT_CONVERGED  1   soft: at least one lambda hit max_epochs; its
+ *                           outputs hold the last iterate and its gap.  Only
+ *                           reported by the synchronous wide schedule; the
+ *                           asynchronous schedule reports it in status_out.
+ *     GS_EINVAL        -1   bad size, pointer, lambda, eps, f or dtype
+ *     GS_EHIP          -2   HIP runtime error (text: lasso_strerror)
+ *     GS_EWORKSPACE    -3   workspace NULL or smaller than required
+ *     GS_EUNSUPPORTED  -4   n larger than this build handles (2048)
+ */
+#ifndef GAPSAFE_H
+#define GAPSAFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { GS_F32 = 0, GS_F64 = 1 } gs_dtype;
+
+enum {
+  GS_OK = 0,
+  GS_NOT_CONVERGED = 1,
+  GS_EINVAL = -1,
+  GS_EHIP = -2,
+  GS_EWORKSPACE = -3,
+  GS_EUNSUPPORTED = -4
+};
+
+/* Per-lambda status written to status_out[t]. */
+enum {
+  GS_STATUS_CONVERGED = 0,     /* gap <= eps_rel * ||y||^2                      */
+  GS_STATUS_NOT_CONVERGED = 1, /* max_epochs reached; gap_out holds the gap of
+                                  the returned beta                          */
+  GS_STATUS_NONFINITE = 2      /* X or y holds a NaN or Inf; outputs are zero  */
+};
+
+/* Schedules (gs_opts.schedule). */
+enum {
+  GS_SCHED_AUTO = 0,   /* narrow for small n*p, wide above the tuned threshold */
+  GS_SCHED_NARROW = 1, /* one wavefront runs the whole path of one problem     */
+  GS_SCHED_WIDE = 2    /* sweeps over all CUs, CD on one wavefront (one problem) */
+};
+
+/* One Lasso path (Algorithm 1 inputs X, y and the lambda grid). */
+typedef struct gs_problem {
+  int32_t n, p;            /* rows and columns of the design, n, p >= 1        */
+  int64_t ldx;             /* leading dimension of X (>= n, or >= the largest
+                              row index + 1 when `rows` is set)              */
+  int32_t dtype;           /* gs_dtype of X and y                              */
+  const void* X;           /* [device] design, column-major                    */
+  const void* y;           /* [device] response                                */
+  const int32_t* rows;     /* [device] optional: n row indices into X and y
+                              (a row subsample); NULL = rows 0..n-1          */
+  int32_t T;               /* number of lambdas, >= 1                          */
+  const double* lambdas;   /* [host] T non-increasing positive values, or NULL */
+  int32_t lambda_relative; /* != 0: lambdas[] are multiples of lambda_max      */
+  double lambda_min_ratio; /* lambdas == NULL: the grid lambda_t =
+                              lambda_max * ratio^(t/(T-1)), t = 0..T-1, so
+                              lambda_0 = lambda_max (Sec. 3.3; the paper's
+                              10^(-delta) is ratio).  0 < ratio <= 1.        */
+  const double* beta_init; /* [device] optional warm start for the first
+                              lambda (p values); NULL = 0, the solution at
+                              lambda_max (Algorithm 1 initialisation)        */
+  double* beta_out;        /* [device] p x T column-major: beta^{lambda_t}     */
+  double* gap_out;         /* [device] T: duality gap of the returned beta on
+                              the final safe active set (the dual norm is
+                              taken over A, Sec. 4.1); it bounds
+                              P(beta) - P(beta_hat)                          */
+  int32_t* epochs_out;     /* [device] T: CD epochs run at lambda_t           */
+  int32_t* nactive_out;    /* [device] T: size of the safe active set at exit */
+  int32_t* status_out;     /* [device] T: GS_STATUS_*                          */
+  double* lambda_out;      /* [device] optional T: the lambdas used           */
+} gs_problem;
+
+typedef struct gs_opts {
+  double eps_rel;        /* stop when gap <= eps_rel * ||y||^2 (default 1e-8;
+                            the paper's epsilon is absolute)                 */
+  int32_t screen_every;  /* f: screening pass every f CD epochs (default 10,
+                            Sec. 4.1)                                        */
+  int32_t max_epochs;    /* K: CD epochs per lambda (default 100000)         */
+  int32_t schedule;      /* GS_SCHED_*                                        */
+  int32_t* select_counts;/* [device] optional (batch only): T x p int32
+                            counters; count[t*p + j] += 1 for every problem
+                            whose beta^{lambda_t}_j != 0 (stability
+                            selection).  Requires equal p and T in the batch;
+                            the caller zeroes it.                            */
+  int64_t* timestamps;   /* [device] optional (batch only): 2*B values, start
+                            and end of each problem in device wall-clock
+                            ticks (see gs_wallclock_hz)                      */
+} gs_opts;
+
+/* Fill *o with the defaults above. */
+void gs_opts_default(gs_opts* o);
+
+/* Device wall-clock frequency used by gs_opts.timestamps, in Hz (0 on error). */
+double gs_wallclock_hz(void);
+
+/* Bytes of workspace that lasso_path / lasso_solve_batch need for these
+ * problems (0 when an argument is invalid). */
+size_t lasso_workspace_size(const gs_problem* probs, int32_t B,
+                            const gs_opts* opts);
+
+/* Algorithm 1 for one problem: precompute ||x_j||^2 and lambda_max =
+ * ||X^T y||_inf (Sec. 1.2), build the grid, then for each lambda_t warm-start
+ * from beta^{lambda_{t-1}}, screen every f epochs with the GAP SAFE sphere
+ * (Sec. 3.2: theta = alpha rho from the residual rescaling of Sec. 2.3,
+ * radius sqrt(2 gap)/lambda inflated by a rounding bound) and run cyclic CD
+ * on the surviving coordinates until the gap is <= eps. */
+int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace,
+               size_t ws_bytes, void* stream);
+
+/* B independent paths in one persistent launch: problems are ordered by
+ * estimated cost and handed to one wavefront each through a device work
+ * queue.  Asynchronous; per-problem results in each problem's outputs. */
+int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace that screen() needs. */
+size_t screen_workspace_size(int32_t n, int32_t p);
+
+/* One GAP SAFE screening pass at (beta, lambda) over the active set A:
+ * rho = y - X beta; c_j = x_j^T rho and M = max_{j in A} |c_j| (the dual norm
+ * over A, Sec. 4.1); theta = alpha rho with alpha = min(max(y^T rho /
+ * (lambda ||rho||^2), -1/M), 1/M) (Sec. 2.3); gap G = P(beta) - D(theta);
+ * radius r = sqrt(2 G)/lambda (Proposition 1); keep j iff
+ * |x_j^T theta| + r ||x_j|| >= 1 (Sec. 2.1 sphere test) with the rounding
+ * inflation.  Asynchronous.
+ *   dtype/X/y/ldx as in gs_problem (no row subsample); beta [device] p FP64
+ *   values; active_in [device] q_in ascending column indices or NULL (all p);
+ *   active_out [device] capacity q_in (p when active_in is NULL), receives the
+ *   kept indices in ascending order; q_out [device] 1 int32; gap_out,
+ *   alpha_out, radius_out [device] 1 double each (radius_out is the inflated
+ *   radius actually used by the test); c_out [device] optional q_in doubles:
+ *   c_j for the j of active_in, in its order. */
+int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
+           const void* y, const double* beta, double lambda,
+           const int32_t* active_in, int32_t q_in, int32_t* active_out,
+           int32_t* q_out, double* gap_out, double* alpha_out,
+           double* radius_out, double* c_out, void* workspace,
+           size_t ws_bytes, void* stream);
+
+/* Human-readable text for a return code (for GS_EHIP, the last HIP error). */
+const char* lasso_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAPSAFE_H */

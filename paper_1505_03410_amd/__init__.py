@@ -1,0 +1,319 @@
+"""Python binding of libgapsafe.so, the gfx950 library for the Lasso solved by
+cyclic coordinate descent with dynamic GAP SAFE sphere screening
+(Fercoq, Gramfort & Salmon, ICML 2015).
+
+The functions here have the names of the C ABI (include/gapsafe.h) and only
+marshal arguments: torch tensors supply device memory and the current stream,
+every step of the method runs in the library's HIP kernels.  There is no CPU
+fallback: importing works without a GPU, calling needs the built library and
+a device.
+
+Design matrices are column-major: pass an (n, p) tensor whose strides are
+(1, ldx), e.g. ``colmajor_to_device(X)`` or ``Xcm.T[:n]`` for a (p, ldx)
+row-major buffer ``Xcm``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgapsafe.so")
+
+GS_F32, GS_F64 = 0, 1
+GS_OK, GS_NOT_CONVERGED = 0, 1
+GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED = -1, -2, -3, -4
+SCHEDULES = {"auto": 0, "narrow": 1, "wide": 2}
+
+
+class GsError(RuntimeError):
+    def __init__(self, code, text):
+        super().__init__(f"gapsafe error {code}: {text}")
+        self.code = code
+
+
+class gs_problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("p", ctypes.c_int32), ("ldx", ctypes.c_int64),
+        ("dtype", ctypes.c_int32), ("X", ctypes.c_void_p), ("y", ctypes.c_void_p),
+        ("rows", ctypes.c_void_p), ("T", ctypes.c_int32),
+        ("lambdas", ctypes.POINTER(ctypes.c_double)),
+        ("lambda_relative", ctypes.c_int32), ("lambda_min_ratio", ctypes.c_double),
+        ("beta_init", ctypes.c_void_p), ("beta_out", ctypes.c_void_p),
+        ("gap_out", ctypes.c_void_p), ("epochs_out", ctypes.c_void_p),
+        ("nactive_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
+        ("lambda_out", ctypes.c_void_p),
+    ]
+
+
+class gs_opts(ctypes.Structure):
+    _fields_ = [
+        ("eps_rel", ctypes.c_double), ("screen_every", ctypes.c_int32),
+        ("max_epochs", ctypes.c_int32), ("schedule", ctypes.c_int32),
+        ("select_counts", ctypes.c_void_p), ("timestamps", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
+           "lasso_solve_batch", "screen_workspace_size", "screen", "lasso_strerror"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgapsafe.so and declare its C ABI.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    P, vp = ctypes.POINTER, ctypes.c_void_p
+    lib.gs_opts_default.argtypes = [P(gs_opts)]
+    lib.gs_opts_default.restype = None
+    lib.gs_wallclock_hz.argtypes = []
+    lib.gs_wallclock_hz.restype = ctypes.c_double
+    lib.lasso_workspace_size.argtypes = [P(gs_problem), ctypes.c_int32, P(gs_opts)]
+    lib.lasso_workspace_size.restype = ctypes.c_size_t
+    lib.lasso_path.argtypes = [P(gs_problem), P(gs_opts), vp, ctypes.c_size_t, vp]
+    lib.lasso_path.restype = ctypes.c_int
+    lib.lasso_solve_batch.argtypes = [P(gs_problem), ctypes.c_int32, P(gs_opts), vp,
+                                      ctypes.c_size_t, vp]
+    lib.lasso_solve_batch.restype = ctypes.c_int
+    lib.screen_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.screen_workspace_size.restype = ctypes.c_size_t
+    lib.screen.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                           vp, vp, vp, ctypes.c_double, vp, ctypes.c_int32, vp, vp, vp, vp,
+                           vp, vp, vp, ctypes.c_size_t, vp]
+    lib.screen.restype = ctypes.c_int
+    lib.lasso_strerror.argtypes = [ctypes.c_int]
+    lib.lasso_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().lasso_strerror(code).decode()
+
+
+def _check(code: int, allow_not_converged: bool = True):
+    if code == GS_OK or (allow_not_converged and code == GS_NOT_CONVERGED):
+        return code
+    raise GsError(code, strerror(code))
+
+
+# ------------------------------------------------------------------ helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return GS_F32
+    if t.dtype == torch.float64:
+        return GS_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def colmajor_to_device(X, ld_multiple: int = 4, dtype=None, device="cuda"):
+    """numpy (n, p) -> device (n, p) tensor with strides (1, ldx), ldx padded
+    to a multiple of ``ld_multiple`` (padding rows are zero)."""
+    torch = _torch()
+    X = np.asarray(X)
+    n, p = X.shape
+    ld = ((n + ld_multiple - 1) // ld_multiple) * ld_multiple
+    buf = np.zeros((p, ld), dtype=dtype or X.dtype)
+    buf[:, :n] = X.T
+    t = torch.from_numpy(buf).to(device)
+    return t.T[:n]
+
+
+def _design(X):
+    if X.dim() != 2 or X.stride(0) != 1 or X.stride(1) < X.shape[0]:
+        raise ValueError("X must be an (n, p) column-major tensor: strides (1, ldx), ldx >= n")
+    if not X.is_cuda:
+        raise ValueError("X must be a device tensor")
+    return X.shape[0], X.shape[1], X.stride(1)
+
+
+class PathResult(dict):
+    """beta (T, p), gap (T,), epochs (T,), nactive (T,), status (T,), lambdas (T,)."""
+
+    __getattr__ = dict.__getitem__
+
+
+def _alloc_outputs(n, p, T, dt, device):
+    torch = _torch()
+    return PathResult(
+        beta=torch.empty((T, p), dtype=torch.float64, device=device),
+        gap=torch.empty(T, dtype=torch.float64, device=device),
+        epochs=torch.empty(T, dtype=torch.int32, device=device),
+        nactive=torch.empty(T, dtype=torch.int32, device=device),
+        status=torch.empty(T, dtype=torch.int32, device=device),
+        lambdas=torch.empty(T, dtype=torch.float64, device=device),
+    )
+
+
+def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, out, n=None):
+    torch = _torch()
+    ld = X.stride(1)
+    if rows is not None:
+        if rows.dtype != torch.int32 or not rows.is_cuda or not rows.is_contiguous():
+            raise ValueError("rows must be a contiguous int32 device tensor")
+        n = rows.numel()
+        p = X.shape[1]
+    else:
+        n, p, ld = _design(X)
+    if y.dtype != X.dtype or not y.is_cuda or not y.is_contiguous():
+        raise ValueError("y must be a contiguous device tensor of X's dtype")
+    host_lam = None
+    if lambdas is not None:
+        host_lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+        T = len(host_lam)
+    if beta_init is not None and (beta_init.dtype != torch.float64 or not beta_init.is_contiguous()
+                                  or beta_init.numel() != p):
+        raise ValueError("beta_init must be p contiguous float64 values")
+    if out is None:
+        out = _alloc_outputs(n, p, T, X.dtype, X.device)
+    pr = gs_problem()
+    pr.n, pr.p, pr.ldx, pr.dtype = n, p, ld, _dtype_code(X)
+    pr.X, pr.y = X.data_ptr(), y.data_ptr()
+    pr.rows = None if rows is None else rows.data_ptr()
+    pr.T = T
+    pr.lambdas = None if host_lam is None else host_lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    pr.lambda_relative = 1 if relative else 0
+    pr.lambda_min_ratio = float(lambda_min_ratio)
+    pr.beta_init = None if beta_init is None else beta_init.data_ptr()
+    pr.beta_out = out["beta"].data_ptr()
+    pr.gap_out = out["gap"].data_ptr()
+    pr.epochs_out = out["epochs"].data_ptr()
+    pr.nactive_out = out["nactive"].data_ptr()
+    pr.status_out = out["status"].data_ptr()
+    pr.lambda_out = out["lambdas"].data_ptr()
+    return pr, out, host_lam
+
+
+def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, timestamps=None):
+    o = gs_opts()
+    load_library().gs_opts_default(ctypes.byref(o))
+    o.eps_rel = float(eps_rel)
+    o.screen_every = int(screen_every)
+    o.max_epochs = int(max_epochs)
+    o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    o.select_counts = None if select_counts is None else select_counts.data_ptr()
+    o.timestamps = None if timestamps is None else timestamps.data_ptr()
+    return o
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    if nbytes == 0:
+        raise GsError(GS_EINVAL, "invalid arguments (workspace size query returned 0)")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------- API
+
+def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
+               relative: bool = False, lambda_min_ratio: float = 1e-3, beta_init=None,
+               rows=None, eps_rel: float = 1e-8, screen_every: int = 10,
+               max_epochs: int = 100000, schedule="auto", stream=None, out=None,
+               workspace=None):
+    """Algorithm 1 on the device for one problem; see include/gapsafe.h.
+    Returns a PathResult of device tensors (valid after the stream syncs) with
+    an extra ``rc`` entry (GS_OK or GS_NOT_CONVERGED)."""
+    lib = load_library()
+    pr, out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
+                              lambda_min_ratio=lambda_min_ratio, beta_init=beta_init,
+                              rows=rows, out=out)
+    o = _opts(eps_rel, screen_every, max_epochs, schedule)
+    need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+    rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc)
+    out["rc"] = rc
+    out["workspace"] = ws
+    return out
+
+
+def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10,
+                      max_epochs: int = 100000, select_counts=None, timestamps=None,
+                      stream=None, workspace=None):
+    """Many paths in one persistent launch.  ``problems`` is a list of dicts
+    with keys X, y and optionally T, lambdas, relative, lambda_min_ratio,
+    beta_init, rows.  Returns the list of PathResults."""
+    lib = load_library()
+    B = len(problems)
+    arr = (gs_problem * B)()
+    outs, keep = [], []
+    for b, pb in enumerate(problems):
+        pr, out, hl = _problem(pb["X"], pb["y"], T=pb.get("T", 100), lambdas=pb.get("lambdas"),
+                               relative=pb.get("relative", False),
+                               lambda_min_ratio=pb.get("lambda_min_ratio", 1e-3),
+                               beta_init=pb.get("beta_init"), rows=pb.get("rows"),
+                               out=pb.get("out"))
+        arr[b] = pr
+        outs.append(out)
+        keep.append(hl)
+    o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps)
+    need = lib.lasso_workspace_size(arr, B, ctypes.byref(o))
+    dev = problems[0]["X"].device
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    rc = lib.lasso_solve_batch(arr, B, ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc)
+    for out in outs:
+        out["workspace"] = ws
+    return outs
+
+
+def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=None,
+           workspace=None):
+    """One GAP SAFE screening pass at (beta, lam).  Returns device tensors:
+    active (kept indices, ascending), q (1,), gap, alpha, radius (1,) and c."""
+    torch = _torch()
+    lib = load_library()
+    n, p, ld = _design(X)
+    dev = X.device
+    if beta.dtype != torch.float64 or beta.numel() != p or not beta.is_contiguous():
+        raise ValueError("beta must be p contiguous float64 values")
+    if active is not None:
+        if active.dtype != torch.int32 or not active.is_contiguous():
+            raise ValueError("active must be a contiguous int32 tensor")
+        q = active.numel()
+    else:
+        q = p
+    act_out = torch.empty(max(q, 1), dtype=torch.int32, device=dev)
+    q_out = torch.empty(1, dtype=torch.int32, device=dev)
+    gap = torch.empty(1, dtype=torch.float64, device=dev)
+    alpha = torch.empty(1, dtype=torch.float64, device=dev)
+    radius = torch.empty(1, dtype=torch.float64, device=dev)
+    c = torch.empty(max(q, 1), dtype=torch.float64, device=dev) if want_c else None
+    need = lib.screen_workspace_size(n, p)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    rc = lib.screen(n, p, ld, _dtype_code(X), _ptr(X), _ptr(y), _ptr(beta), float(lam),
+                    _ptr(active), q, _ptr(act_out), _ptr(q_out), _ptr(gap), _ptr(alpha),
+                    _ptr(radius), _ptr(c), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc, allow_not_converged=False)
+    return dict(active=act_out, q=q_out, gap=gap, alpha=alpha, radius=radius,
+                c=c if c is None else c[:q], workspace=ws)
+
+
+def wallclock_hz() -> float:
+    return load_library().gs_wallclock_hz()

@@ -1,0 +1,548 @@
+// C ABI: argument checks, workspace layout, kernel selection and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gapsafe.h"
+#include "gs_registry.hpp"
+#include "gs_wide.hpp"
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail_hip(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return GS_EHIP;
+}
+
+#define HIPCHK(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return fail_hip(e_, #call);  \
+  } while (0)
+
+constexpr int kMaxN = 2048;
+constexpr int kWideSweepBlocks = 2048;
+constexpr int kWidePreBlocks = 1024;
+// n*p above which GS_SCHED_AUTO spreads one path over the whole GPU.
+constexpr double kWideThreshold = 16.0 * 1024 * 1024;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves aligned sub-arrays from a workspace (or only measures when base is
+// null).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * std::max<size_t>(count, 1);
+    return p;
+  }
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_problem(const gs_problem* pr) {
+  if (!pr) return GS_EINVAL;
+  if (pr->n < 1 || pr->p < 1 || pr->T < 1) return GS_EINVAL;
+  if (pr->dtype != GS_F32 && pr->dtype != GS_F64) return GS_EINVAL;
+  if (!pr->rows && pr->ldx < pr->n) return GS_EINVAL;
+  if (pr->ldx < 1) return GS_EINVAL;
+  if (!pr->X || !pr->y || !pr->beta_out || !pr->gap_out || !pr->epochs_out ||
+      !pr->nactive_out || !pr->status_out)
+    return GS_EINVAL;
+  if (pr->lambdas) {
+    for (int t = 0; t < pr->T; ++t) {
+      if (!finite_pos(pr->lambdas[t])) return GS_EINVAL;
+      if (t > 0 && pr->lambdas[t] > pr->lambdas[t - 1]) return GS_EINVAL;
+    }
+  } else {
+    if (!finite_pos(pr->lambda_min_ratio) || pr->lambda_min_ratio > 1.0) return GS_EINVAL;
+  }
+  if (pr->n > kMaxN) return GS_EUNSUPPORTED;
+  return GS_OK;
+}
+
+int check_opts(const gs_opts* o) {
+  if (!finite_pos(o->eps_rel)) return GS_EINVAL;
+  if (o->screen_every < 1 || o->max_epochs < 0) return GS_EINVAL;
+  if (o->schedule < GS_SCHED_AUTO || o->schedule > GS_SCHED_WIDE) return GS_EINVAL;
+  return GS_OK;
+}
+
+bool vec_ok(const gs_problem* pr) {
+  const size_t es = pr->dtype == GS_F64 ? 8 : 4;
+  return (reinterpret_cast<uintptr_t>(pr->X) % 16 == 0) && ((size_t)pr->ldx * es) % 16 == 0;
+}
+
+const NarrowEntry* narrow_table(int dtype, bool gather, bool vec, int* count) {
+  if (dtype == GS_F32) {
+    if (gather) { *count = kNarrowF32GN; return kNarrowF32G; }
+    if (vec) { *count = kNarrowF32VN; return kNarrowF32V; }
+    *count = kNarrowF32SN;
+    return kNarrowF32S;
+  }
+  if (gather) { *count = kNarrowF64GN; return kNarrowF64G; }
+  if (vec) { *count = kNarrowF64VN; return kNarrowF64V; }
+  *count = kNarrowF64SN;
+  return kNarrowF64S;
+}
+
+// Smallest compiled narrow configuration that holds n rows.
+const NarrowEntry* pick_narrow(const gs_problem* pr) {
+  int cnt = 0;
+  const NarrowEntry* tab = narrow_table(pr->dtype, pr->rows != nullptr, vec_ok(pr), &cnt);
+  for (int i = 0; i < cnt; ++i)
+    if (tab[i].cfg.nmax() >= pr->n) return &tab[i];
+  return nullptr;
+}
+
+const WideEntry* pick_wide(const gs_problem* pr) {
+  const bool v = vec_ok(pr);
+  const int want_vec = v ? (pr->dtype == GS_F64 ? 2 : 4) : 1;
+  for (int i = 0; i < kWideN; ++i) {
+    const WideEntry& w = kWide[i];
+    if (w.dtype == pr->dtype && w.vec == want_vec && w.nmax() >= pr->n) return &w;
+  }
+  return nullptr;
+}
+
+bool use_wide(const gs_problem* pr, const gs_opts* o) {
+  if (pr->rows) return false;  // the wide kernels read contiguous rows only
+  if (o->schedule == GS_SCHED_WIDE) return true;
+  if (o->schedule == GS_SCHED_NARROW) return false;
+  return (double)pr->n * (double)pr->p > kWideThreshold;
+}
+
+// Per-problem workspace arrays.
+void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
+  d->nrm2 = cv.take<double>(pr->p);
+  d->beta = cv.take<double>(pr->p);
+  d->c = cv.take<double>(pr->p);
+  d->act = cv.take<int32_t>(2 * (size_t)pr->p);
+  d->lam = cv.take<double>(pr->T);
+  d->rho = cv.take<double>(pr->n);
+}
+
+struct Shared {
+  ProbDesc* descs;
+  int32_t* queues;   // 64 counters
+  WideState* st;
+  WideBufs wb;
+};
+
+void carve_shared(Carver& cv, int B, int pmax, Shared* s) {
+  s->descs = cv.take<ProbDesc>(B);
+  s->queues = cv.take<int32_t>(64);
+  s->st = cv.take<WideState>(1);
+  s->wb.part = cv.take<double>(4 * (size_t)std::max(kWideSweepBlocks, kWidePreBlocks));
+  s->wb.cnt = cv.take<int32_t>((pmax + kTestTile - 1) / kTestTile + 1);
+  s->wb.nzidx = cv.take<int32_t>(pmax);
+  s->wb.nzval = cv.take<double>(pmax);
+}
+
+void fill_desc(const gs_problem* pr, int orig, ProbDesc* d) {
+  d->X = pr->X;
+  d->y = pr->y;
+  d->rows = pr->rows;
+  d->ldx = pr->ldx;
+  d->n = pr->n;
+  d->p = pr->p;
+  d->T = pr->T;
+  d->dtype = pr->dtype;
+  d->lambda_relative = pr->lambda_relative ? 1 : 0;
+  d->has_lambdas = pr->lambdas ? 1 : 0;
+  d->lambda_min_ratio = pr->lambda_min_ratio;
+  d->beta_init = pr->beta_init;
+  d->beta_out = pr->beta_out;
+  d->gap_out = pr->gap_out;
+  d->epochs_out = pr->epochs_out;
+  d->nactive_out = pr->nactive_out;
+  d->status_out = pr->status_out;
+  d->lambda_out = pr->lambda_out;
+  d->orig = orig;
+  d->pad_ = 0;
+}
+
+PathOpts path_opts(const gs_opts* o, bool batch) {
+  PathOpts po;
+  po.eps_rel = o->eps_rel;
+  po.f = o->screen_every;
+  po.K = o->max_epochs;
+  po.select_counts = batch ? o->select_counts : nullptr;
+  po.timestamps = batch ? reinterpret_cast<long long*>(o->timestamps) : nullptr;
+  return po;
+}
+
+hipError_t launch(const void* k, dim3 g, dim3 b, void** args, size_t smem, hipStream_t s) {
+  return hipLaunchKernel(k, g, b, args, smem, s);
+}
+
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
+  int64_t cnt = count;
+  void* args[] = {&p, &v, &cnt};
+  unsigned g = (unsigned)std::min<int64_t>((count + 255) / 256, 1024);
+  return launch(kFillI32, dim3(std::max(g, 1u)), dim3(256), args, 0, s);
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  return cus;
+}
+
+// Number of concurrently resident wavefronts of a narrow kernel.
+int narrow_slots(const NarrowEntry* e) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->path_kernel, 64, e->lds_bytes) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * device_cus();
+}
+
+// Upload the lambdas of each problem into its workspace copy.
+int upload_lambdas(const gs_problem* pr, const ProbDesc* d, hipStream_t s) {
+  if (pr->lambdas)
+    HIPCHK(hipMemcpyAsync(d->lam, pr->lambdas, sizeof(double) * pr->T, hipMemcpyHostToDevice, s));
+  return GS_OK;
+}
+
+// ---------------------------------------------------------------- wide path
+int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc d,
+             hipStream_t s) {
+  const WideEntry* w = pick_wide(pr);
+  const NarrowEntry* ne = pick_narrow(pr);
+  if (!w || !ne) return GS_EUNSUPPORTED;
+  PathOpts po = path_opts(o, false);
+  WideState* st = sh.st;
+  WideBufs wb = sh.wb;
+  const int dt = pr->dtype;
+  // precompute + init
+  {
+    void* a[] = {&d, &wb};
+    HIPCHK(launch(w->pre_kernel, dim3(kWidePreBlocks), dim3(64 * kSweepWaves), a, 0, s));
+    int npre = kWidePreBlocks;
+    void* b[] = {&d, &st, &wb, &npre, &po};
+    HIPCHK(launch(kWideInit[dt], dim3(1), dim3(256), b, 0, s));
+  }
+  const int ntest = (pr->p + kTestTile - 1) / kTestTile;
+  int nsweep = kWideSweepBlocks;
+  int zero = 0, one = 1;
+  int32_t* nullq = nullptr;
+  int32_t* nullo = nullptr;
+  double* nd = nullptr;
+  const long long max_passes =
+      (long long)pr->T * ((long long)o->max_epochs / o->screen_every + 3) + 16;
+  long long enq = 0;
+  int chunk = 8;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      void* ar[] = {&d, &st, &wb, &zero};
+      HIPCHK(launch(kWideRefresh[dt], dim3(1), dim3(kRefreshThreads), ar, 0, s));
+      void* as[] = {&d, &st, &wb, &zero};
+      HIPCHK(launch(w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), as, 0, s));
+      void* ag[] = {&d, &st, &wb, &nsweep, &zero, &nd, &nd, &nd, &po};
+      HIPCHK(launch(kWideGap[dt], dim3(1), dim3(256), ag, 0, s));
+      void* at[] = {&d, &st, &wb};
+      HIPCHK(launch(kWideTest, dim3(ntest), dim3(256), at, 0, s));
+      void* ac[] = {&d, &st, &wb, &nullo};
+      HIPCHK(launch(kWideCompact, dim3(ntest), dim3(256), ac, 0, s));
+      int nt = ntest;
+      void* af[] = {&d, &st, &wb, &nt, &nullq};
+      HIPCHK(launch(kWideFin, dim3(1), dim3(64), af, 0, s));
+      void* ar2[] = {&d, &st, &wb, &one};
+      HIPCHK(launch(kWideRefresh[dt], dim3(1), dim3(kRefreshThreads), ar2, 0, s));
+      void* acd[] = {&d, &st, &po};
+      HIPCHK(launch(ne->cd_kernel, dim3(1), dim3(64), acd, ne->lds_bytes, s));
+    }
+    enq += chunk;
+    WideState hs;
+    HIPCHK(hipMemcpyAsync(&hs, st, sizeof(WideState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hs.done) return hs.status_acc ? GS_NOT_CONVERGED : GS_OK;
+    if (enq > max_passes) {
+      g_err = "wide schedule: pass budget exceeded";
+      return GS_EHIP;
+    }
+    chunk = std::min(chunk * 2, 256);
+  }
+}
+
+size_t path_ws(const gs_problem* probs, int B) {
+  Carver cv{nullptr};
+  int pmax = 1;
+  for (int b = 0; b < B; ++b) pmax = std::max(pmax, probs[b].p);
+  Shared sh;
+  carve_shared(cv, B, pmax, &sh);
+  for (int b = 0; b < B; ++b) {
+    ProbDesc d;
+    carve_problem(cv, &probs[b], &d);
+  }
+  return align_up(cv.off, 256);
+}
+
+// Narrow launches of a (sorted) descriptor range grouped by configuration.
+struct Group {
+  const NarrowEntry* e;
+  int first, count;
+};
+
+int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, size_t ws_bytes,
+                  hipStream_t s, Shared* sh, std::vector<Group>* groups) {
+  if (!probs || B < 1 || !o) return GS_EINVAL;
+  int rc = check_opts(o);
+  if (rc) return rc;
+  for (int b = 0; b < B; ++b) {
+    rc = check_problem(&probs[b]);
+    if (rc) return rc;
+    if (o->select_counts && (probs[b].p != probs[0].p || probs[b].T != probs[0].T))
+      return GS_EINVAL;
+  }
+  if (!ws) return GS_EWORKSPACE;
+  const size_t need = path_ws(probs, B);
+  if (ws_bytes < need) return GS_EWORKSPACE;
+  Carver cv{static_cast<char*>(ws)};
+  int pmax = 1;
+  for (int b = 0; b < B; ++b) pmax = std::max(pmax, probs[b].p);
+  carve_shared(cv, B, pmax, sh);
+  std::vector<ProbDesc> descs(B);
+  std::vector<const NarrowEntry*> cfg(B);
+  for (int b = 0; b < B; ++b) {
+    fill_desc(&probs[b], b, &descs[b]);
+    carve_problem(cv, &probs[b], &descs[b]);
+    cfg[b] = pick_narrow(&probs[b]);
+    if (!cfg[b]) return GS_EUNSUPPORTED;
+    rc = upload_lambdas(&probs[b], &descs[b], s);
+    if (rc) return rc;
+  }
+  // Group by configuration; inside a group, most expensive first.
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  auto cost = [&](int b) { return (double)probs[b].n * probs[b].p * probs[b].T; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (cfg[a] != cfg[b]) return cfg[a] < cfg[b];
+    return cost(a) > cost(b);
+  });
+  std::vector<ProbDesc> sorted(B);
+  groups->clear();
+  for (int i = 0; i < B; ++i) {
+    sorted[i] = descs[order[i]];
+    const NarrowEntry* e = cfg[order[i]];
+    if (groups->empty() || groups->back().e != e) groups->push_back({e, i, 0});
+    groups->back().count++;
+  }
+  if ((int)groups->size() > 63) return GS_EUNSUPPORTED;
+  HIPCHK(hipMemcpyAsync(sh->descs, sorted.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice, s));
+  return GS_OK;
+}
+
+int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po,
+                  hipStream_t s) {
+  HIPCHK(fill_i32(sh.queues, 0, 64, s));
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const Group& G = groups[g];
+    const ProbDesc* d = sh.descs + G.first;
+    int B = G.count;
+    int* q = sh.queues + g;
+    void* a[] = {&d, &B, &q, &po};
+    const int grid = std::max(1, std::min(G.count, narrow_slots(G.e)));
+    HIPCHK(launch(G.e->path_kernel, dim3(grid), dim3(64), a, G.e->lds_bytes, s));
+  }
+  return GS_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+void gs_opts_default(gs_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps_rel = 1e-8;
+  o->screen_every = 10;
+  o->max_epochs = 100000;
+  o->schedule = GS_SCHED_AUTO;
+}
+
+double gs_wallclock_hz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0.0;
+  return 1000.0 * khz;
+}
+
+size_t lasso_workspace_size(const gs_problem* probs, int32_t B, const gs_opts* opts) {
+  if (!probs || B < 1) return 0;
+  gs_opts def;
+  gs_opts_default(&def);
+  if (!opts) opts = &def;
+  if (check_opts(opts)) return 0;
+  for (int b = 0; b < B; ++b)
+    if (check_problem(&probs[b])) return 0;
+  return path_ws(probs, B);
+}
+
+int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace, size_t ws_bytes,
+               void* stream) {
+  gs_opts def;
+  gs_opts_default(&def);
+  if (!opts) opts = &def;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  rc = check_problem(prob);
+  if (rc) return rc;
+  if (!workspace) return GS_EWORKSPACE;
+  if (ws_bytes < path_ws(prob, 1)) return GS_EWORKSPACE;
+  if (use_wide(prob, opts)) {
+    Carver cv{static_cast<char*>(workspace)};
+    Shared sh;
+    carve_shared(cv, 1, prob->p, &sh);
+    ProbDesc d;
+    fill_desc(prob, 0, &d);
+    carve_problem(cv, prob, &d);
+    rc = upload_lambdas(prob, &d, s);
+    if (rc) return rc;
+    return run_wide(prob, opts, sh, d, s);
+  }
+  Shared sh;
+  std::vector<Group> groups;
+  rc = prepare_batch(prob, 1, opts, workspace, ws_bytes, s, &sh, &groups);
+  if (rc) return rc;
+  return launch_groups(sh, groups, path_opts(opts, false), s);
+}
+
+int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  gs_opts def;
+  gs_opts_default(&def);
+  if (!opts) opts = &def;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Shared sh;
+  std::vector<Group> groups;
+  int rc = prepare_batch(probs, B, opts, workspace, ws_bytes, s, &sh, &groups);
+  if (rc) return rc;
+  return launch_groups(sh, groups, path_opts(opts, true), s);
+}
+
+size_t screen_workspace_size(int32_t n, int32_t p) {
+  if (n < 1 || p < 1) return 0;
+  Carver cv{nullptr};
+  Shared sh;
+  carve_shared(cv, 1, p, &sh);
+  gs_problem pr{};
+  pr.n = n;
+  pr.p = p;
+  pr.T = 1;
+  ProbDesc d;
+  carve_problem(cv, &pr, &d);
+  return align_up(cv.off, 256);
+}
+
+int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, const void* y,
+           const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
+           int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
+           double* radius_out, double* c_out, void* workspace, size_t ws_bytes, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n < 1 || p < 1 || ldx < n) return GS_EINVAL;
+  if (dtype != GS_F32 && dtype != GS_F64) return GS_EINVAL;
+  if (!X || !y || !beta || !active_out || !q_out || !gap_out || !alpha_out || !radius_out)
+    return GS_EINVAL;
+  if (!finite_pos(lambda)) return GS_EINVAL;
+  if (active_in && (q_in < 0 || q_in > p)) return GS_EINVAL;
+  if (n > kMaxN) return GS_EUNSUPPORTED;
+  if (!workspace) return GS_EWORKSPACE;
+  if (ws_bytes < screen_workspace_size(n, p)) return GS_EWORKSPACE;
+  const int q = active_in ? q_in : p;
+  gs_problem pr{};
+  pr.n = n;
+  pr.p = p;
+  pr.ldx = ldx;
+  pr.dtype = dtype;
+  pr.X = X;
+  pr.y = y;
+  pr.T = 1;
+  const WideEntry* w = pick_wide(&pr);
+  if (!w) return GS_EUNSUPPORTED;
+  Carver cv{static_cast<char*>(workspace)};
+  Shared sh;
+  carve_shared(cv, 1, p, &sh);
+  ProbDesc d{};
+  fill_desc(&pr, 0, &d);
+  carve_problem(cv, &pr, &d);
+  if (c_out) d.c = c_out;
+  WideState* st = sh.st;
+  WideBufs wb = sh.wb;
+  PathOpts po{};
+  po.eps_rel = 1.0;
+  po.f = 1;
+  po.K = 0;
+  {
+    int qi = q_in;
+    void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda};
+    HIPCHK(launch(kScreenPrep[dtype], dim3(1), dim3(256), a, 0, s));
+  }
+  int zero = 0, one = 1;
+  {
+    void* a[] = {&d, &st, &wb, &zero};
+    HIPCHK(launch(kWideRefresh[dtype], dim3(1), dim3(kRefreshThreads), a, 0, s));
+  }
+  int nsweep = std::max(1, std::min(kWideSweepBlocks, (q + kSweepWaves * kSweepU - 1) /
+                                                          (kSweepWaves * kSweepU)));
+  {
+    void* a[] = {&d, &st, &wb, &one};
+    HIPCHK(launch(w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0, s));
+  }
+  {
+    void* a[] = {&d, &st, &wb, &nsweep, &one, &gap_out, &alpha_out, &radius_out, &po};
+    HIPCHK(launch(kWideGap[dtype], dim3(1), dim3(256), a, 0, s));
+  }
+  int ntest = std::max(1, (q + kTestTile - 1) / kTestTile);
+  {
+    void* a[] = {&d, &st, &wb};
+    HIPCHK(launch(kWideTest, dim3(ntest), dim3(256), a, 0, s));
+  }
+  {
+    void* a[] = {&d, &st, &wb, &active_out};
+    HIPCHK(launch(kWideCompact, dim3(ntest), dim3(256), a, 0, s));
+  }
+  {
+    void* a[] = {&d, &st, &wb, &ntest, &q_out};
+    HIPCHK(launch(kWideFin, dim3(1), dim3(64), a, 0, s));
+  }
+  return GS_OK;
+}
+
+const char* lasso_strerror(int code) {
+  switch (code) {
+    case GS_OK: return "ok";
+    case GS_NOT_CONVERGED: return "not converged: max_epochs reached for some lambda";
+    case GS_EINVAL: return "invalid argument";
+    case GS_EHIP: return g_err.empty() ? "HIP runtime error" : g_err.c_str();
+    case GS_EWORKSPACE: return "workspace missing or too small";
+    case GS_EUNSUPPORTED: return "unsupported: n larger than 2048";
+    default: return "unknown error code";
+  }
+}
+
+}  // extern "C"

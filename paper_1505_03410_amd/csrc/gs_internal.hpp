@@ -1,0 +1,70 @@
+// Internal structures shared by the host dispatch code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+// Device-side descriptor of one Lasso path.  Built on the host, copied into
+// the workspace, read by the kernels.  Pointers are device pointers.
+struct ProbDesc {
+  const void* X;
+  const void* y;
+  const int32_t* rows;
+  int64_t ldx;
+  int32_t n, p, T, dtype;
+  int32_t lambda_relative;
+  int32_t has_lambdas;     // lam holds caller values (absolute or relative)
+  double lambda_min_ratio;
+  const double* beta_init;
+  double* beta_out;
+  double* gap_out;
+  int32_t* epochs_out;
+  int32_t* nactive_out;
+  int32_t* status_out;
+  double* lambda_out;
+  // workspace arrays of this problem
+  double* nrm2;   // p: ||x_j||^2
+  double* beta;   // p: working coefficients (FP64)
+  double* c;      // p: x_j^T rho of the last sweep, indexed by position in A
+  int32_t* act;   // 2p: active set (two buffers for the wide schedule)
+  double* lam;    // T: lambdas (caller values on entry, absolute after init)
+  double* rho;    // n: residual (wide schedule)
+  int32_t orig;   // index of the problem in the caller's array
+  int32_t pad_;
+};
+
+struct PathOpts {
+  double eps_rel;
+  int32_t f, K;
+  int32_t* select_counts;  // T x p or null
+  long long* timestamps;   // 2B or null
+};
+
+// Scalars of the wide schedule's state machine (one problem).
+struct WideState {
+  // set by init
+  double lambda_max, ynorm2, eps;
+  // current lambda
+  int32_t t, k, q, full, cur;  // cur: which act buffer holds A
+  int32_t done, phase;         // phase: 1 = a test is pending after the gap
+  int32_t need_refresh, passes, status_acc, nonfinite;
+  // last pass
+  double gap, alpha_s, radius_s, e_c, M;
+  double R2, Ry, l1, sbx, xmax;
+  int32_t nnz, nblk_sweep, q_new, pad_;
+};
+
+// Kernel configuration: rows per lane layout.  S lanes share one column
+// (a "segment" of the column each), C = 64/S columns are processed at once.
+struct Cfg {
+  int id;
+  int dtype;   // 0 f32, 1 f64
+  int vec;     // elements per 16-byte load (4 f32, 2 f64) or 1 (scalar)
+  int S, NG;   // lanes per column, row groups per lane
+  int gather;  // 1: rows come from an index list
+  int nmax() const { return S * NG * vec; }
+};
+
+}  // namespace gs

@@ -1,0 +1,176 @@
+// Non-template kernels of the wide schedule and of screen(), plus the table
+// of wide sweep instantiations.
+#include "gs_registry.hpp"
+#include "gs_wide.hpp"
+
+namespace gs {
+
+__device__ __forceinline__ GapInfo state_gap(const WideState* st) {
+  GapInfo g;
+  g.alpha = st->alpha_s;
+  g.gap = st->gap;
+  g.radius = st->radius_s;
+  g.e_c = st->e_c;
+  return g;
+}
+
+// Sphere test over one tile of A: kept count per block; screened nonzero
+// coefficients are set to zero and flagged for a residual refresh.
+__global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, WideBufs wb) {
+  __shared__ double sh[256];
+  if (st->done || st->phase != 1) return;
+  const int q = st->q;
+  const bool full = st->full != 0;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const GapInfo g = state_gap(st);
+  const int tile0 = blockIdx.x * kTestTile;
+  int cnt = 0;
+  bool dn = false;
+  for (int e = threadIdx.x; e < kTestTile; e += 256) {
+    const int k = tile0 + e;
+    if (k >= q) break;
+    const int j = full ? k : act[k];
+    if (sphere_keep(g, d.c[k], d.nrm2[j], d.n)) {
+      ++cnt;
+    } else if (d.beta[j] != 0.0) {
+      d.beta[j] = 0.0;
+      dn = true;
+    }
+  }
+  if (dn) st->need_refresh = 1;
+  const double tot = block_sum<256>((double)cnt, sh);
+  if (threadIdx.x == 0) wb.cnt[blockIdx.x] = (int)tot;
+}
+
+// Ordered compaction: block b writes its kept indices after those of blocks
+// 0..b-1.  Thread t owns 8 consecutive positions of the tile.
+__global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st, WideBufs wb,
+                                                      int32_t* out) {
+  constexpr int PER = kTestTile / 256;
+  __shared__ int scan[256];
+  if (st->done || st->phase != 1) return;
+  const int q = st->q;
+  const bool full = st->full != 0;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  int32_t* dst = out ? out : d.act + (int64_t)(st->cur ^ 1) * d.p;
+  const GapInfo g = state_gap(st);
+  int off = 0;
+  for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];
+  const int k0 = blockIdx.x * kTestTile + threadIdx.x * PER;
+  int js[PER];
+  unsigned keep = 0;
+  int c = 0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int k = k0 + e;
+    js[e] = -1;
+    if (k < q) {
+      const int j = full ? k : act[k];
+      js[e] = j;
+      if (sphere_keep(g, d.c[k], d.nrm2[j], d.n)) {
+        keep |= 1u << e;
+        ++c;
+      }
+    }
+  }
+  scan[threadIdx.x] = c;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 256 counts.
+  for (int o = 1; o < 256; o <<= 1) {
+    int v = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = off + scan[threadIdx.x] - c;
+#pragma unroll
+  for (int e = 0; e < PER; ++e)
+    if (keep & (1u << e)) dst[pos++] = js[e];
+}
+
+__global__ __launch_bounds__(64) void k_wide_fin(ProbDesc d, WideState* st, WideBufs wb,
+                                                 int ntest, int32_t* q_out) {
+  if (st->done || st->phase != 1) return;
+  int s = 0;
+  for (int b = threadIdx.x; b < ntest; b += 64) s += wb.cnt[b];
+  s = wave_sum_i(s);
+  if (threadIdx.x == 0) {
+    if (q_out) {
+      *q_out = s;
+      st->phase = 0;
+    } else {
+      st->q = s;
+      st->cur ^= 1;
+      st->full = 0;
+      st->phase = 2;
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// screen(): beta to FP64, the active list, ||y||^2 and the state.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_screen_prep(ProbDesc d, WideState* st,
+                                                     const double* beta_in,
+                                                     const int32_t* active_in, int q_in,
+                                                     double lambda) {
+  __shared__ double sh[256];
+  for (int j = threadIdx.x; j < d.p; j += 256) d.beta[j] = beta_in[j];
+  if (active_in)
+    for (int k = threadIdx.x; k < q_in; k += 256) d.act[k] = active_in[k];
+  const XT* Y = (const XT*)d.y;
+  double yy = 0.0;
+  for (int i = threadIdx.x; i < d.n; i += 256) {
+    double v = (double)Y[i];
+    yy = fma(v, v, yy);
+  }
+  yy = block_sum<256>(yy, sh);
+  if (threadIdx.x == 0) {
+    d.lam[0] = lambda;
+    st->ynorm2 = yy;
+    st->eps = 0.0;
+    st->t = 0;
+    st->k = 0;
+    st->q = q_in;
+    st->full = active_in ? 0 : 1;
+    st->cur = 0;
+    st->done = 0;
+    st->phase = 0;
+    st->need_refresh = 0;
+  }
+}
+
+const void* const kWideInit[2] = {reinterpret_cast<const void*>(&k_wide_init<float>),
+                                  reinterpret_cast<const void*>(&k_wide_init<double>)};
+const void* const kWideRefresh[2] = {reinterpret_cast<const void*>(&k_wide_refresh<float>),
+                                     reinterpret_cast<const void*>(&k_wide_refresh<double>)};
+const void* const kWideGap[2] = {reinterpret_cast<const void*>(&k_wide_gap<float>),
+                                 reinterpret_cast<const void*>(&k_wide_gap<double>)};
+const void* const kScreenPrep[2] = {reinterpret_cast<const void*>(&k_screen_prep<float>),
+                                    reinterpret_cast<const void*>(&k_screen_prep<double>)};
+const void* const kWideTest = reinterpret_cast<const void*>(&k_wide_test);
+const void* const kWideCompact = reinterpret_cast<const void*>(&k_wide_compact);
+const void* const kWideFin = reinterpret_cast<const void*>(&k_wide_fin);
+const void* const kFillI32 = reinterpret_cast<const void*>(&k_fill_i32);
+
+#define GS_WIDE_ENTRY(XT, VEC, NG)                                              \
+  {                                                                             \
+    sizeof(XT) == 8 ? 1 : 0, VEC, NG,                                           \
+        reinterpret_cast<const void*>(&k_wide_pre<XT, VEC, NG>),                \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG>)               \
+  }
+
+// Ordered by dtype, vector width, then capacity (64 * NG * VEC rows).
+const WideEntry kWide[] = {
+    GS_WIDE_ENTRY(float, 4, 2),  GS_WIDE_ENTRY(float, 4, 4),   GS_WIDE_ENTRY(float, 4, 8),
+    GS_WIDE_ENTRY(float, 1, 8),  GS_WIDE_ENTRY(float, 1, 32),  GS_WIDE_ENTRY(double, 2, 4),
+    GS_WIDE_ENTRY(double, 2, 16), GS_WIDE_ENTRY(double, 1, 8), GS_WIDE_ENTRY(double, 1, 32),
+};
+const int kWideN = sizeof(kWide) / sizeof(kWide[0]);
+
+}  // namespace gs

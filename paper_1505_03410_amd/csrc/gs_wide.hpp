@@ -1,0 +1,393 @@
+// The wide schedule: one Lasso path whose screening passes use the whole GPU.
+// A pass is a chain of kernels that read the state machine in the workspace
+// (WideState), so the host only enqueues passes and polls `done`:
+//
+//   refresh (1 block)  rho = y - X_S beta_S, ||rho||^2, y^T rho
+//   sweep   (grid)     c_k = x_{A[k]}^T rho, per-block max|c|, sums
+//   gap     (1 block)  alpha, G, radius; stop test; record beta^{lambda_t}
+//   test    (grid)     sphere test, per-block kept counts, zero dropped beta
+//   compact (grid)     ordered compaction of A into the other buffer
+//   fin     (1 block)  |A'|, swap buffers
+//   refresh (1 block)  again only if a nonzero coefficient was screened
+//   cd      (1 wave)   f CD epochs over A (k_wide_cd in gs_narrow.hpp)
+//
+// Every reduction goes through per-block partials reduced in a fixed order,
+// so results are bitwise reproducible.
+#pragma once
+
+#include "gs_device.hpp"
+
+namespace gs {
+
+constexpr int kSweepWaves = 4;      // waves per sweep block
+constexpr int kSweepU = 4;          // columns in flight per wave
+constexpr int kTestTile = 2048;     // entries per test/compact block
+constexpr int kRefreshThreads = 1024;
+
+struct WideBufs {
+  double* part;     // partial results, 4 per sweep block (or per pre block)
+  int32_t* cnt;     // kept counts per test block
+  int32_t* nzidx;   // p: nonzero coefficient list (refresh)
+  double* nzval;    // p
+};
+
+// Deterministic block reductions (256 or 1024 threads).
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = NT / 2; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+template <int NT>
+__device__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = NT / 2; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---- precompute: ||x_j||^2, per-block max |x_j^T y| and a non-finite flag.
+template <typename XT, int VEC, int NG>
+__global__ __launch_bounds__(64 * kSweepWaves) void k_wide_pre(ProbDesc d, WideBufs wb) {
+  using L = ColLayout<XT, VEC, 64, NG, false>;
+  constexpr int RPL = L::RPL;
+  __shared__ double sh[64 * kSweepWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const XT* X = (const XT*)d.X;
+  const XT* Y = (const XT*)d.y;
+  double yr[RPL];
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      int i = L::row(lane, m, e);
+      yr[m * VEC + e] = (i < d.n) ? (double)Y[i] : 0.0;
+    }
+  const int W = gridDim.x * kSweepWaves;
+  const int wid = blockIdx.x * kSweepWaves + w;
+  double mx = 0.0, bad = 0.0;
+  for (int j = wid; j < d.p; j += W) {
+    XT xv[RPL];
+    L::load(X + (int64_t)j * d.ldx, d.n, lane, nullptr, xv);
+    double s2 = 0.0, sy = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      s2 = fma((double)xv[i], (double)xv[i], s2);
+      sy = fma((double)xv[i], yr[i], sy);
+    }
+    s2 = wave_sum(s2);
+    sy = wave_sum(sy);
+    if (lane == 0) {
+      d.nrm2[j] = s2;
+      mx = fmax(mx, fabs(sy));
+      if (!isfinite(s2) || !isfinite(sy)) bad = 1.0;
+    }
+  }
+  mx = block_max<64 * kSweepWaves>(mx, sh);
+  bad = block_max<64 * kSweepWaves>(bad, sh);
+  if (threadIdx.x == 0) {
+    wb.part[4 * blockIdx.x + 0] = mx;
+    wb.part[4 * blockIdx.x + 1] = bad;
+  }
+}
+
+// ---- init: lambda_max, ||y||^2, the grid, beta, the state machine.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, WideBufs wb,
+                                                   int npre, PathOpts opts) {
+  __shared__ double sh[256];
+  const XT* Y = (const XT*)d.y;
+  double mx = 0.0, bad = 0.0, yy = 0.0;
+  for (int b = threadIdx.x; b < npre; b += 256) {
+    mx = fmax(mx, wb.part[4 * b]);
+    bad = fmax(bad, wb.part[4 * b + 1]);
+  }
+  for (int i = threadIdx.x; i < d.n; i += 256) {
+    double v = (double)Y[i];
+    yy = fma(v, v, yy);
+  }
+  mx = block_max<256>(mx, sh);
+  bad = block_max<256>(bad, sh);
+  yy = block_sum<256>(yy, sh);
+  if (!isfinite(yy)) bad = 1.0;
+  const int T = d.T;
+  for (int t = threadIdx.x; t < T; t += 256) {
+    double lam;
+    if (d.has_lambdas)
+      lam = d.lam[t] * (d.lambda_relative ? mx : 1.0);
+    else
+      lam = (T == 1) ? mx : mx * pow(d.lambda_min_ratio, (double)t / (double)(T - 1));
+    d.lam[t] = lam;
+    if (d.lambda_out) d.lambda_out[t] = lam;
+  }
+  for (int j = threadIdx.x; j < d.p; j += 256)
+    d.beta[j] = (d.beta_init && bad == 0.0) ? d.beta_init[j] : 0.0;
+  if (bad != 0.0) {
+    for (int64_t e = threadIdx.x; e < (int64_t)d.p * T; e += 256) d.beta_out[e] = 0.0;
+    for (int t = threadIdx.x; t < T; t += 256) {
+      d.gap_out[t] = NAN;
+      d.epochs_out[t] = 0;
+      d.nactive_out[t] = 0;
+      d.status_out[t] = 2;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->lambda_max = mx;
+    st->ynorm2 = yy;
+    st->eps = opts.eps_rel * yy;
+    st->t = 0;
+    st->k = 0;
+    st->q = d.p;
+    st->full = 1;
+    st->cur = 0;
+    st->done = (bad != 0.0) ? 1 : 0;
+    st->phase = 0;
+    st->need_refresh = 0;
+    st->passes = 0;
+    st->status_acc = 0;
+    st->nonfinite = (bad != 0.0) ? 1 : 0;
+  }
+}
+
+// ---- residual refresh: ordered list of nonzero coefficients over A, then
+// rho = y - sum beta_j x_j (ascending j) with one thread per row.
+// mode 0: always; mode 1: only when a nonzero coefficient was screened.
+template <typename XT>
+__global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, WideState* st,
+                                                                  WideBufs wb, int mode) {
+  constexpr int NW = kRefreshThreads / 64;
+  __shared__ int wcnt[NW];
+  __shared__ double sh[kRefreshThreads];
+  if (st->done) return;
+  if (mode == 1 && (st->phase != 2 || !st->need_refresh)) return;
+  const int q = st->q;
+  const bool full = st->full != 0;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // Wave w scans positions [w*span, (w+1)*span) of A in order.
+  const int span = (q + NW - 1) / NW;
+  const int k0 = w * span, k1 = min(q, k0 + span);
+  int cntw = 0;
+  for (int base = k0; base < k1; base += 64) {
+    int k = base + lane;
+    double b = 0.0;
+    if (k < k1) b = d.beta[full ? k : act[k]];
+    cntw += __popcll(ballot(b != 0.0));
+  }
+  if (lane == 0) wcnt[w] = cntw;
+  __syncthreads();
+  int off = 0, nnz = 0;
+  for (int v = 0; v < NW; ++v) {
+    if (v < w) off += wcnt[v];
+    nnz += wcnt[v];
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int base = k0; base < k1; base += 64) {
+    int k = base + lane;
+    int j = 0;
+    double b = 0.0;
+    if (k < k1) {
+      j = full ? k : act[k];
+      b = d.beta[j];
+    }
+    uint64_t m = ballot(b != 0.0);
+    if (b != 0.0) {
+      int pos = off + __popcll(m & lt);
+      wb.nzidx[pos] = j;
+      wb.nzval[pos] = b;
+    }
+    off += __popcll(m);
+  }
+  __threadfence_block();
+  __syncthreads();
+  const XT* X = (const XT*)d.X;
+  const XT* Y = (const XT*)d.y;
+  double s2 = 0.0, sy = 0.0;
+  for (int i = threadIdx.x; i < d.n; i += kRefreshThreads) {
+    const int r = d.rows ? d.rows[i] : i;
+    double yi = (double)Y[r];
+    double v = yi;
+    for (int e = 0; e < nnz; ++e) v = fma(-wb.nzval[e], (double)X[(int64_t)wb.nzidx[e] * d.ldx + r], v);
+    d.rho[i] = v;
+    s2 = fma(v, v, s2);
+    sy = fma(yi, v, sy);
+  }
+  s2 = block_sum<kRefreshThreads>(s2, sh);
+  sy = block_sum<kRefreshThreads>(sy, sh);
+  if (threadIdx.x == 0) {
+    st->R2 = s2;
+    st->Ry = sy;
+    st->nnz = nnz;
+    if (mode == 1) st->need_refresh = 0;
+  }
+}
+
+// ---- the sweep: c_k = x_{A[k]}^T rho for the k of A, per-block partials
+// (max |c|, ||beta||_1, sum |beta_j| ||x_j||, max ||x_j||).  When
+// with_nrm2 is set the column norms are computed here too (screen()).
+template <typename XT, int VEC, int NG>
+__global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, WideState* st,
+                                                                 WideBufs wb, int with_nrm2) {
+  using L = ColLayout<XT, VEC, 64, NG, false>;
+  constexpr int RPL = L::RPL;
+  __shared__ double sh[64 * kSweepWaves];
+  if (st->done) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = st->q;
+  const bool full = st->full != 0;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const XT* X = (const XT*)d.X;
+  double r[RPL];
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      int i = L::row(lane, m, e);
+      r[m * VEC + e] = (i < d.n) ? d.rho[i] : 0.0;
+    }
+  const int W = gridDim.x * kSweepWaves;
+  const int wid = blockIdx.x * kSweepWaves + w;
+  double Ml = 0.0, l1 = 0.0, sb = 0.0, xm = 0.0;
+  for (int base = wid * kSweepU; base < q; base += W * kSweepU) {
+    XT xv[kSweepU][RPL];
+    int jj[kSweepU];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      int k = base + u;
+      jj[u] = (k < q) ? (full ? k : act[k]) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      if (jj[u] >= 0) {
+        L::load(X + (int64_t)jj[u] * d.ldx, d.n, lane, nullptr, xv[u]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) xv[u][i] = XT(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      double a = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        a = fma((double)xv[u][i], r[i], a);
+        if (with_nrm2) s2 = fma((double)xv[u][i], (double)xv[u][i], s2);
+      }
+      a = wave_sum(a);
+      if (with_nrm2) s2 = wave_sum(s2);
+      if (jj[u] >= 0 && lane == 0) {
+        const int j = jj[u];
+        d.c[base + u] = a;
+        if (with_nrm2) d.nrm2[j] = s2;
+        const double nr = with_nrm2 ? s2 : d.nrm2[j];
+        const double b = d.beta[j];
+        Ml = fmax(Ml, fabs(a));
+        l1 += fabs(b);
+        sb += fabs(b) * sqrt(nr);
+        xm = fmax(xm, sqrt(nr));
+      }
+    }
+  }
+  Ml = block_max<64 * kSweepWaves>(Ml, sh);
+  l1 = block_sum<64 * kSweepWaves>(l1, sh);
+  sb = block_sum<64 * kSweepWaves>(sb, sh);
+  xm = block_max<64 * kSweepWaves>(xm, sh);
+  if (threadIdx.x == 0) {
+    wb.part[4 * blockIdx.x + 0] = Ml;
+    wb.part[4 * blockIdx.x + 1] = l1;
+    wb.part[4 * blockIdx.x + 2] = sb;
+    wb.part[4 * blockIdx.x + 3] = xm;
+  }
+}
+
+// ---- gap, stop test and bookkeeping.  mode 0: path; mode 1: screen() (the
+// gap is reported and the test always runs).
+template <typename XT>
+__global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, WideBufs wb,
+                                                  int nsweep, int mode, double* gap_o,
+                                                  double* alpha_o, double* radius_o,
+                                                  PathOpts opts) {
+  __shared__ double sh[256];
+  if (st->done) return;
+  double M = 0.0, l1 = 0.0, sb = 0.0, xm = 0.0;
+  for (int b = threadIdx.x; b < nsweep; b += 256) {
+    M = fmax(M, wb.part[4 * b]);
+    l1 += wb.part[4 * b + 1];
+    sb += wb.part[4 * b + 2];
+    xm = fmax(xm, wb.part[4 * b + 3]);
+  }
+  M = block_max<256>(M, sh);
+  l1 = block_sum<256>(l1, sh);
+  sb = block_sum<256>(sb, sh);
+  xm = block_max<256>(xm, sh);
+  const int t = st->t;
+  const double lambda = d.lam[t];
+  GapInfo g = gap_safe(st->R2, st->Ry, l1, sb, xm, M, st->nnz, d.n, lambda, sqrt(st->ynorm2));
+  if (mode == 1) {
+    if (threadIdx.x == 0) {
+      *gap_o = g.gap;
+      *alpha_o = g.alpha;
+      *radius_o = g.radius;
+      st->alpha_s = g.alpha;
+      st->radius_s = g.radius;
+      st->e_c = g.e_c;
+      st->gap = g.gap;
+      st->phase = 1;
+    }
+    return;
+  }
+  const bool conv = g.gap <= st->eps;
+  const bool out_of_budget = st->k >= opts.K;
+  if (conv || out_of_budget) {
+    const int p = d.p;
+    double* bo = d.beta_out + (int64_t)t * p;
+    for (int j = threadIdx.x; j < p; j += 256) bo[j] = d.beta[j];
+    if (threadIdx.x == 0) {
+      d.gap_out[t] = g.gap;
+      d.epochs_out[t] = st->k;
+      d.nactive_out[t] = st->q;
+      d.status_out[t] = conv ? 0 : 1;
+      if (!conv) st->status_acc = 1;
+      st->passes += 1;
+      st->t = t + 1;
+      st->k = 0;
+      st->q = p;
+      st->full = 1;
+      st->cur = 0;
+      st->phase = 0;
+      st->need_refresh = 0;
+      if (t + 1 >= d.T) st->done = 1;
+    }
+  } else if (threadIdx.x == 0) {
+    st->alpha_s = g.alpha;
+    st->radius_s = g.radius;
+    st->e_c = g.e_c;
+    st->gap = g.gap;
+    st->phase = 1;
+    st->passes += 1;
+  }
+}
+
+// ---- sphere test: per-block kept counts; zero screened nonzero coefficients.
+__global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, WideBufs wb);
+// ---- ordered compaction of the kept indices into `out` (or the other buffer).
+__global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st, WideBufs wb,
+                                                      int32_t* out);
+// ---- |A'| and buffer swap (path) or q_out (screen()).
+__global__ __launch_bounds__(64) void k_wide_fin(ProbDesc d, WideState* st, WideBufs wb,
+                                                 int ntest, int32_t* q_out);
+
+}  // namespace gs

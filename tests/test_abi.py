@@ -1,0 +1,134 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/gapsafe.h declares, and rejects bad arguments before
+launching anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1505_03410_amd as gs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "gapsafe.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gs.LIB_PATH):
+        pytest.fail("libgapsafe.so is not built: run __graft_entry__.build()")
+    return gs.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared_functions()
+    assert set(declared) == set(gs.EXPORTS), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header():
+    # offsets implied by natural alignment of the C structs
+    assert ctypes.sizeof(gs.gs_problem) == 136
+    assert gs.gs_problem.lambda_min_ratio.offset == 72
+    assert gs.gs_problem.lambda_out.offset == 128
+    assert ctypes.sizeof(gs.gs_opts) == 40
+
+
+def test_defaults(lib):
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    assert o.eps_rel == 1e-8 and o.screen_every == 10 and o.max_epochs == 100000
+    assert o.schedule == 0 and not o.select_counts and not o.timestamps
+
+
+def _prob(**kw):
+    pr = gs.gs_problem()
+    pr.n, pr.p, pr.ldx, pr.dtype, pr.T = 8, 20, 8, gs.GS_F32, 3
+    fake = 4096
+    pr.X = pr.y = pr.beta_out = pr.gap_out = fake
+    pr.epochs_out = pr.nactive_out = pr.status_out = fake
+    pr.lambda_min_ratio = 0.01
+    for k, v in kw.items():
+        setattr(pr, k, v)
+    return pr
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(p=0), dict(T=0), dict(ldx=4), dict(dtype=7), dict(X=None),
+    dict(gap_out=None), dict(lambda_min_ratio=0.0), dict(lambda_min_ratio=2.0),
+    dict(lambda_min_ratio=float("nan")),
+])
+def test_invalid_problem_rejected(lib, bad):
+    pr = _prob(**bad)
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    assert lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o)) == 0
+    rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30, None)
+    assert rc == gs.GS_EINVAL
+
+
+def test_invalid_lambdas_rejected(lib):
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    for vals in ([1.0, 2.0, 0.5], [1.0, -1.0, -2.0], [1.0, float("inf"), 0.1]):
+        lam = np.array(vals)
+        pr = _prob(lambdas=lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30, None)
+        assert rc == gs.GS_EINVAL, vals
+
+
+@pytest.mark.parametrize("field,val", [("eps_rel", 0.0), ("eps_rel", float("nan")),
+                                       ("screen_every", 0), ("max_epochs", -1), ("schedule", 9)])
+def test_invalid_opts_rejected(lib, field, val):
+    pr = _prob()
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    setattr(o, field, val)
+    rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30, None)
+    assert rc == gs.GS_EINVAL
+
+
+def test_workspace_checks(lib):
+    pr = _prob()
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
+    assert need > 0 and need % 256 == 0
+    assert lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), None, need, None) == gs.GS_EWORKSPACE
+    assert lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), ctypes.c_void_p(4096), need - 1,
+                          None) == gs.GS_EWORKSPACE
+    # bigger problems need more
+    pr2 = _prob(p=4000, T=100)
+    assert lib.lasso_workspace_size(ctypes.byref(pr2), 1, ctypes.byref(o)) > need
+    assert lib.screen_workspace_size(8, 20) > 0
+    assert lib.screen_workspace_size(0, 20) == 0
+
+
+def test_unsupported_n(lib):
+    pr = _prob(n=5000, ldx=5000)
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30, None)
+    assert rc == gs.GS_EUNSUPPORTED
+
+
+def test_screen_invalid(lib):
+    vp = ctypes.c_void_p(4096)
+    args = [8, 20, 8, gs.GS_F32, vp, vp, vp, 0.5, None, 0, vp, vp, vp, vp, vp, None, vp, 1 << 30, None]
+    for idx, val in [(0, 0), (2, 4), (3, 5), (7, 0.0), (7, float("inf")), (4, None)]:
+        a = list(args)
+        a[idx] = val
+        assert lib.screen(*a) == gs.GS_EINVAL, (idx, val)
+
+
+def test_strerror(lib):
+    for c in (0, 1, -1, -2, -3, -4, 99):
+        assert isinstance(gs.strerror(c), str) and gs.strerror(c)

@@ -1,0 +1,333 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Tolerances follow from the method (Sec. 3.2 and Proposition 1 of Fercoq,
+Gramfort & Salmon): a gap G certifies ||X(beta - beta_hat)||^2 <= 2G and
+||theta - theta_hat|| <= sqrt(2G)/lambda, so two certified solutions are
+compared through these bounds; the oracle also re-certifies every GPU
+iterate by recomputing its gap independently.  FP64 reductions on both sides
+differ only by summation order, so pass-level scalars agree to ~1e-12.
+"""
+import numpy as np
+import pytest
+
+import paper_1505_03410_amd as gs
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    gs.load_library()  # fails loudly when the HIP library is missing
+    return torch
+
+
+def _dev(torch, X, y, ld_multiple=4):
+    Xd = gs.colmajor_to_device(X, ld_multiple=ld_multiple)
+    yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
+    return Xd, yd
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ screen
+
+def _screen_case(torch, orc, X, y, beta, lam, active=None, ld_multiple=4):
+    Xd, yd = _dev(torch, X, y, ld_multiple)
+    bd = torch.from_numpy(np.ascontiguousarray(beta, dtype=np.float64)).cuda()
+    ad = None if active is None else torch.from_numpy(active.astype(np.int32)).cuda()
+    g = gs.screen(Xd, yd, bd, lam, ad)
+    torch.cuda.synchronize()
+    o = orc.screen(_f64(X), _f64(y), _f64(beta), lam, active)
+    q = int(_np(g["q"])[0])
+    kept = set(_np(g["active"])[:q].tolist())
+    # scalars
+    scale = 0.5 * o["rho_norm2"] + lam * o["l1"] + 1e-300
+    assert abs(float(_np(g["gap"])[0]) - o["gap"]) <= 1e-10 * scale
+    assert abs(float(_np(g["alpha"])[0]) - o["alpha"]) <= 1e-12 * abs(o["alpha"]) + 1e-300
+    # c_j = x_j^T rho in FP64
+    xn = np.linalg.norm(_f64(X)[:, o["active"]], axis=0)
+    err = np.abs(_np(g["c"]) - o["c"])
+    assert np.all(err <= 1e-12 * xn * np.sqrt(o["rho_norm2"]) + 1e-300)
+    # safe: everything the exact formula keeps is kept; and the GPU keeps
+    # nothing the test would drop with a margin of 1e-6
+    ex = set(o["active"][o["keep_exact"]].tolist())
+    assert ex <= kept
+    mu = np.abs(o["alpha"] * o["c"]) + o["radius"] * xn
+    loose = set(o["active"][mu >= 1 - 1e-6].tolist())
+    assert kept <= loose
+    assert list(_np(g["active"])[:q]) == sorted(kept)
+    return g, o
+
+
+def test_screen_c0_f64(torch, orc):
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    lmax = np.abs(X.T @ y).max()
+    rng = np.random.default_rng(0)
+    for ratio in (0.9, 0.3, 0.1):
+        beta = np.zeros(500)
+        beta[rng.choice(500, 8, replace=False)] = 0.1 * rng.standard_normal(8)
+        _screen_case(torch, orc, X, y, beta, ratio * lmax, ld_multiple=2)
+
+
+def test_screen_c1_f32_with_active_set(torch, orc):
+    d = synth.c1()
+    X, y = d["X"], d["y"]
+    lmax = np.abs(_f64(X).T @ _f64(y)).max()
+    lam = 0.2 * lmax
+    r = orc.lasso_path(X, y, lambdas=[lmax, lam], K=40)  # a mid-run iterate
+    beta = r["beta"][1]
+    g, o = _screen_case(torch, orc, X, y, beta, lam)
+    act = np.sort(np.random.default_rng(1).choice(7129, 3000, replace=False)).astype(np.int32)
+    act = np.union1d(act, np.flatnonzero(beta)).astype(np.int32)
+    _screen_case(torch, orc, X, y, beta, lam, active=act)
+
+
+def test_screen_ragged_and_small(torch, orc):
+    """n not a multiple of the vector width (scalar loads), tiny p, empty A."""
+    for (n, p, ldm) in [(37, 5, 1), (37, 300, 4), (1, 40, 1), (130, 1, 4)]:
+        d = synth.gaussian(n * 7 + p, n, p, k=min(3, p))
+        X = d["X"].astype(np.float32)
+        y = d["y"].astype(np.float32)
+        lam = 0.3 * np.abs(_f64(X).T @ _f64(y)).max()
+        _screen_case(torch, orc, X, y, np.zeros(p), lam, ld_multiple=ldm)
+    d = synth.gaussian(3, 20, 50)
+    X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+    g, o = _screen_case(torch, orc, X, y, np.zeros(50), 0.5,
+                        active=np.zeros(0, np.int32))
+    assert int(_np(g["q"])[0]) == 0
+
+
+@pytest.mark.parametrize("full", [True])
+def test_screen_c4_full_size_sampled(torch, orc, full):
+    """The 1000 x 100000 (400 MB) sweep in the launch configuration the
+    benchmark times: gap and alpha against the oracle, c_j on a sample of
+    columns against FP64 dot products."""
+    d = synth.c4()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    rng = np.random.default_rng(4)
+    beta = np.zeros(X.shape[1])
+    beta[rng.choice(X.shape[1], 40, replace=False)] = 0.05 * rng.standard_normal(40)
+    bd = torch.from_numpy(beta).cuda()
+    lmax = float(np.abs(_f64(X).T @ _f64(y)).max())
+    lam = 0.3 * lmax
+    g = gs.screen(Xd, yd, bd, lam)
+    torch.cuda.synchronize()
+    o = orc.screen(X, y, beta, lam)
+    scale = 0.5 * o["rho_norm2"] + lam * o["l1"]
+    assert abs(float(_np(g["gap"])[0]) - o["gap"]) <= 1e-10 * scale
+    c = _np(g["c"])
+    rho = _f64(y) - _f64(X) @ _f64(beta)
+    js = rng.choice(X.shape[1], 2000, replace=False)
+    ref = _f64(X)[:, js].T @ rho
+    xn = np.linalg.norm(_f64(X)[:, js], axis=0)
+    assert np.all(np.abs(c[js] - ref) <= 1e-12 * xn * np.linalg.norm(rho))
+    q = int(_np(g["q"])[0])
+    ex = set(o["active"][o["keep_exact"]].tolist())
+    kept = set(_np(g["active"])[:q].tolist())
+    assert ex <= kept and len(kept) - len(ex) <= max(5, len(ex) // 1000)
+
+
+# -------------------------------------------------------------------- paths
+
+def _primal(Xf, yf, b, lam):
+    r = Xf @ b - yf
+    return 0.5 * r @ r + lam * np.abs(b).sum()
+
+
+def _check_path(X, y, got, orc, lambdas, eps_rel=1e-8, tight=None, beta_tol=None):
+    """Check each returned beta against a tight oracle solution beta*:
+    the reported gap bounds the suboptimality, P(beta) - P(beta*) <= G + G*,
+    and ||X(beta - beta*)|| <= sqrt(2G) + sqrt(2G*) (Sec. 3.2 weak duality and
+    the strong convexity of the quadratic in X beta)."""
+    Xf, yf = _f64(X), _f64(y)
+    yy = float(yf @ yf)
+    eps = eps_rel * yy
+    B = _np(got["beta"])
+    gap = _np(got["gap"])
+    st = _np(got["status"])
+    assert np.all(st == 0), st
+    assert np.all(gap <= eps)
+    if tight is None:
+        tight = orc.lasso_path(Xf, yf, lambdas=lambdas, eps_rel=1e-13)
+    worst = 0.0
+    for t, lam in enumerate(lambdas):
+        Gs = max(tight["gap"][t], 0.0)
+        sub = _primal(Xf, yf, B[t], lam) - _primal(Xf, yf, tight["beta"][t], lam)
+        assert sub <= gap[t] + Gs + 1e-12 * yy, (t, sub, gap[t])
+        d = Xf @ (B[t] - tight["beta"][t])
+        assert np.linalg.norm(d) <= np.sqrt(2 * max(gap[t], 0)) + np.sqrt(2 * Gs) + 1e-9 * np.sqrt(yy)
+        nb = np.linalg.norm(tight["beta"][t])
+        if nb > 0:
+            worst = max(worst, np.linalg.norm(B[t] - tight["beta"][t]) / nb)
+        else:
+            assert np.all(B[t] == 0)
+    if beta_tol is not None:
+        assert worst <= beta_tol, worst
+    return worst
+
+
+def test_path_c0_f64(torch, orc):
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    lmax = orc.precompute(X, y)["lambda_max"]
+    lams = [lmax, lmax * d["lambda_ratio"]]
+    Xd, yd = _dev(torch, X, y, 2)
+    got = gs.lasso_path(Xd, yd, lambdas=lams)
+    torch.cuda.synchronize()
+    _check_path(X, y, got, orc, lams, beta_tol=1e-5)
+    assert int(_np(got["epochs"])[0]) == 0
+    assert np.all(_np(got["beta"])[0] == 0)
+
+
+def test_path_c1_full(torch, orc):
+    """The benchmark workload: 72 x 7129 FP32, 100 lambdas, delta = 3."""
+    d = synth.c1()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3)
+    torch.cuda.synchronize()
+    lams = _np(got["lambdas"])
+    ref = orc.grid(orc.precompute(X, y)["lambda_max"], 100, 3.0)
+    np.testing.assert_allclose(lams, ref, rtol=1e-13)
+    worst = _check_path(X, y, got, orc, lams)
+    print(f"c1 path: worst relative beta error vs tight oracle {worst:.2e}, "
+          f"epochs {int(_np(got['epochs']).sum())}")
+
+
+def test_path_wide_matches(torch, orc):
+    """The wide schedule (sweeps over all CUs) on a C1-shaped problem."""
+    d = synth.c1()
+    X, y = d["X"][:, :3000], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path(Xd, yd, T=30, lambda_min_ratio=1e-2, schedule="wide")
+    torch.cuda.synchronize()
+    _check_path(X, y, got, orc, _np(got["lambdas"]))
+
+
+def test_path_large_n_configs(torch, orc):
+    """Rows spread over 16 and 64 lanes (n = 300 and n = 1000)."""
+    for n, p in [(300, 800), (1000, 600)]:
+        d = synth.gaussian(n + p, n, p, k=20, sigma=0.5)
+        X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+        Xd, yd = _dev(torch, X, y)
+        got = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.01)
+        torch.cuda.synchronize()
+        _check_path(X, y, got, orc, _np(got["lambdas"]))
+
+
+def test_batch_row_subsamples(torch, orc):
+    """lasso_solve_batch with row subsamples of the C1 matrix (the stability
+    selection workload at reduced count), plus the selection counts."""
+    d = synth.c2(B=6)
+    X, y, rows = d["X"], d["y"], d["rows"]
+    Xd, yd = _dev(torch, X, y)
+    probs, T = [], 40
+    for b in range(rows.shape[0]):
+        probs.append(dict(X=Xd, y=yd, rows=torch.from_numpy(rows[b]).cuda(), T=T,
+                          lambda_min_ratio=1e-2))
+    counts = torch.zeros((T, X.shape[1]), dtype=torch.int32, device="cuda")
+    outs = gs.lasso_solve_batch(probs, select_counts=counts)
+    torch.cuda.synchronize()
+    sel = np.zeros((T, X.shape[1]), np.int32)
+    for b, out in enumerate(outs):
+        Xs, ys = X[rows[b]], y[rows[b]]
+        _check_path(Xs, ys, out, orc, _np(out["lambdas"]))
+        sel += (_np(out["beta"]) != 0)
+    np.testing.assert_array_equal(_np(counts), sel)
+
+
+# --------------------------------------------------------------- edge cases
+
+def test_lambda_above_max_gives_zero(torch, orc):
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    lmax = orc.precompute(X, y)["lambda_max"]
+    Xd, yd = _dev(torch, X, y, 2)
+    got = gs.lasso_path(Xd, yd, lambdas=[3.0, 1.0 + 1e-9], relative=True)
+    torch.cuda.synchronize()
+    assert np.all(_np(got["beta"]) == 0)
+    assert np.all(_np(got["epochs"]) == 0)
+    np.testing.assert_allclose(_np(got["lambdas"]), [3 * lmax, lmax * (1 + 1e-9)], rtol=1e-14)
+
+
+def test_nonfinite_input_flagged(torch):
+    d = synth.gaussian(1, 40, 100)
+    X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+    X[3, 17] = np.nan
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path(Xd, yd, T=5, lambda_min_ratio=0.1)
+    torch.cuda.synchronize()
+    assert np.all(_np(got["status"]) == 2)
+    assert np.all(_np(got["beta"]) == 0)
+
+
+def test_epoch_budget(torch, orc):
+    """max_epochs reached: status 1 and a gap that is the true gap of the
+    returned beta (the oracle recomputes it)."""
+    d = synth.c1()
+    X, y = d["X"][:, :2000], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    lmax = orc.precompute(X, y)["lambda_max"]
+    lam = 0.01 * lmax
+    got = gs.lasso_path(Xd, yd, lambdas=[lam], max_epochs=7)
+    torch.cuda.synchronize()
+    assert int(_np(got["status"])[0]) == 1 and int(_np(got["epochs"])[0]) == 7
+    # the gap of the returned beta, recomputed by the oracle on the same
+    # (full) active set: the first pass after the budget has not screened
+    o1 = orc.screen(X, y, _np(got["beta"])[0], lam)
+    assert _np(got["gap"])[0] <= o1["gap"] * (1 + 1e-9)
+    # same budget in the oracle: same iterate up to rounding
+    o = orc.lasso_path(X, y, lambdas=[lam], K=7)
+    assert np.linalg.norm(_f64(X) @ (_np(got["beta"])[0] - o["beta"][0])) <= \
+        1e-4 * np.linalg.norm(_f64(y))
+
+
+def test_zero_column_and_tiny_shapes(torch, orc):
+    d = synth.gaussian(5, 33, 70)
+    X = d["X"].astype(np.float32)
+    X[:, 10] = 0.0
+    y = d["y"].astype(np.float32)
+    for ldm in (1, 4):
+        Xd, yd = _dev(torch, X, y, ldm)
+        got = gs.lasso_path(Xd, yd, T=8, lambda_min_ratio=0.05)
+        torch.cuda.synchronize()
+        _check_path(X, y, got, orc, _np(got["lambdas"]))
+        assert np.all(_np(got["beta"])[:, 10] == 0)
+    for n, p in [(1, 3), (5, 1), (64, 2)]:
+        d = synth.gaussian(n * 10 + p, n, p, k=1)
+        X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+        Xd, yd = _dev(torch, X, y, 1)
+        got = gs.lasso_path(Xd, yd, T=4, lambda_min_ratio=0.1)
+        torch.cuda.synchronize()
+        _check_path(X, y, got, orc, _np(got["lambdas"]))
+
+
+def test_determinism_and_resume(torch, orc):
+    """Two runs are bitwise equal; a path resumed at t = 6 from the stored
+    beta^{lambda_5} (FP64, so the state is exact) equals the uninterrupted run."""
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y, 2)
+    a = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.05)
+    b = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.05)
+    torch.cuda.synchronize()
+    for k in ("beta", "gap", "epochs", "nactive"):
+        assert np.array_equal(_np(a[k]), _np(b[k])), k
+    lams = _np(a["lambdas"])
+    c = gs.lasso_path(Xd, yd, lambdas=lams[6:], beta_init=a["beta"][5].contiguous())
+    torch.cuda.synchronize()
+    for k in ("beta", "gap", "epochs", "nactive"):
+        assert np.array_equal(_np(c[k]), _np(a[k])[6:]), k

@@ -17,9 +17,10 @@
  *   beta_out, screen()'s beta) are always FP64, so that a returned beta is
  *   exactly the iterate whose gap is reported.  All reductions, the residual,
  *   the duality gap and the screening radius are FP64 on the device.
- * - Vectorized 16-byte loads are used when X is 16-byte aligned and
- *   ldx*sizeof(dtype) is a multiple of 16; otherwise scalar loads.  No entry
- *   beyond row n-1 of a column is read.
+ * - Vectorized 16-byte loads are used when X is 16-byte aligned,
+ *   ldx*sizeof(dtype) is a multiple of 16 and n is a multiple of
+ *   16/sizeof(dtype); otherwise scalar loads.  No entry beyond row n-1 of a
+ *   column is read.
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  The
  *   per-problem ("narrow") schedule is stream-ordered and asynchronous:
  *   outputs are valid once the caller synchronizes the stream.  The wide
@@ -77,6 +78,15 @@ enum {
   GS_SCHED_WIDE = 2    /* sweeps over all CUs, CD on one wavefront (one problem) */
 };
 
+/* CD epoch modes of the narrow schedule (gs_opts.cd_mode).  Both run the
+ * same cyclic coordinate descent; they differ in what is kept on chip. */
+enum {
+  GS_CD_AUTO = 0,     /* correlation (Gram) updates in LDS when the active set
+                         has at most 1024 coordinates and the LDS cache holds
+                         at least 8 columns of it; residual updates otherwise */
+  GS_CD_RESIDUAL = 1  /* residual updates only (rho in registers and LDS)    */
+};
+
 /* One Lasso path (Algorithm 1 inputs X, y and the lambda grid). */
 typedef struct gs_problem {
   int32_t n, p;            /* rows and columns of the design, n, p >= 1        */
@@ -115,6 +125,7 @@ typedef struct gs_opts {
                             Sec. 4.1)                                        */
   int32_t max_epochs;    /* K: CD epochs per lambda (default 100000)         */
   int32_t schedule;      /* GS_SCHED_*                                        */
+  int32_t cd_mode;       /* GS_CD_*: how the narrow schedule runs its epochs  */
   int32_t* select_counts;/* [device] optional (batch only): T x p int32
                             counters; count[t*p + j] += 1 for every problem
                             whose beta^{lambda_t}_j != 0 (stability
@@ -174,6 +185,18 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
            int32_t* q_out, double* gap_out, double* alpha_out,
            double* radius_out, double* c_out, void* workspace,
            size_t ws_bytes, void* stream);
+
+/* Optional kernel timing for benchmarks (off by default).  When on, the
+ * library records a pair of HIP events on the launch stream around each
+ * launch of the named kernels and accumulates their elapsed time:
+ *   "sweep"  the X^T rho sweep of the wide schedule and of screen()
+ *   "path"   the persistent per-problem path kernel (narrow schedule)
+ * gs_timing_query waits for the recorded events, then returns the total in
+ * milliseconds and the number of launches (0 / -1 for an unknown name).
+ * Not thread-safe; meant for single-threaded benchmark drivers. */
+void gs_timing_enable(int on);
+void gs_timing_reset(void);
+int gs_timing_query(const char* kernel, double* total_ms, int64_t* launches);
 
 /* Human-readable text for a return code (for GS_EHIP, the last HIP error). */
 const char* lasso_strerror(int code);

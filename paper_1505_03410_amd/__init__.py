@@ -27,6 +27,7 @@ GS_F32, GS_F64 = 0, 1
 GS_OK, GS_NOT_CONVERGED = 0, 1
 GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED = -1, -2, -3, -4
 SCHEDULES = {"auto": 0, "narrow": 1, "wide": 2}
+CD_MODES = {"auto": 0, "residual": 1}
 
 
 class GsError(RuntimeError):
@@ -53,12 +54,14 @@ class gs_opts(ctypes.Structure):
     _fields_ = [
         ("eps_rel", ctypes.c_double), ("screen_every", ctypes.c_int32),
         ("max_epochs", ctypes.c_int32), ("schedule", ctypes.c_int32),
+        ("cd_mode", ctypes.c_int32),
         ("select_counts", ctypes.c_void_p), ("timestamps", ctypes.c_void_p),
     ]
 
 
 EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
-           "lasso_solve_batch", "screen_workspace_size", "screen", "lasso_strerror"]
+           "lasso_solve_batch", "screen_workspace_size", "screen", "gs_timing_enable",
+           "gs_timing_reset", "gs_timing_query", "lasso_strerror"]
 
 _lib = None
 
@@ -90,6 +93,12 @@ def load_library(path: str = LIB_PATH):
                            vp, vp, vp, ctypes.c_double, vp, ctypes.c_int32, vp, vp, vp, vp,
                            vp, vp, vp, ctypes.c_size_t, vp]
     lib.screen.restype = ctypes.c_int
+    lib.gs_timing_enable.argtypes = [ctypes.c_int]
+    lib.gs_timing_enable.restype = None
+    lib.gs_timing_reset.argtypes = []
+    lib.gs_timing_reset.restype = None
+    lib.gs_timing_query.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.gs_timing_query.restype = ctypes.c_int
     lib.lasso_strerror.argtypes = [ctypes.c_int]
     lib.lasso_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -210,13 +219,15 @@ def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, o
     return pr, out, host_lam
 
 
-def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, timestamps=None):
+def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, timestamps=None,
+          cd_mode="auto"):
     o = gs_opts()
     load_library().gs_opts_default(ctypes.byref(o))
     o.eps_rel = float(eps_rel)
     o.screen_every = int(screen_every)
     o.max_epochs = int(max_epochs)
     o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    o.cd_mode = CD_MODES[cd_mode] if isinstance(cd_mode, str) else int(cd_mode)
     o.select_counts = None if select_counts is None else select_counts.data_ptr()
     o.timestamps = None if timestamps is None else timestamps.data_ptr()
     return o
@@ -234,8 +245,8 @@ def _workspace(nbytes, device):
 def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
                relative: bool = False, lambda_min_ratio: float = 1e-3, beta_init=None,
                rows=None, eps_rel: float = 1e-8, screen_every: int = 10,
-               max_epochs: int = 100000, schedule="auto", stream=None, out=None,
-               workspace=None):
+               max_epochs: int = 100000, schedule="auto", cd_mode="auto", stream=None,
+               out=None, workspace=None):
     """Algorithm 1 on the device for one problem; see include/gapsafe.h.
     Returns a PathResult of device tensors (valid after the stream syncs) with
     an extra ``rc`` entry (GS_OK or GS_NOT_CONVERGED)."""
@@ -243,7 +254,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
     pr, out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
                               lambda_min_ratio=lambda_min_ratio, beta_init=beta_init,
                               rows=rows, out=out)
-    o = _opts(eps_rel, screen_every, max_epochs, schedule)
+    o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode)
     need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
     rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))
@@ -255,7 +266,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
 
 def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10,
                       max_epochs: int = 100000, select_counts=None, timestamps=None,
-                      stream=None, workspace=None):
+                      cd_mode="auto", stream=None, workspace=None):
     """Many paths in one persistent launch.  ``problems`` is a list of dicts
     with keys X, y and optionally T, lambdas, relative, lambda_min_ratio,
     beta_init, rows.  Returns the list of PathResults."""
@@ -272,7 +283,7 @@ def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10
         arr[b] = pr
         outs.append(out)
         keep.append(hl)
-    o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps)
+    o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps, cd_mode)
     need = lib.lasso_workspace_size(arr, B, ctypes.byref(o))
     dev = problems[0]["X"].device
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
@@ -313,6 +324,23 @@ def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=N
     _check(rc, allow_not_converged=False)
     return dict(active=act_out, q=q_out, gap=gap, alpha=alpha, radius=radius,
                 c=c if c is None else c[:q], workspace=ws)
+
+
+def timing_enable(on: bool = True):
+    load_library().gs_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    load_library().gs_timing_reset()
+
+
+def timing_query(kernel: str):
+    """(total milliseconds, launches) of the named kernel since the reset."""
+    tot = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    if load_library().gs_timing_query(kernel.encode(), ctypes.byref(tot), ctypes.byref(cnt)) != 0:
+        raise ValueError(f"unknown kernel name {kernel!r}")
+    return tot.value, cnt.value
 
 
 def wallclock_hz() -> float:

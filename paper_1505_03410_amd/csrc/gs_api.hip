@@ -79,12 +79,17 @@ int check_opts(const gs_opts* o) {
   if (!finite_pos(o->eps_rel)) return GS_EINVAL;
   if (o->screen_every < 1 || o->max_epochs < 0) return GS_EINVAL;
   if (o->schedule < GS_SCHED_AUTO || o->schedule > GS_SCHED_WIDE) return GS_EINVAL;
+  if (o->cd_mode < GS_CD_AUTO || o->cd_mode > GS_CD_RESIDUAL) return GS_EINVAL;
   return GS_OK;
 }
 
+// 16-byte loads need an aligned X, aligned columns and n a multiple of the
+// vector width (no load then straddles row n).
 bool vec_ok(const gs_problem* pr) {
   const size_t es = pr->dtype == GS_F64 ? 8 : 4;
-  return (reinterpret_cast<uintptr_t>(pr->X) % 16 == 0) && ((size_t)pr->ldx * es) % 16 == 0;
+  const int vec = (int)(16 / es);
+  return (reinterpret_cast<uintptr_t>(pr->X) % 16 == 0) && ((size_t)pr->ldx * es) % 16 == 0 &&
+         pr->n % vec == 0;
 }
 
 const NarrowEntry* narrow_table(int dtype, bool gather, bool vec, int* count) {
@@ -129,6 +134,7 @@ bool use_wide(const gs_problem* pr, const gs_opts* o) {
 // Per-problem workspace arrays.
 void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   d->nrm2 = cv.take<double>(pr->p);
+  d->inv = cv.take<double>(pr->p);
   d->beta = cv.take<double>(pr->p);
   d->c = cv.take<double>(pr->p);
   d->act = cv.take<int32_t>(2 * (size_t)pr->p);
@@ -181,6 +187,8 @@ PathOpts path_opts(const gs_opts* o, bool batch) {
   po.eps_rel = o->eps_rel;
   po.f = o->screen_every;
   po.K = o->max_epochs;
+  po.gram_cap = 0;
+  po.pad_ = 0;
   po.select_counts = batch ? o->select_counts : nullptr;
   po.timestamps = batch ? reinterpret_cast<long long*>(o->timestamps) : nullptr;
   return po;
@@ -188,6 +196,48 @@ PathOpts path_opts(const gs_opts* o, bool batch) {
 
 hipError_t launch(const void* k, dim3 g, dim3 b, void** args, size_t smem, hipStream_t s) {
   return hipLaunchKernel(k, g, b, args, smem, s);
+}
+
+// ---- optional event timing of selected kernels (gs_timing_*)
+struct Timed {
+  int slot;
+  hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<Timed> g_pending;
+double g_total_ms[2] = {0.0, 0.0};
+int64_t g_launches[2] = {0, 0};
+enum { kTimeSweep = 0, kTimePath = 1 };
+
+hipError_t timed_launch(int slot, const void* k, dim3 g, dim3 b, void** args, size_t smem,
+                        hipStream_t s) {
+  if (!g_timing) return launch(k, g, b, args, smem, s);
+  Timed t{slot, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&t.a);
+  if (e == hipSuccess) e = hipEventCreate(&t.b);
+  if (e == hipSuccess) e = hipEventRecord(t.a, s);
+  if (e == hipSuccess) e = launch(k, g, b, args, smem, s);
+  if (e == hipSuccess) e = hipEventRecord(t.b, s);
+  if (e == hipSuccess) {
+    g_pending.push_back(t);
+  } else {
+    if (t.a) (void)hipEventDestroy(t.a);
+    if (t.b) (void)hipEventDestroy(t.b);
+  }
+  return e;
+}
+
+void resolve_timing() {
+  for (const Timed& t : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      g_total_ms[t.slot] += ms;
+      g_launches[t.slot] += 1;
+    }
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_pending.clear();
 }
 
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
@@ -208,14 +258,40 @@ int device_cus() {
   return cus;
 }
 
+size_t device_lds_per_cu() {
+  static int lds = 0;
+  if (!lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess ||
+        lds <= 0)
+      lds = 64 * 1024;
+  }
+  return (size_t)lds;
+}
+
 // Number of concurrently resident wavefronts of a narrow kernel.
-int narrow_slots(const NarrowEntry* e) {
+int narrow_slots(const NarrowEntry* e, size_t lds) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->path_kernel, 64, e->lds_bytes) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->path_kernel, 64, lds) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return per_cu * device_cus();
+}
+
+// Gram cache size (floats) for `count` problems of one configuration: the
+// LDS of a CU is shared by the wavefronts that must run on it at once.
+int gram_cap_for(const NarrowEntry* e, int count) {
+  const size_t per_cu = device_lds_per_cu();
+  const int cus = device_cus();
+  const int waves = std::max(1, (count + cus - 1) / cus);
+  const size_t budget = per_cu / waves;
+  if (budget <= e->lds_bytes + 4096) return 0;
+  size_t cap = (budget - e->lds_bytes - 1024) / sizeof(float);
+  cap = std::min<size_t>(cap, 1 << 20) & ~(size_t)63;
+  return (int)cap;
 }
 
 // Upload the lambdas of each problem into its workspace copy.
@@ -232,6 +308,11 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
   const NarrowEntry* ne = pick_narrow(pr);
   if (!w || !ne) return GS_EUNSUPPORTED;
   PathOpts po = path_opts(o, false);
+  // the CD kernel stages the active positions' coefficients in LDS
+  po.gram_cap = gram_cap_for(ne, 1);
+  const size_t cd_lds = ne->lds_bytes + sizeof(float) * (size_t)po.gram_cap;
+  HIPCHK(hipFuncSetAttribute(ne->cd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)cd_lds));
   WideState* st = sh.st;
   WideBufs wb = sh.wb;
   const int dt = pr->dtype;
@@ -258,7 +339,8 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
       void* ar[] = {&d, &st, &wb, &zero};
       HIPCHK(launch(kWideRefresh[dt], dim3(1), dim3(kRefreshThreads), ar, 0, s));
       void* as[] = {&d, &st, &wb, &zero};
-      HIPCHK(launch(w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), as, 0, s));
+      HIPCHK(timed_launch(kTimeSweep, w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), as,
+                          0, s));
       void* ag[] = {&d, &st, &wb, &nsweep, &zero, &nd, &nd, &nd, &po};
       HIPCHK(launch(kWideGap[dt], dim3(1), dim3(256), ag, 0, s));
       void* at[] = {&d, &st, &wb};
@@ -271,7 +353,7 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
       void* ar2[] = {&d, &st, &wb, &one};
       HIPCHK(launch(kWideRefresh[dt], dim3(1), dim3(kRefreshThreads), ar2, 0, s));
       void* acd[] = {&d, &st, &po};
-      HIPCHK(launch(ne->cd_kernel, dim3(1), dim3(64), acd, ne->lds_bytes, s));
+      HIPCHK(launch(ne->cd_kernel, dim3(1), dim3(64), acd, cd_lds, s));
     }
     enq += chunk;
     WideState hs;
@@ -354,7 +436,7 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   return GS_OK;
 }
 
-int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po,
+int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po, int cd_mode,
                   hipStream_t s) {
   HIPCHK(fill_i32(sh.queues, 0, 64, s));
   for (size_t g = 0; g < groups.size(); ++g) {
@@ -362,9 +444,14 @@ int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts p
     const ProbDesc* d = sh.descs + G.first;
     int B = G.count;
     int* q = sh.queues + g;
-    void* a[] = {&d, &B, &q, &po};
-    const int grid = std::max(1, std::min(G.count, narrow_slots(G.e)));
-    HIPCHK(launch(G.e->path_kernel, dim3(grid), dim3(64), a, G.e->lds_bytes, s));
+    PathOpts pg = po;
+    pg.gram_cap = cd_mode == GS_CD_RESIDUAL ? 0 : gram_cap_for(G.e, G.count);
+    const size_t lds = G.e->lds_bytes + sizeof(float) * (size_t)pg.gram_cap;
+    HIPCHK(hipFuncSetAttribute(G.e->path_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    void* a[] = {&d, &B, &q, &pg};
+    const int grid = std::max(1, std::min(G.count, narrow_slots(G.e, lds)));
+    HIPCHK(timed_launch(kTimePath, G.e->path_kernel, dim3(grid), dim3(64), a, lds, s));
   }
   return GS_OK;
 }
@@ -429,7 +516,7 @@ int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace, siz
   std::vector<Group> groups;
   rc = prepare_batch(prob, 1, opts, workspace, ws_bytes, s, &sh, &groups);
   if (rc) return rc;
-  return launch_groups(sh, groups, path_opts(opts, false), s);
+  return launch_groups(sh, groups, path_opts(opts, false), opts->cd_mode, s);
 }
 
 int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, void* workspace,
@@ -442,7 +529,7 @@ int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, v
   std::vector<Group> groups;
   int rc = prepare_batch(probs, B, opts, workspace, ws_bytes, s, &sh, &groups);
   if (rc) return rc;
-  return launch_groups(sh, groups, path_opts(opts, true), s);
+  return launch_groups(sh, groups, path_opts(opts, true), opts->cd_mode, s);
 }
 
 size_t screen_workspace_size(int32_t n, int32_t p) {
@@ -511,7 +598,8 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, cons
                                                           (kSweepWaves * kSweepU)));
   {
     void* a[] = {&d, &st, &wb, &one};
-    HIPCHK(launch(w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0, s));
+    HIPCHK(timed_launch(kTimeSweep, w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0,
+                        s));
   }
   {
     void* a[] = {&d, &st, &wb, &nsweep, &one, &gap_out, &alpha_out, &radius_out, &po};
@@ -531,6 +619,26 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, cons
     HIPCHK(launch(kWideFin, dim3(1), dim3(64), a, 0, s));
   }
   return GS_OK;
+}
+
+void gs_timing_enable(int on) { g_timing = on != 0; }
+
+void gs_timing_reset(void) {
+  resolve_timing();
+  g_total_ms[0] = g_total_ms[1] = 0.0;
+  g_launches[0] = g_launches[1] = 0;
+}
+
+int gs_timing_query(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel) return -1;
+  int slot = -1;
+  if (std::strcmp(kernel, "sweep") == 0) slot = kTimeSweep;
+  if (std::strcmp(kernel, "path") == 0) slot = kTimePath;
+  if (slot < 0) return -1;
+  resolve_timing();
+  if (total_ms) *total_ms = g_total_ms[slot];
+  if (launches) *launches = g_launches[slot];
+  return 0;
 }
 
 const char* lasso_strerror(int code) {

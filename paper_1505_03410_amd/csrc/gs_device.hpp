@@ -21,23 +21,80 @@ __device__ __forceinline__ double soft_thr(double u, double x) {
 }
 
 // ---- cross-lane reductions (wave64).  Butterflies give every lane of the
-// group the bitwise-same result (FP addition is commutative).
+// group the bitwise-same result (FP addition is commutative).  Lane exchange
+// uses DPP inside a row of 16 (quad_perm xor 1 and xor 2, half-row mirror,
+// row mirror: once a group of 2^k lanes holds one value, the mirror pairs it
+// with the neighbouring group) and the gfx950 permlane swaps across rows.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  return __hiloint2double(dpp_i<CTRL>(__double2hiint(v)), dpp_i<CTRL>(__double2loint(v)));
+}
+// Cross-row exchange: permlane16_swap (rows 2i <-> 2i+1) and permlane32_swap
+// (lower <-> upper half) applied to (v, v) return, in every lane, the pair
+// (value of the lower partner, value of the upper partner); combining a[0]
+// with a[1] therefore uses the same operand order in all lanes.
+__device__ __forceinline__ void swap16_d(double v, double& a, double& b) {
+  auto h = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  auto l = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  a = __hiloint2double((int)h[0], (int)l[0]);
+  b = __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ void swap32_d(double v, double& a, double& b) {
+  auto h = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  auto l = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  a = __hiloint2double((int)h[0], (int)l[0]);
+  b = __hiloint2double((int)h[1], (int)l[1]);
+}
+
 template <int S>
 __device__ __forceinline__ double seg_sum(double v) {
-#pragma unroll
-  for (int o = S / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if constexpr (S >= 2) v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  if constexpr (S >= 4) v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (S >= 8) v += dpp_d<0x141>(v);   // row_half_mirror
+  if constexpr (S >= 16) v += dpp_d<0x140>(v);  // row_mirror
+  if constexpr (S >= 32) {
+    double a, b;
+    swap16_d(v, a, b);
+    v = a + b;
+  }
+  if constexpr (S >= 64) {
+    double a, b;
+    swap32_d(v, a, b);
+    v = a + b;
+  }
   return v;
 }
 __device__ __forceinline__ double wave_sum(double v) { return seg_sum<64>(v); }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  double a, b;
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  swap16_d(v, a, b);
+  v = fmax(a, b);
+  swap32_d(v, a, b);
+  return fmax(a, b);
 }
 __device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_i<0xB1>(v);
+  v += dpp_i<0x4E>(v);
+  v += dpp_i<0x141>(v);
+  v += dpp_i<0x140>(v);
+  auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = (int)r[0] + (int)r[1];
+  auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (int)q[0] + (int)q[1];
+}
+// Orders LDS accesses of the lanes of one wavefront (LDS instructions of a
+// wave execute in issue order) without waiting for outstanding global loads.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -70,36 +127,59 @@ struct VecLoad<XT, 1> {
 
 // Lane layout of one column: lane (slot, seg), seg in [0,S), owns the rows
 // r = (seg + S*m)*VEC + e for m < NG, e < VEC.  With a row list (gather, VEC
-// must be 1) the row index comes from ridx[m].
+// must be 1) the row index comes from ridx[m].  Vector loads are only used
+// when n is a multiple of VEC, so a group is either wholly inside the column
+// or wholly outside it.
 template <typename XT, int VEC, int S, int NG, bool GATHER>
 struct ColLayout {
   static constexpr int RPL = NG * VEC;  // rows per lane
   static constexpr int C = 64 / S;      // columns per wavefront step
   static constexpr int NMAX = S * NG * VEC;
+  static_assert(RPL <= 64, "row mask holds 64 rows per lane");
 
   __device__ static __forceinline__ int row(int seg, int m, int e) {
     return (seg + S * m) * VEC + e;
   }
 
-  // Loads the lane's rows of column `col` (pointer to its first entry).
-  // Entries at rows >= n are 0; no entry beyond row n-1 is read.
-  __device__ static __forceinline__ void load(const XT* __restrict__ col, int n, int seg,
-                                              const int* ridx, XT (&xv)[RPL]) {
+  // Bit (m*VEC + e) is set when that row of the lane is < n.  Constant per
+  // lane: loads are issued unmasked and the mask is applied where the values
+  // are used, so that a prefetched load is not waited for early.
+  __device__ static __forceinline__ uint64_t rowmask(int seg, int n) {
+    uint64_t mk = 0;
+#pragma unroll
+    for (int m = 0; m < NG; ++m)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        if (row(seg, m, e) < n) mk |= 1ull << (m * VEC + e);
+    return mk;
+  }
+
+  // Issues the loads of the lane's rows of column `col`; groups beyond row
+  // n-1 read row 0 instead (their values are masked at use).  ridx holds the
+  // clamped source rows of a gather.
+  __device__ static __forceinline__ void load_raw(const XT* __restrict__ col, int n, int seg,
+                                                  const int* ridx, XT (&xv)[RPL]) {
 #pragma unroll
     for (int m = 0; m < NG; ++m) {
       if constexpr (GATHER) {
-        int r = ridx[m];
-        xv[m] = (r >= 0) ? col[r] : XT(0);
+        xv[m] = col[ridx[m]];
       } else {
         const int r0 = (seg + S * m) * VEC;
-        if (r0 + VEC <= n) {
-          VecLoad<XT, VEC>::go(col + r0, &xv[m * VEC]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) xv[m * VEC + e] = (r0 + e < n) ? col[r0 + e] : XT(0);
-        }
+        VecLoad<XT, VEC>::go(col + (r0 < n ? r0 : 0), &xv[m * VEC]);
       }
     }
+  }
+
+  __device__ static __forceinline__ double at(const XT (&xv)[RPL], uint64_t mk, int i) {
+    return ((mk >> i) & 1ull) ? (double)xv[i] : 0.0;
+  }
+
+  // Masked load (values usable at once).
+  __device__ static __forceinline__ void load(const XT* __restrict__ col, int n, int seg,
+                                              const int* ridx, uint64_t mk, XT (&xv)[RPL]) {
+    load_raw(col, n, seg, ridx, xv);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) xv[i] = ((mk >> i) & 1ull) ? xv[i] : XT(0);
   }
 };
 

@@ -1,12 +1,15 @@
 // Narrow-schedule kernel instantiations: float, 1-wide loads, row gather.
-// Ordered by capacity S*NG*VEC rows (32 ... 2048).
+// Ordered by capacity S*NG*VEC rows.
 #include "gs_narrow.hpp"
 #include "gs_registry.hpp"
 
 namespace gs {
 const NarrowEntry kNarrowF32G[] = {
     GS_NARROW_ENTRY(float, 1, 4, 8, true),
+    GS_NARROW_ENTRY(float, 1, 4, 9, true),
+    GS_NARROW_ENTRY(float, 1, 4, 12, true),
     GS_NARROW_ENTRY(float, 1, 4, 16, true),
+    GS_NARROW_ENTRY(float, 1, 4, 24, true),
     GS_NARROW_ENTRY(float, 1, 4, 32, true),
     GS_NARROW_ENTRY(float, 1, 16, 16, true),
     GS_NARROW_ENTRY(float, 1, 16, 32, true),

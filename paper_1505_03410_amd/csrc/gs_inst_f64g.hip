@@ -1,5 +1,5 @@
 // Narrow-schedule kernel instantiations: double, 1-wide loads, row gather.
-// Ordered by capacity S*NG*VEC rows (32 ... 2048).
+// Ordered by capacity S*NG*VEC rows.
 #include "gs_narrow.hpp"
 #include "gs_registry.hpp"
 

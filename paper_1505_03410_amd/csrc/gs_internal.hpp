@@ -26,6 +26,7 @@ struct ProbDesc {
   double* lambda_out;
   // workspace arrays of this problem
   double* nrm2;   // p: ||x_j||^2
+  double* inv;    // p: 1/||x_j||^2 (0 for a zero column)
   double* beta;   // p: working coefficients (FP64)
   double* c;      // p: x_j^T rho of the last sweep, indexed by position in A
   int32_t* act;   // 2p: active set (two buffers for the wide schedule)
@@ -38,6 +39,8 @@ struct ProbDesc {
 struct PathOpts {
   double eps_rel;
   int32_t f, K;
+  int32_t gram_cap;        // floats of LDS for the Gram cache (0: residual mode only)
+  int32_t pad_;
   int32_t* select_counts;  // T x p or null
   long long* timestamps;   // 2B or null
 };

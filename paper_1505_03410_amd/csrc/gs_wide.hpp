@@ -78,10 +78,11 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_pre(ProbDesc d, WideB
     }
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
+  const uint64_t mk = L::rowmask(lane, d.n);
   double mx = 0.0, bad = 0.0;
   for (int j = wid; j < d.p; j += W) {
     XT xv[RPL];
-    L::load(X + (int64_t)j * d.ldx, d.n, lane, nullptr, xv);
+    L::load(X + (int64_t)j * d.ldx, d.n, lane, nullptr, mk, xv);
     double s2 = 0.0, sy = 0.0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_pre(ProbDesc d, WideB
     sy = wave_sum(sy);
     if (lane == 0) {
       d.nrm2[j] = s2;
+      d.inv[j] = s2 > 0.0 ? 1.0 / s2 : 0.0;
       mx = fmax(mx, fabs(sy));
       if (!isfinite(s2) || !isfinite(sy)) bad = 1.0;
     }
@@ -260,35 +262,33 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
     }
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
+  const uint64_t mk = L::rowmask(lane, d.n);
   double Ml = 0.0, l1 = 0.0, sb = 0.0, xm = 0.0;
   for (int base = wid * kSweepU; base < q; base += W * kSweepU) {
     XT xv[kSweepU][RPL];
     int jj[kSweepU];
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
-      int k = base + u;
-      jj[u] = (k < q) ? (full ? k : act[k]) : -1;
+      const int k = base + u < q ? base + u : q - 1;
+      jj[u] = full ? k : act[k];
     }
 #pragma unroll
-    for (int u = 0; u < kSweepU; ++u) {
-      if (jj[u] >= 0) {
-        L::load(X + (int64_t)jj[u] * d.ldx, d.n, lane, nullptr, xv[u]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) xv[u][i] = XT(0);
-      }
-    }
+    for (int u = 0; u < kSweepU; ++u)
+      L::load_raw(X + (int64_t)jj[u] * d.ldx, d.n, lane, nullptr, xv[u]);
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
       double a = 0.0, s2 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        a = fma((double)xv[u][i], r[i], a);
-        if (with_nrm2) s2 = fma((double)xv[u][i], (double)xv[u][i], s2);
+        a = fma((double)xv[u][i], r[i], a);  // r is zero at rows >= n
+        if (with_nrm2) {
+          const double xi = L::at(xv[u], mk, i);
+          s2 = fma(xi, xi, s2);
+        }
       }
       a = wave_sum(a);
       if (with_nrm2) s2 = wave_sum(s2);
-      if (jj[u] >= 0 && lane == 0) {
+      if (base + u < q && lane == 0) {
         const int j = jj[u];
         d.c[base + u] = a;
         if (with_nrm2) d.nrm2[j] = s2;

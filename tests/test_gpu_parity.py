@@ -179,25 +179,27 @@ def _check_path(X, y, got, orc, lambdas, eps_rel=1e-8, tight=None, beta_tol=None
     return worst
 
 
-def test_path_c0_f64(torch, orc):
+@pytest.mark.parametrize("cd_mode", ["auto", "residual"])
+def test_path_c0_f64(torch, orc, cd_mode):
     d = synth.c0()
     X, y = d["X"], d["y"]
     lmax = orc.precompute(X, y)["lambda_max"]
     lams = [lmax, lmax * d["lambda_ratio"]]
     Xd, yd = _dev(torch, X, y, 2)
-    got = gs.lasso_path(Xd, yd, lambdas=lams)
+    got = gs.lasso_path(Xd, yd, lambdas=lams, cd_mode=cd_mode)
     torch.cuda.synchronize()
     _check_path(X, y, got, orc, lams, beta_tol=1e-5)
     assert int(_np(got["epochs"])[0]) == 0
     assert np.all(_np(got["beta"])[0] == 0)
 
 
-def test_path_c1_full(torch, orc):
+@pytest.mark.parametrize("cd_mode", ["auto", "residual"])
+def test_path_c1_full(torch, orc, cd_mode):
     """The benchmark workload: 72 x 7129 FP32, 100 lambdas, delta = 3."""
     d = synth.c1()
     X, y = d["X"], d["y"]
     Xd, yd = _dev(torch, X, y)
-    got = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3)
+    got = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3, cd_mode=cd_mode)
     torch.cuda.synchronize()
     lams = _np(got["lambdas"])
     ref = orc.grid(orc.precompute(X, y)["lambda_max"], 100, 3.0)
@@ -217,13 +219,15 @@ def test_path_wide_matches(torch, orc):
     _check_path(X, y, got, orc, _np(got["lambdas"]))
 
 
-def test_path_large_n_configs(torch, orc):
-    """Rows spread over 16 and 64 lanes (n = 300 and n = 1000)."""
-    for n, p in [(300, 800), (1000, 600)]:
+@pytest.mark.parametrize("cd_mode", ["auto", "residual"])
+def test_path_large_n_configs(torch, orc, cd_mode):
+    """Rows spread over 16 and 64 lanes (n = 300 and n = 1000), and a ragged
+    n with scalar loads."""
+    for n, p in [(300, 800), (1000, 600), (203, 500)]:
         d = synth.gaussian(n + p, n, p, k=20, sigma=0.5)
         X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
         Xd, yd = _dev(torch, X, y)
-        got = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.01)
+        got = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.01, cd_mode=cd_mode)
         torch.cuda.synchronize()
         _check_path(X, y, got, orc, _np(got["lambdas"]))
 

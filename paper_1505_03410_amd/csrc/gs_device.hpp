@@ -11,6 +11,18 @@ namespace gs {
 
 constexpr double kU = 1.1102230246251565e-16;  // unit roundoff of FP64, 2^-53
 
+// A pointer read out of device memory (a problem descriptor) is generic to
+// the compiler, which then emits flat instructions; those count against the
+// LDS wait counter as well, so an LDS wait would also drain every prefetched
+// global load.  Pointers typed in the global address space (gbl<T>*) make
+// the compiler emit global_load/global_store instead.
+template <typename T>
+using gbl = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gbl<T>* gptr(T* p) {
+  return (gbl<T>*)p;
+}
+
 // Higham's gamma_m = m u / (1 - m u): relative error bound of an m-term sum
 // or dot product in FP64.
 __device__ __forceinline__ double gam(double m) { return m * kU / (1.0 - m * kU); }
@@ -112,6 +124,11 @@ struct VecLoad<float, 4> {
     float4 v = *reinterpret_cast<const float4*>(p);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
+  __device__ static void go(const gbl<float>* p, float* o) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const gbl<v4>*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
 };
 template <>
 struct VecLoad<double, 2> {
@@ -119,10 +136,16 @@ struct VecLoad<double, 2> {
     double2 v = *reinterpret_cast<const double2*>(p);
     o[0] = v.x; o[1] = v.y;
   }
+  __device__ static void go(const gbl<double>* p, double* o) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *reinterpret_cast<const gbl<v2>*>(p);
+    o[0] = v.x; o[1] = v.y;
+  }
 };
 template <typename XT>
 struct VecLoad<XT, 1> {
   __device__ static void go(const XT* p, XT* o) { o[0] = p[0]; }
+  __device__ static void go(const gbl<XT>* p, XT* o) { o[0] = p[0]; }
 };
 
 // Lane layout of one column: lane (slot, seg), seg in [0,S), owns the rows
@@ -157,8 +180,9 @@ struct ColLayout {
   // Issues the loads of the lane's rows of column `col`; groups beyond row
   // n-1 read row 0 instead (their values are masked at use).  ridx holds the
   // clamped source rows of a gather.
-  __device__ static __forceinline__ void load_raw(const XT* __restrict__ col, int n, int seg,
-                                                  const int* ridx, XT (&xv)[RPL]) {
+  template <typename P>
+  __device__ static __forceinline__ void load_raw(P col, int n, int seg, const int* ridx,
+                                                  XT (&xv)[RPL]) {
 #pragma unroll
     for (int m = 0; m < NG; ++m) {
       if constexpr (GATHER) {
@@ -175,8 +199,9 @@ struct ColLayout {
   }
 
   // Masked load (values usable at once).
-  __device__ static __forceinline__ void load(const XT* __restrict__ col, int n, int seg,
-                                              const int* ridx, uint64_t mk, XT (&xv)[RPL]) {
+  template <typename P>
+  __device__ static __forceinline__ void load(P col, int n, int seg, const int* ridx,
+                                              uint64_t mk, XT (&xv)[RPL]) {
     load_raw(col, n, seg, ridx, xv);
 #pragma unroll
     for (int i = 0; i < RPL; ++i) xv[i] = ((mk >> i) & 1ull) ? xv[i] : XT(0);

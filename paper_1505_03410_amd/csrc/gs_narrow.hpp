@@ -55,7 +55,7 @@ struct Narrow {
 
   // Per-wave context.
   struct Ctx {
-    const XT* X;
+    const gbl<XT>* X;
     int64_t ldx;
     int n, p;
     int lane, slot, seg;
@@ -65,11 +65,11 @@ struct Narrow {
     double* rho_l;              // LDS, n
     XT* tile;                   // LDS, 64 * RPL
     int* rows_l;                // LDS, n (gather)
-    double* nrm2;
-    double* inv;                // 1/||x_j||^2 (0 for a zero column)
-    double* beta;
-    double* c;
-    int32_t* act;
+    gbl<double>* nrm2;
+    gbl<double>* inv;           // 1/||x_j||^2 (0 for a zero column)
+    gbl<double>* beta;
+    gbl<double>* c;
+    gbl<int32_t>* act;
   };
 
   // LDS state shared by the two modes.  The region `G` holds either the Gram
@@ -94,7 +94,7 @@ struct Narrow {
     bool v;
   };
 
-  static __device__ __forceinline__ const XT* col(const Ctx& x, int j) {
+  static __device__ __forceinline__ const gbl<XT>* col(const Ctx& x, int j) {
     return x.X + (int64_t)j * x.ldx;
   }
   static __device__ __forceinline__ int src_row(const Ctx& x, int i) {
@@ -102,7 +102,7 @@ struct Narrow {
     return i;
   }
 
-  static __device__ __forceinline__ void setup(Ctx& x, const int32_t* rows) {
+  static __device__ __forceinline__ void setup(Ctx& x, const gbl<int32_t>* rows) {
     x.mk = L::rowmask(x.seg, x.n);
     if constexpr (GATHER) {
       for (int i = x.lane; i < x.n; i += 64) x.rows_l[i] = rows[i];
@@ -520,7 +520,7 @@ struct Narrow {
                                                   bool full,
                                    int& evicted) {
     const int j = __builtin_amdgcn_readfirstlane(full ? pos : x.act[pos]);
-    const XT* cj = col(x, j);
+    const gbl<XT>* cj = col(x, j);
     for (int i = x.lane; i < x.n; i += 64) gm.xj[i] = cj[src_row(x, i)];
     const int s = gm.victim;
     gm.victim = (gm.victim + 1 < gm.ns) ? gm.victim + 1 : 0;
@@ -529,7 +529,7 @@ struct Narrow {
     if (x.lane == 0) gm.owner[s] = pos;
     float* Gc = gm.G + s * q;
     for (int k = x.lane; k < q; k += 64) {
-      const XT* ck = col(x, full ? k : x.act[k]);
+      const gbl<XT>* ck = col(x, full ? k : x.act[k]);
       double a0 = 0.0, a1 = 0.0;
       if constexpr (GATHER || VEC == 1) {
         for (int i = 0; i < x.n; ++i) a0 = fma((double)ck[src_row(x, i)], (double)gm.xj[i], a0);
@@ -657,16 +657,18 @@ struct Narrow {
   }
 };
 
-// LDS bytes the narrow kernel needs besides the Gram cache region (whose
-// size in floats is a launch argument, PathOpts::gram_cap).
+// LDS bytes the narrow kernel needs before the Gram cache region (whose
+// size in floats is a launch argument, PathOpts::gram_cap); the region
+// starts 16-byte aligned at this offset.
 template <typename XT, int VEC, int S, int NG, bool GATHER>
 constexpr size_t narrow_lds_bytes() {
   using N = Narrow<XT, VEC, S, NG, GATHER>;
-  return 2 * sizeof(double) * N::NMAX + sizeof(XT) * 64 * N::RPL + sizeof(int) * N::NMAX +
-         sizeof(XT) * N::NMAX + 2 * sizeof(int) * N::QG + sizeof(int) * N::NSMAX + 16;
+  return (2 * sizeof(double) * N::NMAX + sizeof(XT) * 64 * N::RPL + sizeof(int) * N::NMAX +
+          sizeof(XT) * N::NMAX + 2 * sizeof(int) * N::QG + sizeof(int) * N::NSMAX + 15) &
+         ~(size_t)15;
 }
 
-template <typename N, typename XT>
+template <typename N, typename XT, size_t GOFF>
 __device__ __forceinline__ void bind_lds(typename N::Ctx& x, typename N::Gram& gm,
                                          unsigned char* smem, int gram_cap) {
   x.y_l = reinterpret_cast<double*>(smem);
@@ -678,8 +680,7 @@ __device__ __forceinline__ void bind_lds(typename N::Ctx& x, typename N::Gram& g
   gm.np = gm.slot + N::QG;
   gm.owner = gm.np + N::QG;
   // 16-byte aligned: the region also holds doubles in residual mode
-  gm.G = reinterpret_cast<float*>(
-      (reinterpret_cast<uintptr_t>(gm.owner + N::NSMAX) + 15) & ~(uintptr_t)15);
+  gm.G = reinterpret_cast<float*>(smem + GOFF);
   gm.cap = gram_cap;
   gm.ns = 0;
   gm.victim = 0;
@@ -701,25 +702,27 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     if (task >= B) break;
     const ProbDesc d = descs[task];
     long long t_start = wall_clock64();
+    gbl<double>* lam_g = gptr(d.lam);
+    gbl<double>* bout_g = gptr(d.beta_out);
 
     typename N::Ctx x;
     typename N::Gram gm;
-    x.X = (const XT*)d.X;
+    x.X = gptr((const XT*)d.X);
     x.ldx = d.ldx;
     x.n = d.n;
     x.p = d.p;
     x.lane = lane;
     x.slot = lane / S;
     x.seg = lane % S;
-    bind_lds<N, XT>(x, gm, smem, opts.gram_cap);
-    x.nrm2 = d.nrm2;
-    x.inv = d.inv;
-    x.beta = d.beta;
-    x.c = d.c;
-    x.act = d.act;
-    N::setup(x, d.rows);
+    bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, gm, smem, opts.gram_cap);
+    x.nrm2 = gptr(d.nrm2);
+    x.inv = gptr(d.inv);
+    x.beta = gptr(d.beta);
+    x.c = gptr(d.c);
+    x.act = gptr(d.act);
+    N::setup(x, gptr(d.rows));
     const int n = d.n, p = d.p, T = d.T;
-    const XT* Y = (const XT*)d.y;
+    const gbl<XT>* Y = gptr((const XT*)d.y);
 
     // ---- y into LDS; precompute ||x_j||^2 and lambda_max = ||X^T y||_inf
     double yy = 0.0;
@@ -771,18 +774,21 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     for (int t = lane; t < T; t += 64) {
       double lam;
       if (d.has_lambdas)
-        lam = d.lam[t] * (d.lambda_relative ? lmax : 1.0);
+        lam = lam_g[t] * (d.lambda_relative ? lmax : 1.0);
       else
         lam = (T == 1) ? lmax : lmax * pow(d.lambda_min_ratio, (double)t / (double)(T - 1));
-      d.lam[t] = lam;
-      if (d.lambda_out) d.lambda_out[t] = lam;
+      lam_g[t] = lam;
+      if (d.lambda_out) gptr(d.lambda_out)[t] = lam;
     }
-    for (int j = lane; j < p; j += 64) x.beta[j] = (d.beta_init && !bad) ? d.beta_init[j] : 0.0;
+    {
+      const gbl<const double>* bi = gptr(d.beta_init);
+      for (int j = lane; j < p; j += 64) x.beta[j] = (bi && !bad) ? bi[j] : 0.0;
+    }
     __threadfence_block();
 
     if (bad) {
       for (int t = 0; t < T; ++t) {
-        for (int j = lane; j < p; j += 64) d.beta_out[(int64_t)t * p + j] = 0.0;
+        for (int j = lane; j < p; j += 64) bout_g[(int64_t)t * p + j] = 0.0;
         if (lane == 0) {
           d.gap_out[t] = NAN;
           d.epochs_out[t] = 0;
@@ -795,7 +801,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
       const double ynorm = sqrt(ynorm2);
       const int f = opts.f, K = opts.K;
       for (int t = 0; t < T; ++t) {
-        const double lambda = d.lam[t];
+        const double lambda = lam_g[t];
         int q = p;
         bool full = true;
         int k = 0, status = 1;
@@ -849,7 +855,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
           k += ne;
         }
         // beta^{lambda_t} and its certificate
-        double* bo = d.beta_out + (int64_t)t * p;
+        gbl<double>* bo = bout_g + (int64_t)t * p;
         for (int j = lane; j < p; j += 64) {
           double b = x.beta[j];
           bo[j] = b;
@@ -881,27 +887,27 @@ __global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathO
   const int lane = threadIdx.x;
   typename N::Ctx x;
   typename N::Gram gm;
-  x.X = (const XT*)d.X;
+  x.X = gptr((const XT*)d.X);
   x.ldx = d.ldx;
   x.n = d.n;
   x.p = d.p;
   x.lane = lane;
   x.slot = lane / S;
   x.seg = lane % S;
-  bind_lds<N, XT>(x, gm, smem, opts.gram_cap);
-  x.nrm2 = d.nrm2;
-  x.inv = d.inv;
-  x.beta = d.beta;
-  x.c = d.c;
-  x.act = d.act + (int64_t)st->cur * d.p;
-  N::setup(x, d.rows);
-  for (int i = lane; i < d.n; i += 64) x.rho_l[i] = d.rho[i];
+  bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, gm, smem, opts.gram_cap);
+  x.nrm2 = gptr(d.nrm2);
+  x.inv = gptr(d.inv);
+  x.beta = gptr(d.beta);
+  x.c = gptr(d.c);
+  x.act = gptr(d.act) + (int64_t)st->cur * d.p;
+  N::setup(x, gptr(d.rows));
+  for (int i = lane; i < d.n; i += 64) x.rho_l[i] = gptr(d.rho)[i];
   wave_lds_order();
   const int q = st->q;
   const bool full = st->full != 0;
   const int k0 = st->k;
   const int ne = min(opts.f, opts.K - k0);
-  const double lambda = d.lam[st->t];
+  const double lambda = gptr(d.lam)[st->t];
   N::cd_epochs(x, gm, q, full, lambda, ne, 0);
   if (lane == 0) {
     st->k = k0 + ne;

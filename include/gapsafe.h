@@ -79,12 +79,30 @@ enum {
 };
 
 /* CD epoch modes of the narrow schedule (gs_opts.cd_mode).  Both run the
- * same cyclic coordinate descent; they differ in what is kept on chip. */
+ * same cyclic coordinate descent (Algorithm 1) and make the same updates up
+ * to the order of rounding. */
 enum {
-  GS_CD_AUTO = 0,     /* correlation (Gram) updates in LDS when the active set
-                         has at most 1024 coordinates and the LDS cache holds
-                         at least 8 columns of it; residual updates otherwise */
+  GS_CD_AUTO = 0,     /* pattern mode: while no coefficient changes sign or
+                         leaves/reaches zero, a whole epoch is one triangular
+                         solve on the support plus a Gram update of the
+                         correlations, checked exactly against that premise;
+                         an epoch that fails the check runs in residual mode */
   GS_CD_RESIDUAL = 1  /* residual updates only (rho in registers and LDS)    */
+};
+
+/* Counters of gs_opts.stats (indices). */
+enum {
+  GS_STAT_PATTERN_EPOCHS = 0, /* epochs committed by the pattern mode         */
+  GS_STAT_RESIDUAL_EPOCHS,    /* epochs run by the residual mode              */
+  GS_STAT_REJECTED,           /* pattern epochs rejected by the check         */
+  GS_STAT_BUILDS,             /* Gram columns computed                        */
+  GS_STAT_SETUPS,             /* pattern set-ups                              */
+  GS_STAT_SUPPORT_CHANGES,    /* set-ups whose support features changed     */
+  GS_STAT_PASSES,             /* screening passes                             */
+  GS_STAT_SKIPPED,            /* epochs skipped at an exact fixed point       */
+  GS_STAT_EXACT,              /* pattern epochs whose zero coordinates needed
+                                 the exact check (the norm bound did not hold) */
+  GS_NSTATS
 };
 
 /* One Lasso path (Algorithm 1 inputs X, y and the lambda grid). */
@@ -134,6 +152,9 @@ typedef struct gs_opts {
   int64_t* timestamps;   /* [device] optional (batch only): 2*B values, start
                             and end of each problem in device wall-clock
                             ticks (see gs_wallclock_hz)                      */
+  int64_t* stats;        /* [device] optional: GS_NSTATS counters of the
+                            narrow schedule, incremented (atomically) by the
+                            call; the caller zeroes them                     */
 } gs_opts;
 
 /* Fill *o with the defaults above. */

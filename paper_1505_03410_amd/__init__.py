@@ -56,8 +56,13 @@ class gs_opts(ctypes.Structure):
         ("max_epochs", ctypes.c_int32), ("schedule", ctypes.c_int32),
         ("cd_mode", ctypes.c_int32),
         ("select_counts", ctypes.c_void_p), ("timestamps", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
     ]
 
+
+# Names of the GS_NSTATS counters of gs_opts.stats, in index order.
+STAT_NAMES = ["pattern_epochs", "residual_epochs", "rejected", "builds", "setups",
+              "support_changes", "passes", "skipped", "exact_checks"]
 
 EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
            "lasso_solve_batch", "screen_workspace_size", "screen", "gs_timing_enable",
@@ -220,7 +225,7 @@ def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, o
 
 
 def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, timestamps=None,
-          cd_mode="auto"):
+          cd_mode="auto", stats=None):
     o = gs_opts()
     load_library().gs_opts_default(ctypes.byref(o))
     o.eps_rel = float(eps_rel)
@@ -230,6 +235,11 @@ def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, times
     o.cd_mode = CD_MODES[cd_mode] if isinstance(cd_mode, str) else int(cd_mode)
     o.select_counts = None if select_counts is None else select_counts.data_ptr()
     o.timestamps = None if timestamps is None else timestamps.data_ptr()
+    if stats is not None:
+        torch = _torch()
+        if stats.dtype != torch.int64 or stats.numel() < len(STAT_NAMES) or not stats.is_contiguous():
+            raise ValueError("stats must be a contiguous int64 tensor of %d counters" % len(STAT_NAMES))
+        o.stats = stats.data_ptr()
     return o
 
 
@@ -246,7 +256,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
                relative: bool = False, lambda_min_ratio: float = 1e-3, beta_init=None,
                rows=None, eps_rel: float = 1e-8, screen_every: int = 10,
                max_epochs: int = 100000, schedule="auto", cd_mode="auto", stream=None,
-               out=None, workspace=None):
+               out=None, workspace=None, stats=None):
     """Algorithm 1 on the device for one problem; see include/gapsafe.h.
     Returns a PathResult of device tensors (valid after the stream syncs) with
     an extra ``rc`` entry (GS_OK or GS_NOT_CONVERGED)."""
@@ -254,7 +264,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
     pr, out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
                               lambda_min_ratio=lambda_min_ratio, beta_init=beta_init,
                               rows=rows, out=out)
-    o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode)
+    o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode, stats=stats)
     need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
     rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))
@@ -266,7 +276,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
 
 def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10,
                       max_epochs: int = 100000, select_counts=None, timestamps=None,
-                      cd_mode="auto", stream=None, workspace=None):
+                      cd_mode="auto", stream=None, workspace=None, stats=None):
     """Many paths in one persistent launch.  ``problems`` is a list of dicts
     with keys X, y and optionally T, lambdas, relative, lambda_min_ratio,
     beta_init, rows.  Returns the list of PathResults."""
@@ -283,7 +293,8 @@ def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10
         arr[b] = pr
         outs.append(out)
         keep.append(hl)
-    o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps, cd_mode)
+    o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps, cd_mode,
+              stats)
     need = lib.lasso_workspace_size(arr, B, ctypes.byref(o))
     dev = problems[0]["X"].device
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)

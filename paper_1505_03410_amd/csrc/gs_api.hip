@@ -132,15 +132,36 @@ bool use_wide(const gs_problem* pr, const gs_opts* o) {
 }
 
 // Per-problem workspace arrays.
+// Gram slots of the pattern mode: a Lasso solution has at most n nonzeros in
+// general position; the margin covers transient supports.
+int pattern_slots(const gs_problem* pr) {
+  const int want = (pr->n + 7) / 8 * 8 + 16;
+  return std::max(1, std::min({kSlotsMax, pr->p, want}));
+}
+
+// Per-problem workspace arrays.  The pattern mode's feature-indexed arrays
+// hold ldg entries (p rounded up to 64).
 void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
+  const int64_t ldg = (int64_t)align_up((size_t)pr->p, 64);
+  const int ns = pattern_slots(pr);
   d->nrm2 = cv.take<double>(pr->p);
   d->inv = cv.take<double>(pr->p);
   d->beta = cv.take<double>(pr->p);
-  d->c = cv.take<double>(pr->p);
+  d->c = cv.take<double>(ldg);
   d->act = cv.take<int32_t>(2 * (size_t)pr->p);
   d->lam = cv.take<double>(pr->T);
   d->rho = cv.take<double>(pr->n);
+  d->gc = cv.take<float>((size_t)ns * ldg);
+  d->ng = cv.take<float>(ldg);
+  d->pslot = cv.take<int32_t>(ldg);
+  d->psup = cv.take<int32_t>(ldg);
+  d->c2 = cv.take<double>(ldg);
+  d->ldg = ldg;
+  d->ns = ns;
 }
+
+// LDS floats of the support's Gram block: ns columns of stride 64 or 128.
+int gs_floats(int ns) { return ns * (ns > 64 ? 128 : 64); }
 
 struct Shared {
   ProbDesc* descs;
@@ -179,7 +200,6 @@ void fill_desc(const gs_problem* pr, int orig, ProbDesc* d) {
   d->status_out = pr->status_out;
   d->lambda_out = pr->lambda_out;
   d->orig = orig;
-  d->pad_ = 0;
 }
 
 PathOpts path_opts(const gs_opts* o, bool batch) {
@@ -187,10 +207,13 @@ PathOpts path_opts(const gs_opts* o, bool batch) {
   po.eps_rel = o->eps_rel;
   po.f = o->screen_every;
   po.K = o->max_epochs;
-  po.gram_cap = 0;
+  po.lds_cap = 0;
+  po.pattern = o->cd_mode == GS_CD_RESIDUAL ? 0 : 1;
+  po.gs_cap = 0;
   po.pad_ = 0;
   po.select_counts = batch ? o->select_counts : nullptr;
   po.timestamps = batch ? reinterpret_cast<long long*>(o->timestamps) : nullptr;
+  po.stats = reinterpret_cast<long long*>(o->stats);
   return po;
 }
 
@@ -281,15 +304,17 @@ int narrow_slots(const NarrowEntry* e, size_t lds) {
   return per_cu * device_cus();
 }
 
-// Gram cache size (floats) for `count` problems of one configuration: the
-// LDS of a CU is shared by the wavefronts that must run on it at once.
-int gram_cap_for(const NarrowEntry* e, int count) {
+// Size (floats) of the residual mode's LDS staging region for `count`
+// problems of one configuration: the LDS of a CU is shared by the wavefronts
+// that must run on it at once.
+int lds_cap_for(const NarrowEntry* e, int count, int gs) {
   const size_t per_cu = device_lds_per_cu();
   const int cus = device_cus();
   const int waves = std::max(1, (count + cus - 1) / cus);
   const size_t budget = per_cu / waves;
-  if (budget <= e->lds_bytes + 4096) return 0;
-  size_t cap = (budget - e->lds_bytes - 1024) / sizeof(float);
+  const size_t fixed = e->lds_bytes + sizeof(float) * (size_t)gs;
+  if (budget <= fixed + 4096) return 0;
+  size_t cap = (budget - fixed - 1024) / sizeof(float);
   cap = std::min<size_t>(cap, 1 << 20) & ~(size_t)63;
   return (int)cap;
 }
@@ -309,8 +334,8 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
   if (!w || !ne) return GS_EUNSUPPORTED;
   PathOpts po = path_opts(o, false);
   // the CD kernel stages the active positions' coefficients in LDS
-  po.gram_cap = gram_cap_for(ne, 1);
-  const size_t cd_lds = ne->lds_bytes + sizeof(float) * (size_t)po.gram_cap;
+  po.lds_cap = lds_cap_for(ne, 1, 0);
+  const size_t cd_lds = ne->lds_bytes + sizeof(float) * (size_t)po.lds_cap;
   HIPCHK(hipFuncSetAttribute(ne->cd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)cd_lds));
   WideState* st = sh.st;
@@ -385,6 +410,7 @@ size_t path_ws(const gs_problem* probs, int B) {
 struct Group {
   const NarrowEntry* e;
   int first, count;
+  int gs;  // LDS floats of the largest support Gram block in the group
 };
 
 int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, size_t ws_bytes,
@@ -428,15 +454,16 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   for (int i = 0; i < B; ++i) {
     sorted[i] = descs[order[i]];
     const NarrowEntry* e = cfg[order[i]];
-    if (groups->empty() || groups->back().e != e) groups->push_back({e, i, 0});
+    if (groups->empty() || groups->back().e != e) groups->push_back({e, i, 0, 0});
     groups->back().count++;
+    groups->back().gs = std::max(groups->back().gs, gs_floats(sorted[i].ns));
   }
   if ((int)groups->size() > 63) return GS_EUNSUPPORTED;
   HIPCHK(hipMemcpyAsync(sh->descs, sorted.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice, s));
   return GS_OK;
 }
 
-int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po, int cd_mode,
+int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po,
                   hipStream_t s) {
   HIPCHK(fill_i32(sh.queues, 0, 64, s));
   for (size_t g = 0; g < groups.size(); ++g) {
@@ -445,8 +472,16 @@ int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts p
     int B = G.count;
     int* q = sh.queues + g;
     PathOpts pg = po;
-    pg.gram_cap = cd_mode == GS_CD_RESIDUAL ? 0 : gram_cap_for(G.e, G.count);
-    const size_t lds = G.e->lds_bytes + sizeof(float) * (size_t)pg.gram_cap;
+    // the support's Gram block first (when the CU's share holds it), then
+    // the residual mode's staging region
+    const size_t per_wave = device_lds_per_cu() /
+                            std::max(1, (G.count + device_cus() - 1) / device_cus());
+    pg.gs_cap = (po.pattern && G.e->lds_bytes + sizeof(float) * (size_t)G.gs + 1024 <= per_wave)
+                    ? G.gs
+                    : 0;
+    pg.lds_cap = lds_cap_for(G.e, G.count, pg.gs_cap);
+    const size_t lds =
+        G.e->lds_bytes + sizeof(float) * ((size_t)pg.gs_cap + (size_t)pg.lds_cap);
     HIPCHK(hipFuncSetAttribute(G.e->path_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     void* a[] = {&d, &B, &q, &pg};
@@ -516,7 +551,7 @@ int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace, siz
   std::vector<Group> groups;
   rc = prepare_batch(prob, 1, opts, workspace, ws_bytes, s, &sh, &groups);
   if (rc) return rc;
-  return launch_groups(sh, groups, path_opts(opts, false), opts->cd_mode, s);
+  return launch_groups(sh, groups, path_opts(opts, false), s);
 }
 
 int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, void* workspace,
@@ -529,7 +564,7 @@ int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, v
   std::vector<Group> groups;
   int rc = prepare_batch(probs, B, opts, workspace, ws_bytes, s, &sh, &groups);
   if (rc) return rc;
-  return launch_groups(sh, groups, path_opts(opts, true), opts->cd_mode, s);
+  return launch_groups(sh, groups, path_opts(opts, true), s);
 }
 
 size_t screen_workspace_size(int32_t n, int32_t p) {

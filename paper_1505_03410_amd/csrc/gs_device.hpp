@@ -92,6 +92,7 @@ __device__ __forceinline__ double wave_max(double v) {
   swap32_d(v, a, b);
   return fmax(a, b);
 }
+__device__ __forceinline__ double wave_min(double v) { return -wave_max(-v); }
 __device__ __forceinline__ int wave_sum_i(int v) {
   v += dpp_i<0xB1>(v);
   v += dpp_i<0x4E>(v);

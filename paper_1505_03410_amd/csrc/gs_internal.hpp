@@ -32,17 +32,45 @@ struct ProbDesc {
   int32_t* act;   // 2p: active set (two buffers for the wide schedule)
   double* lam;    // T: lambdas (caller values on entry, absolute after init)
   double* rho;    // n: residual (wide schedule)
-  int32_t orig;   // index of the problem in the caller's array
-  int32_t pad_;
+  // pattern mode of the narrow schedule; the feature-indexed arrays hold ldg
+  // entries
+  float* gc;        // ns x ldg: Gram columns by slot, row j = feature j
+  float* ng;        // ldg: ||G_{j,S}||_2 of the zero coordinates of A
+  int32_t* pslot;   // ldg: slot holding the Gram column of feature j, or -1
+  int32_t* psup;    // ldg: index of feature j in the support list, or -1
+  double* c2;       // ldg: second buffer of the correlations c (by position)
+  int64_t ldg;      // p rounded up to a multiple of 64
+  int32_t ns;       // Gram slots of this problem (<= kSlotsMax)
+  int32_t orig;     // index of the problem in the caller's array
+};
+
+// Largest number of Gram slots of one problem (and so the largest support
+// handled by the pattern mode).
+constexpr int kSlotsMax = 128;
+// Counters of gs_opts.stats.
+enum {
+  kStatPatternEpochs = 0,  // epochs committed by the pattern mode
+  kStatResidualEpochs,     // epochs run by the residual mode
+  kStatRejected,           // pattern epochs rejected (re-run in residual mode)
+  kStatBuilds,             // Gram columns computed
+  kStatSetups,             // pattern set-ups
+  kStatSupportChanges,     // set-ups whose support features changed
+  kStatPasses,             // screening passes
+  kStatSkipped,            // epochs skipped at an exact fixed point
+  kStatExact,              // pattern epochs that needed the exact zero-coordinate check
+  kNumStats
 };
 
 struct PathOpts {
   double eps_rel;
   int32_t f, K;
-  int32_t gram_cap;        // floats of LDS for the Gram cache (0: residual mode only)
+  int32_t lds_cap;         // floats of LDS for staging the active coefficients
+  int32_t pattern;         // 1: pattern mode allowed, 0: residual mode only
+  int32_t gs_cap;          // floats of LDS for the support's Gram block
   int32_t pad_;
   int32_t* select_counts;  // T x p or null
   long long* timestamps;   // 2B or null
+  long long* stats;        // kNumStats or null
 };
 
 // Scalars of the wide schedule's state machine (one problem).

@@ -7,8 +7,29 @@
 // dot product is a per-lane FMA chain followed by a butterfly over S lanes.
 //
 // The epochs between two screening passes run in one of two modes; both are
-// cyclic CD over the active set A in ascending order and make the same
-// updates in exact arithmetic:
+// cyclic CD over the active set A in ascending order (Algorithm 1) and make
+// the same updates up to the order of rounding:
+//
+//  * pattern mode.  Let S be the positions of A whose coefficient is nonzero
+//    (s of them, ascending), sigma their signs and g = X_A^T rho the
+//    correlations at the start of an epoch.  As long as no coordinate of S
+//    changes sign or reaches zero and no other coordinate leaves zero, the
+//    epoch is a linear map: its steps delta solve
+//        (D + L) delta = g_S - lambda sigma,
+//    with D + L the diagonal and lower part of the Gram matrix G_SS in the
+//    cyclic order, and a zero coordinate k is visited with the correlation
+//    g_k - sum_{m in S before k} G_km delta_m.  The mode solves the system by
+//    forward substitution, then checks the premise exactly: the signs of
+//    beta_S + delta, and |g_k| + sum_m |G_km delta_m| <= lambda for every zero
+//    coordinate (a bound on its correlation at its visit, so that it stays
+//    at zero).  If both hold, the result is the cyclic epoch's and it is
+//    committed (beta_S += delta, g -= G_{A,S} delta); otherwise nothing is
+//    written and the residual mode runs that epoch.  The Gram columns of S
+//    over A sit in a global (L2-resident) cache indexed by position; they
+//    follow the compactions of A and are computed again for a new lambda.
+//    The columns and the substitution are FP32, the coefficients and g FP64;
+//    the FP32 error on g is proportional to the steps, and every screening
+//    pass recomputes g from a fresh residual.
 //
 //  * residual mode.  A chunk of C consecutive active coordinates: the C dot
 //    products x_j^T rho are formed at once against the current residual; the
@@ -18,17 +39,6 @@
 //    and the scan continues after it.  Column loads are software-pipelined
 //    two chunks ahead; beta and 1/||x_j||^2 of the active positions sit in
 //    LDS, so the loop's only global traffic is X.
-//
-//  * Gram mode, for active sets of at most QG coordinates whose nonzeros fit
-//    the LDS column cache: the correlations g = X_A^T rho (exact at the start
-//    of the interval, from the sweep) are held in registers, 8 positions per
-//    lane, and a change delta at coordinate j becomes g -= delta X_A^T x_j: a
-//    q/64-wide update with a cached Gram column from LDS instead of a
-//    dependent n-long reduction.  A column is computed the first time its
-//    coordinate changes at the current lambda and follows the compactions of
-//    A.  The cached columns are FP32; their error on g is proportional to the
-//    steps and vanishes at the fixed point, and every screening pass
-//    recomputes g from a fresh residual.
 //
 // Lanes of one wavefront order their LDS accesses without block barriers, so
 // pending global loads are never drained inside the loops.
@@ -40,6 +50,10 @@
 
 namespace gs {
 
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 template <typename XT, int VEC, int S, int NG, bool GATHER>
 struct Narrow {
   using L = ColLayout<XT, VEC, S, NG, GATHER>;
@@ -49,9 +63,8 @@ struct Narrow {
   static constexpr int NT = (NMAX + 63) / 64;        // rows per lane, row-major layout
   static constexpr int NB = NT <= 2 ? 8 : (NT <= 4 ? 4 : (NT <= 8 ? 2 : 1));  // refresh batch
   static constexpr int U = RPL <= 8 ? 4 : (RPL <= 24 ? 3 : (RPL <= 32 ? 2 : 1));  // sweep batch
-  static constexpr int TQ = 8;        // active positions per lane in Gram mode
-  static constexpr int QG = 64 * TQ;  // largest active set run in Gram mode
-  static constexpr int NSMAX = 256;   // Gram cache slots
+  static constexpr int NSC = kSlotsMax;          // Gram slots (largest support in pattern mode)
+  static constexpr int NBLD = RPL <= 20 ? 4 : 2;  // Gram columns computed per sweep of A
 
   // Per-wave context.
   struct Ctx {
@@ -65,26 +78,45 @@ struct Narrow {
     double* rho_l;              // LDS, n
     XT* tile;                   // LDS, 64 * RPL
     int* rows_l;                // LDS, n (gather)
+    float* stg;                 // LDS staging region of the residual mode
+    int stg_cap;                // its size in floats
     gbl<double>* nrm2;
     gbl<double>* inv;           // 1/||x_j||^2 (0 for a zero column)
     gbl<double>* beta;
-    gbl<double>* c;
+    gbl<double>* c;             // correlations by position (one of two buffers)
     gbl<int32_t>* act;
   };
 
-  // LDS state shared by the two modes.  The region `G` holds either the Gram
-  // cache (Gram mode) or the active positions' beta and 1/||x||^2 (residual
-  // mode, when 16 q bytes fit).  Scalars are wavefront-uniform.
-  struct Gram {
-    int* slot;    // QG: cache slot of position k, or -1 (between intervals)
-    int* np;      // QG: position of k after the last compaction, or -1
-    int* owner;   // NSMAX: position whose column a slot holds, or -1
-    XT* xj;       // NMAX: staging of the column being correlated
-    float* G;     // cap floats: slot s holds x_{A[k]}^T x_{A[owner[s]]} at G[s*q + k]
-    int cap;      // floats available in G
-    int ns;       // slots in use for the current q
-    int victim;   // round-robin eviction cursor
-    bool on;      // the cache describes the current active set
+  // Pattern-mode state.  Scalars are wavefront-uniform; sp..u hold the
+  // support members m = lane (index 0) and m = lane + 64 (index 1).
+  struct Pat {
+    gbl<float>* gc;       // slot v: x_j^T x_{owner[v]} at gc[v*ldg + j] for j in A
+    gbl<float>* ng;       // feature -> ||G_{j,S}||_2 (zero coordinates of A)
+    gbl<int32_t>* pslot;  // feature -> slot, or -1
+    gbl<int32_t>* psup;   // feature -> index in S, or -1
+    gbl<double>* c2;      // the other correlation buffer
+    int64_t ldg;
+    int ns;               // slots of this problem
+    int gs_cap;           // LDS floats of the block
+    int* owner;           // LDS ns: feature whose column a slot holds, or -1
+    int* spos;            // LDS NSC: positions of S
+    int* sfeat;           // LDS NSC: features of S when the block was built
+    int* pfeat;           // LDS NSC: features marked in psup
+    int* bslot;           // LDS NBLD: slots of the columns being computed
+    int* bfeat;           // LDS NBLD: their features
+    float* stage;         // LDS NBLD x NMAX: those columns
+    float* gs;            // LDS: column l of G_SS / ||x_m||^2 at gs[l*gsp + m], 1 on the diagonal
+    int s;                // |S|
+    int gsp;              // column stride of gs (64 or 128)
+    int s_t;              // |S| when the block was built (-1: never)
+    int npf;              // entries of pfeat
+    int victim;           // round-robin cursor of the slot search
+    bool valid;           // registers and block describe the current S and c
+    bool ng_ok;           // ng holds the row norms for S over the current A
+    double tau;           // min over zero coordinates of (lambda - |c0_k|) / ng_k
+    int sp[2], sl[2], sj[2];
+    double sb[2], b0[2], sg[2];
+    float id[2], u[2];
   };
 
   struct Stage {
@@ -280,10 +312,9 @@ struct Narrow {
   }
 
   // Sphere test over A with ordered in-place compaction of A and c; screened
-  // nonzero coefficients are set to zero (dropped_nz is then set).  With np,
-  // the new position of every old one (-1 when dropped) is recorded.
+  // nonzero coefficients are set to zero (dropped_nz is then set).
   static __device__ __forceinline__ int test_compact(const Ctx& x, const GapInfo& g, int q, bool full,
-                                     bool& dropped_nz, int* np = nullptr) {
+                                     bool& dropped_nz) {
     int q2 = 0;
     bool dn = false;
     const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
@@ -316,7 +347,6 @@ struct Narrow {
           x.act[pos] = jv[u];
           x.c[pos] = cv[u];  // c of kept coordinates moves with them
         }
-        if (np && v) np[k] = keep ? pos : -1;
         q2 += __popcll(m);
       }
     }
@@ -398,8 +428,8 @@ struct Narrow {
   // One cyclic CD epoch over A (Algorithm 1):
   //   beta_j <- ST(lambda/||x_j||^2, beta_j + x_j^T rho / ||x_j||^2),
   //   rho    <- rho - (beta_j' - beta_j) x_j.
-  // The epoch may start at position k0 > 0 (the rest of an epoch begun in
-  // Gram mode): positions before k0 are left alone.
+  // The epoch may start at position k0 > 0: positions before k0 are left
+  // alone.
   template <bool POSL>
   static __device__ __forceinline__ void cd_epoch(const Ctx& x, int q, bool full, double lambda, double* pb,
                                   const double* pinv, double (&r)[RPL], int k0) {
@@ -424,17 +454,16 @@ struct Narrow {
   }
 
   // ne residual-mode epochs (the first one from position k0), the residual
-  // taken from and returned to LDS.  With room for 16 q bytes in the cache
+  // taken from and returned to LDS.  With room for 16 q bytes in the staging
   // region, beta and 1/||x||^2 of the active positions are staged in LDS
-  // for the interval (the region's Gram cache is then given up).
-  static __device__ __forceinline__ void cd_epochs(const Ctx& x, Gram& gm, int q, bool full, double lambda,
+  // for the interval.
+  static __device__ __forceinline__ void cd_epochs(const Ctx& x, int q, bool full, double lambda,
                                    int ne, int k0) {
     double r[RPL];
     load_rows(x, x.rho_l, r);
-    const bool posl = q > 0 && (size_t)q * 2 * sizeof(double) <= (size_t)gm.cap * sizeof(float);
+    const bool posl = q > 0 && (size_t)q * 2 * sizeof(double) <= (size_t)x.stg_cap * sizeof(float);
     if (posl) {
-      gm.on = false;
-      double* pb = reinterpret_cast<double*>(gm.G);
+      double* pb = reinterpret_cast<double*>(x.stg);
       double* pinv = pb + q;
       for (int k = x.lane; k < q; k += 64) {
         const int j = full ? k : x.act[k];
@@ -460,231 +489,509 @@ struct Narrow {
     wave_lds_order();
   }
 
-  // ---- Gram mode -------------------------------------------------------------
+  // ---- pattern mode ----------------------------------------------------------
+  //
+  // State of a pattern (set up after a screening pass or a residual-mode
+  // epoch, when c = X_A^T rho is exact):
+  //   * the support list S (positions ascending), with per member m: the
+  //     coefficient b_m, its sign sigma_m, 1/||x_m||^2 and
+  //     u_m = (g_m - lambda sigma_m) / ||x_m||^2, the scaled gradient gap;
+  //   * the Gram block of S, G_SS / ||x_m||^2 column by column in LDS;
+  //   * an anchor: beta0 = beta_S and c0 = c at the last exact point, and for
+  //     every zero coordinate k of A the row norm ng_k = ||G_{k,S}||_2, with
+  //     tau = min_k (lambda - |c0_k|) / ng_k.
+  // An epoch is the forward substitution on the block (its running vector is
+  // u itself: step l takes delta_l = u_l and subtracts delta_l times column l
+  // from u; the diagonal entry is 1, so u_l becomes 0 as in the coordinate
+  // update, and u ends as the next epoch's gradient gap).  A zero coordinate
+  // k is then visited with the correlation c0_k - G_{k,S} (Delta + delta
+  // restricted to members before k), Delta = beta_S - beta0; its size is at
+  // most |c0_k| + ng_k (||Delta||_2 + ||delta||_2) by Cauchy-Schwarz, so
+  // ||Delta||_2 + ||delta||_2 < tau proves that every zero coordinate stays
+  // at zero.  Otherwise the exact check runs over the Gram columns of S in
+  // the global cache and, when it passes, moves the anchor to the new point.
 
-  // Starts the cache for the active set of size q (when it is off).
-  static __device__ __forceinline__ void gram_begin(const Ctx& x, Gram& gm, int q) {
-    if (!gm.on) {
-      for (int k = x.lane; k < q; k += 64) gm.slot[k] = -1;
-      for (int s = x.lane; s < NSMAX; s += 64) gm.owner[s] = -1;
-      gm.victim = 0;
-      gm.on = true;
-    }
-    gm.ns = min(NSMAX, gm.cap / max(q, 1));
+  // A new lambda: the active set restarts from all of {0..p-1}; cached
+  // columns and row norms only cover the old one.
+  static __device__ __forceinline__ void pattern_new_lambda(const Ctx& x, Pat& pt) {
+    for (int v = x.lane; v < pt.ns; v += 64) pt.owner[v] = -1;
+    for (int j = x.lane; j < x.p; j += 64) pt.pslot[j] = -1;
+    pt.victim = 0;
+    pt.valid = false;
+    pt.ng_ok = false;
     wave_lds_order();
+    __threadfence_block();
   }
 
-  // After the active set shrank from q_old to q_new (new positions in gm.np):
-  // move every cached column to stride q_new and drop the slots whose
-  // coordinate left.  In place: in ascending order every destination address
-  // is at most its source address, so no source is overwritten before read.
-  static __device__ __forceinline__ void gram_compact(const Ctx& x, Gram& gm, int q_old, int q_new) {
-    if (q_new == q_old) return;  // nothing dropped: positions unchanged
-    for (int s = 0; s < gm.ns; ++s) {
-      const int own = gm.owner[s];
-      if (own < 0) continue;
-      const int nown = gm.np[own];
-      wave_lds_order();
-      if (x.lane == 0) gm.owner[s] = nown;
-      if (nown < 0) continue;
-      for (int k0 = 0; k0 < q_old; k0 += 256) {
-        float v[4];
-        int dd[4];
+  // Gram columns of the nb features in bfeat into the slots bslot:
+  // gc[v*ldg + A[k]] = x_{A[k]}^T x_j for every position k < q, in one sweep.
+  static __device__ __forceinline__ void build_cols(const Ctx& x, const Pat& pt, int q, bool full,
+                                                    int nb) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + 64 * u + x.lane;
-          v[u] = k < q_old ? gm.G[s * q_old + k] : 0.f;
-          dd[u] = k < q_old ? gm.np[k] : -1;
-        }
-        wave_lds_order();
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (dd[u] >= 0) gm.G[s * q_new + dd[u]] = v[u];
-        wave_lds_order();
+    for (int b = 0; b < NBLD; ++b) {
+      if (b < nb) {
+        const int j = __builtin_amdgcn_readfirstlane(pt.bfeat[b]);
+        const gbl<XT>* cj = col(x, j);
+        for (int i = x.lane; i < NMAX; i += 64)
+          pt.stage[b * NMAX + i] = i < x.n ? (float)cj[src_row(x, i)] : 0.f;
       }
     }
-    for (int k0 = 0; k0 < q_old; k0 += 64) {
-      const int k = k0 + x.lane;
-      const int sl = k < q_old ? gm.slot[k] : -1;
-      const int d = k < q_old ? gm.np[k] : -1;
-      wave_lds_order();
-      if (d >= 0) gm.slot[d] = sl;
-      wave_lds_order();
-    }
-  }
-
-  // Computes the Gram column of position pos (x_{A[k]}^T x_{A[pos]} for all
-  // k < q) into a slot; returns the slot and, in `evicted`, the position
-  // whose column the slot held before (-1 if none).
-  static __device__ __forceinline__ int gram_build(const Ctx& x, Gram& gm, int pos, int q,
-                                                  bool full,
-                                   int& evicted) {
-    const int j = __builtin_amdgcn_readfirstlane(full ? pos : x.act[pos]);
-    const gbl<XT>* cj = col(x, j);
-    for (int i = x.lane; i < x.n; i += 64) gm.xj[i] = cj[src_row(x, i)];
-    const int s = gm.victim;
-    gm.victim = (gm.victim + 1 < gm.ns) ? gm.victim + 1 : 0;
-    evicted = __builtin_amdgcn_readfirstlane(gm.owner[s]);
     wave_lds_order();
-    if (x.lane == 0) gm.owner[s] = pos;
-    float* Gc = gm.G + s * q;
-    for (int k = x.lane; k < q; k += 64) {
-      const gbl<XT>* ck = col(x, full ? k : x.act[k]);
-      double a0 = 0.0, a1 = 0.0;
-      if constexpr (GATHER || VEC == 1) {
-        for (int i = 0; i < x.n; ++i) a0 = fma((double)ck[src_row(x, i)], (double)gm.xj[i], a0);
-      } else {
-        for (int i = 0; i < x.n; i += VEC) {
-          XT t[VEC];
-          VecLoad<XT, VEC>::go(ck + i, t);
+    float v[NBLD][RPL];
+    gbl<float>* dst[NBLD];
 #pragma unroll
-          for (int e = 0; e < VEC; e += 2) {
-            a0 = fma((double)t[e], (double)gm.xj[i + e], a0);
-            if (e + 1 < VEC) a1 = fma((double)t[e + 1], (double)gm.xj[i + e + 1], a1);
+    for (int b = 0; b < NBLD; ++b) {
+#pragma unroll
+      for (int m = 0; m < NG; ++m)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[b][m * VEC + e] = pt.stage[b * NMAX + L::row(x.seg, m, e)];
+      const int sl = __builtin_amdgcn_readfirstlane(pt.bslot[b]);
+      dst[b] = pt.gc + (int64_t)(b < nb ? sl : 0) * pt.ldg;
+    }
+    constexpr int UB = 2;
+    for (int base = 0; base < q; base += UB * C) {
+      XT xr[UB][RPL];
+      int jr[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        jr[u] = act_at(x, base + u * C + x.slot, q, full);
+        L::load_raw(col(x, jr[u]), x.n, x.seg, x.ridx, xr[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int k = base + u * C + x.slot;
+#pragma unroll
+        for (int b = 0; b < NBLD; ++b) {
+          if (b < nb) {
+            // rows >= n: raw copies of row 0 meet zeros of the staged column
+            float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+            for (int i = 0; i < RPL; i += 2) {
+              a0 = fmaf((float)xr[u][i], v[b][i], a0);
+              if (i + 1 < RPL) a1 = fmaf((float)xr[u][i + 1], v[b][i + 1], a1);
+            }
+            const double dsum = seg_sum<S>((double)a0 + (double)a1);
+            if (x.seg == 0 && k < q) dst[b][jr[u]] = (float)dsum;
           }
         }
-      }
-      Gc[k] = (float)(a0 + a1);
-    }
-    wave_lds_order();
-    return s;
-  }
-
-  // Register state of the Gram mode: positions (t << 6) + lane, t < TQ.
-  struct GramRegs {
-    double gr[TQ], br[TQ], ir[TQ];
-    int sr[TQ];
-  };
-
-  // The in-order scan of row T (positions 64T .. 64T+63); compile-time T keeps
-  // every register array statically indexed.
-  template <int T>
-  static __device__ __forceinline__ void gram_row(const Ctx& x, Gram& gm, GramRegs& R, int q,
-                                                  int nt, bool full, double lambda, int budget,
-                                                  int& builds, int& kstart) {
-    const double thr = lambda * R.ir[T];
-    int start = 0;
-    for (;;) {
-      bool chg = false;
-      double bn = R.br[T];
-      if (R.ir[T] > 0.0 && x.lane >= start) {
-        bn = soft_thr(thr, R.br[T] + R.gr[T] * R.ir[T]);
-        chg = (bn != R.br[T]);
-      }
-      const uint64_t mk = ballot(chg);
-      if (!mk) break;
-      const int l0 = __builtin_ctzll(mk);
-      const double delta = readlane_d(bn - R.br[T], l0);
-      if (x.lane == l0) R.br[T] = bn;
-      const int pos = (T << 6) + l0;
-      int s = __builtin_amdgcn_readlane(R.sr[T], l0);
-      if (s < 0) {
-        int ev;
-        s = gram_build(x, gm, pos, q, full, ev);
-        ++builds;
-        if (ev >= 0) {
-#pragma unroll
-          for (int t3 = 0; t3 < TQ; ++t3)
-            if (t3 == (ev >> 6) && x.lane == (ev & 63)) R.sr[t3] = -1;
-        }
-        if (x.lane == l0) R.sr[T] = s;
-      }
-      const float* Gc = gm.G + s * q;
-      float gv[TQ];
-#pragma unroll
-      for (int t2 = 0; t2 < TQ; ++t2) {
-        const int kk = (t2 << 6) + x.lane;
-        gv[t2] = (t2 < nt) ? Gc[kk < q ? kk : q - 1] : 0.f;
-      }
-#pragma unroll
-      for (int t2 = 0; t2 < TQ; ++t2) R.gr[t2] = fma(-delta, (double)gv[t2], R.gr[t2]);
-      if (builds > budget) kstart = pos + 1;
-      start = l0 + 1;
-      if (start >= 64 || kstart >= 0) break;
-    }
-  }
-
-  template <int T>
-  static __device__ __forceinline__ void gram_rows(const Ctx& x, Gram& gm, GramRegs& R, int q,
-                                                   int nt, bool full, double lambda, int budget,
-                                                   int& builds, int& kstart) {
-    if constexpr (T < TQ) {
-      if (T < nt && kstart < 0) {
-        gram_row<T>(x, gm, R, q, nt, full, lambda, budget, builds, kstart);
-        gram_rows<T + 1>(x, gm, R, q, nt, full, lambda, budget, builds, kstart);
-      }
-    }
-  }
-
-  // Up to ne cyclic CD epochs over A in Gram mode (g at entry in c); beta is
-  // written back at the end.  Returns the number of complete epochs.  Once
-  // more than `budget` columns were built in this call (the cache thrashes)
-  // it stops right after the coordinate being updated and sets kstart to the
-  // next position of the unfinished epoch (kstart = -1 otherwise); the caller
-  // finishes the interval in residual mode from there, so the cyclic order is
-  // unchanged.
-  static __device__ __forceinline__ int gram_epochs(const Ctx& x, Gram& gm, int q, bool full, double lambda,
-                                    int ne, int budget, int& kstart) {
-    const int nt = (q + 63) >> 6;
-    GramRegs R;
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) {
-      const int k = (t << 6) + x.lane;
-      const bool v = k < q;
-      const int kk = v ? k : q - 1;
-      const int j = full ? kk : x.act[kk];
-      R.gr[t] = v ? x.c[kk] : 0.0;
-      R.br[t] = v ? x.beta[j] : 0.0;
-      R.ir[t] = v ? x.inv[j] : 0.0;
-      R.sr[t] = v ? gm.slot[kk] : -1;
-    }
-    int builds = 0, e = 0;
-    kstart = -1;
-    for (; e < ne && kstart < 0; ++e)
-      gram_rows<0>(x, gm, R, q, nt, full, lambda, budget, builds, kstart);
-    if (kstart >= 0) --e;  // the last epoch is unfinished
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) {
-      const int k = (t << 6) + x.lane;
-      if (k < q) {
-        x.beta[full ? k : x.act[k]] = R.br[t];
-        gm.slot[k] = R.sr[t];
       }
     }
     __threadfence_block();
     wave_lds_order();
-    return e;
+  }
+
+  // Row norms ng_j = ||G_{j,S}||_2 of the zero coordinates of A and
+  // tau = min (lambda - |c_k|) / ng_k over them (c by position).
+  static __device__ __forceinline__ double row_norms_tau(const Ctx& x, const Pat& pt, int q,
+                                                         bool full, double lambda, bool recompute) {
+    const int s = pt.s;
+    double tau = INFINITY;
+    for (int base = 0; base < q; base += 256) {
+      int jv[4];
+      bool zv[4];
+      double cv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = base + 64 * t + x.lane;
+        jv[t] = act_at(x, k, q, full);
+        cv[t] = x.c[k < q ? k : q - 1];
+        zv[t] = k < q && pt.psup[jv[t]] < 0;
+      }
+      float nv[4];
+      if (recompute) {
+        float a[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int m0 = 0; m0 < s; m0 += 4) {
+          float g[4][4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = m0 + u;
+            const int sl = m < s ? (m < 64 ? __builtin_amdgcn_readlane(pt.sl[0], m)
+                                           : __builtin_amdgcn_readlane(pt.sl[1], m - 64))
+                                 : 0;
+            const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) g[u][t] = m < s ? gcol[jv[t]] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[t] = fmaf(g[u][t], g[u][t], a[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          nv[t] = sqrtf(a[t]);
+          if (zv[t]) pt.ng[jv[t]] = nv[t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) nv[t] = pt.ng[jv[t]];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (zv[t]) tau = fmin(tau, slack_ratio(cv[t], nv[t], lambda));
+    }
+    __threadfence_block();
+    return wave_min(tau);
+  }
+
+  // (lambda - |c|) / ng, with the FP32 row norm rounded up; a coordinate that
+  // no support column touches stays at zero iff |c| <= lambda.
+  static __device__ __forceinline__ double slack_ratio(double c, float ng, double lambda) {
+    const double sl = lambda - fabs(c);
+    if (ng > 0.f) return sl / ((double)ng * (1.0 + 1e-5));
+    return sl >= 0.0 ? INFINITY : -1.0;
+  }
+
+  // Sets up the pattern of the current coefficients over A (requires c =
+  // X_A^T rho for the current beta).  Returns false when the support exceeds
+  // the slots or the LDS block.
+  static __device__ __forceinline__ bool pattern_setup(const Ctx& x, Pat& pt, int q, bool full,
+                                                       double lambda, int (&stc)[kNumStats]) {
+    // unmark the previous support, then list the new one
+    for (int m = x.lane; m < pt.npf; m += 64) pt.psup[pt.pfeat[m]] = -1;
+    __threadfence_block();
+    const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
+    int s = 0;
+    for (int base = 0; base < q; base += 64) {
+      const int k = base + x.lane;
+      const bool kq = k < q;
+      const int j = act_at(x, k, q, full);
+      const bool nz = kq && x.beta[j] != 0.0;
+      const uint64_t m = ballot(nz);
+      const int idx = s + __popcll(m & lt);
+      if (nz && idx < NSC) {
+        pt.spos[idx] = k;
+        pt.pfeat[idx] = j;
+        pt.psup[j] = idx;
+      }
+      s += __popcll(m);
+    }
+    pt.npf = min(s, NSC);
+    wave_lds_order();
+    __threadfence_block();
+    const int sp_stride = s > 64 ? 128 : 64;
+    if (s > pt.ns || s * sp_stride > pt.gs_cap) return false;
+    ++stc[kStatSetups];
+    pt.s = s;
+    pt.gsp = sp_stride;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int m = x.lane + 64 * h;
+      const bool v = m < s;
+      const int k = v ? pt.spos[m] : 0;
+      const int j = act_at(x, k, q, full);
+      pt.sp[h] = k;
+      pt.sj[h] = j;
+      pt.sb[h] = v ? x.beta[j] : 0.0;
+      pt.sg[h] = pt.sb[h] > 0.0 ? 1.0 : -1.0;
+      pt.id[h] = v ? (float)x.inv[j] : 0.f;
+      pt.sl[h] = v ? pt.pslot[j] : 0;
+      pt.b0[h] = pt.sb[h];
+      pt.u[h] = v ? (float)(x.c[k] - lambda * pt.sg[h]) * pt.id[h] : 0.f;
+    }
+    // a slot for every member, the missing columns computed NBLD at a time
+    bool failed = false;
+    while (!failed) {
+      uint64_t need0 = ballot(x.lane < s && pt.sl[0] < 0);
+      uint64_t need1 = ballot(x.lane + 64 < s && pt.sl[1] < 0);
+      if (!need0 && !need1) break;
+      int nb = 0;
+      while (nb < NBLD && (need0 || need1)) {
+        int m;
+        if (need0) {
+          m = __builtin_ctzll(need0);
+          need0 &= need0 - 1;
+        } else {
+          m = 64 + __builtin_ctzll(need1);
+          need1 &= need1 - 1;
+        }
+        // a slot whose owner is not in S (there is one: s <= ns and m has
+        // none); the scan is bounded all the same
+        int v = 0, o = 0;
+        bool found = false;
+        for (int tries = 0; tries < pt.ns && !found; ++tries) {
+          v = pt.victim;
+          pt.victim = v + 1 < pt.ns ? v + 1 : 0;
+          o = __builtin_amdgcn_readfirstlane(pt.owner[v]);
+          found = o < 0 || __builtin_amdgcn_readfirstlane(pt.psup[o]) < 0;
+        }
+        if (!found) {
+          failed = true;
+          break;
+        }
+        const int jm = m < 64 ? __builtin_amdgcn_readlane(pt.sj[0], m)
+                              : __builtin_amdgcn_readlane(pt.sj[1], m - 64);
+        wave_lds_order();
+        if (x.lane == 0) {
+          if (o >= 0) pt.pslot[o] = -1;
+          pt.pslot[jm] = v;
+          pt.owner[v] = jm;
+          pt.bslot[nb] = v;
+          pt.bfeat[nb] = jm;
+        }
+        if (m < 64) {
+          if (x.lane == m) pt.sl[0] = v;
+        } else {
+          if (x.lane == m - 64) pt.sl[1] = v;
+        }
+        ++nb;
+      }
+      wave_lds_order();
+      if (nb) build_cols(x, pt, q, full, nb);  // every assigned slot gets its column
+      stc[kStatBuilds] += nb;
+    }
+    if (failed) return false;
+    // the block and the row norms depend on the features of S only
+    bool same = (s == pt.s_t);
+    if (same) {
+      bool diff = false;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = x.lane + 64 * h;
+        if (m < s && pt.sfeat[m] != pt.sj[h]) diff = true;
+      }
+      same = ballot(diff) == 0;
+    }
+    if (!same) {
+      ++stc[kStatSupportChanges];
+      for (int l = 0; l < s; ++l) {
+        const int vl = l < 64 ? __builtin_amdgcn_readlane(pt.sl[0], l)
+                              : __builtin_amdgcn_readlane(pt.sl[1], l - 64);
+        const int jl = l < 64 ? __builtin_amdgcn_readlane(pt.sj[0], l)
+                              : __builtin_amdgcn_readlane(pt.sj[1], l - 64);
+        const gbl<float>* gcol = pt.gc + (int64_t)vl * pt.ldg;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int m = x.lane + 64 * h;
+          if (m < sp_stride) {
+            float val = (m < s) ? gcol[pt.sj[h]] * pt.id[h] : 0.f;
+            if (m == l) val = 1.f;
+            pt.gs[l * sp_stride + m] = val;
+          }
+        }
+        (void)jl;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = x.lane + 64 * h;
+        if (m < s) pt.sfeat[m] = pt.sj[h];
+      }
+      pt.s_t = s;
+      pt.ng_ok = false;
+      wave_lds_order();
+    }
+    pt.tau = row_norms_tau(x, pt, q, full, lambda, !pt.ng_ok);
+    pt.ng_ok = true;
+    pt.valid = true;
+    return true;
+  }
+
+  // The exact zero-coordinate check of an epoch (steps d, previous offset dp
+  // = beta_S - beta0, both FP32): for every position k, with accP = G_{k,S} dp
+  // and accD = G_{k,S} d, the coordinate's correlation at its visit is
+  // c_k - accP - (accD over members before k); the new anchor value is
+  // c_k - accP - accD (written to c2).  Returns true when every zero
+  // coordinate stays at zero; tau_new is the slack ratio at the new anchor.
+  static __device__ __forceinline__ bool pattern_exact(const Ctx& x, const Pat& pt, int q,
+                                                       bool full, double lambda,
+                                                       const float (&d)[2], const float (&dp)[2],
+                                                       double& tau_new) {
+    const int s = pt.s;
+    bool bad = false;
+    double tau = INFINITY;
+    for (int base = 0; base < q; base += 256) {
+      int jv[4], mf[4];
+      double cv[4];
+      float accP[4], accD[4], part[4];
+      bool isS[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = base + 64 * t + x.lane;
+        jv[t] = act_at(x, k, q, full);
+        cv[t] = x.c[k < q ? k : q - 1];
+        const int bound = base + 64 * t;
+        mf[t] = __popcll(ballot(x.lane < s && pt.sp[0] < bound)) +
+                __popcll(ballot(x.lane + 64 < s && pt.sp[1] < bound));
+        accP[t] = accD[t] = part[t] = 0.f;
+        isS[t] = false;
+      }
+      for (int m0 = 0; m0 < s; m0 += 4) {
+        float g[4][4], dm[4], pm[4];
+        int pos[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int m = m0 + u;
+          const bool mv = m < s;
+          const int h = m < 64 ? 0 : 1;
+          const int ml = m & 63;
+          const int sl = mv ? (h ? __builtin_amdgcn_readlane(pt.sl[1], ml)
+                                 : __builtin_amdgcn_readlane(pt.sl[0], ml))
+                            : 0;
+          dm[u] = mv ? (h ? readlane_f(d[1], ml) : readlane_f(d[0], ml)) : 0.f;
+          pm[u] = mv ? (h ? readlane_f(dp[1], ml) : readlane_f(dp[0], ml)) : 0.f;
+          pos[u] = mv ? (h ? __builtin_amdgcn_readlane(pt.sp[1], ml)
+                           : __builtin_amdgcn_readlane(pt.sp[0], ml))
+                      : -1000000;
+          const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) g[u][t] = mv ? gcol[jv[t]] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int m = m0 + u;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (m == mf[t]) part[t] = accD[t];  // members before row t are summed
+            accP[t] = fmaf(g[u][t], pm[u], accP[t]);
+            accD[t] = fmaf(g[u][t], dm[u], accD[t]);
+            const int dd = pos[u] - (base + 64 * t);
+            if (dd >= 0 && dd < 64) {  // member inside row t
+              if (x.lane > dd) part[t] = fmaf(g[u][t], dm[u], part[t]);
+              if (x.lane == dd) isS[t] = true;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (mf[t] >= s) part[t] = accD[t];
+        const int k = base + 64 * t + x.lane;
+        if (k < q) {
+          const double cn = cv[t] - ((double)accP[t] + (double)accD[t]);
+          pt.c2[k] = cn;
+          if (!isS[t]) {
+            const double vis = cv[t] - (double)accP[t] - (double)part[t];
+            if (fabs(vis) > lambda) bad = true;
+            tau = fmin(tau, slack_ratio(cn, pt.ng[jv[t]], lambda));
+          }
+        }
+      }
+    }
+    __threadfence_block();
+    tau_new = wave_min(tau);
+    return ballot(bad) == 0;
+  }
+
+  // One cyclic CD epoch over A by the pattern mode.  Returns 0 when the
+  // premise fails (nothing written), 1 when committed, 2 when committed and
+  // no coefficient moved (the state is a fixed point of the epoch).
+  static __device__ __forceinline__ int pattern_epoch(Ctx& x, Pat& pt, int q, bool full,
+                                                      double lambda, int (&stc)[kNumStats]) {
+    const int s = pt.s;
+    const int sps = pt.gsp;
+    float u[2] = {pt.u[0], pt.u[1]};
+    float d[2] = {0.f, 0.f};
+    const bool two = s > 64;
+    // forward substitution on the scaled block: delta_l = u_l, u -= delta_l col_l
+    for (int l0 = 0; l0 < s; l0 += 8) {
+      float t0[8], t1[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int l = l0 + v;
+        const float* colp = pt.gs + (l < s ? l : 0) * sps;
+        t0[v] = colp[x.lane];
+        t1[v] = two ? colp[64 + x.lane] : 0.f;
+      }
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int l = l0 + v;
+        if (l < s) {
+          float dl;
+          if (l < 64) {
+            dl = readlane_f(u[0], l);
+            if (x.lane == l) d[0] = dl;
+          } else {
+            dl = readlane_f(u[1], l - 64);
+            if (x.lane == l - 64) d[1] = dl;
+          }
+          u[0] = fmaf(-t0[v], dl, u[0]);
+          u[1] = fmaf(-t1[v], dl, u[1]);
+        }
+      }
+    }
+    double bn[2];
+    float dp[2];
+    bool bad = false, moved = false;
+    double sD = 0.0, sd = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int m = x.lane + 64 * h;
+      const bool v = m < s;
+      if (!v) d[h] = 0.f;
+      bn[h] = pt.sb[h] + (double)d[h];
+      const double dprev = pt.sb[h] - pt.b0[h];
+      dp[h] = (float)dprev;
+      if (v) {
+        if (!(pt.sg[h] > 0.0 ? bn[h] > 0.0 : bn[h] < 0.0)) bad = true;
+        if (d[h] != 0.f) moved = true;
+        sD = fma(dprev, dprev, sD);
+        sd = fma((double)d[h], (double)d[h], sd);
+      }
+    }
+    if (ballot(bad)) return 0;
+    const double reach = (sqrt(wave_sum(sD)) + sqrt(wave_sum(sd))) * (1.0 + 1e-6);
+    bool reanchor = false;
+    double tau_new = 0.0;
+    if (!(reach < pt.tau)) {
+      ++stc[kStatExact];
+      if (!pattern_exact(x, pt, q, full, lambda, d, dp, tau_new)) return 0;
+      reanchor = true;
+    }
+    // commit
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int m = x.lane + 64 * h;
+      if (m < s && d[h] != 0.f) {
+        pt.sb[h] = bn[h];
+        x.beta[pt.sj[h]] = bn[h];
+      }
+      pt.u[h] = u[h];
+    }
+    if (reanchor) {
+      gbl<double>* t = x.c;
+      x.c = pt.c2;
+      pt.c2 = t;
+      pt.b0[0] = pt.sb[0];
+      pt.b0[1] = pt.sb[1];
+      pt.tau = tau_new;
+    }
+    __threadfence_block();
+    return ballot(moved) ? 1 : 2;
   }
 };
 
-// LDS bytes the narrow kernel needs before the Gram cache region (whose
-// size in floats is a launch argument, PathOpts::gram_cap); the region
-// starts 16-byte aligned at this offset.
+// LDS bytes the narrow kernel needs before its two dynamic regions (the
+// support's Gram block, PathOpts::gs_cap floats, then the residual mode's
+// staging region, PathOpts::lds_cap floats); they start 16-byte aligned at
+// this offset.
 template <typename XT, int VEC, int S, int NG, bool GATHER>
 constexpr size_t narrow_lds_bytes() {
   using N = Narrow<XT, VEC, S, NG, GATHER>;
   return (2 * sizeof(double) * N::NMAX + sizeof(XT) * 64 * N::RPL + sizeof(int) * N::NMAX +
-          sizeof(XT) * N::NMAX + 2 * sizeof(int) * N::QG + sizeof(int) * N::NSMAX + 15) &
+          4 * sizeof(int) * N::NSC + 2 * sizeof(int) * N::NBLD +
+          sizeof(float) * N::NBLD * N::NMAX + 15) &
          ~(size_t)15;
 }
 
 template <typename N, typename XT, size_t GOFF>
-__device__ __forceinline__ void bind_lds(typename N::Ctx& x, typename N::Gram& gm,
-                                         unsigned char* smem, int gram_cap) {
+__device__ __forceinline__ void bind_lds(typename N::Ctx& x, typename N::Pat& pt,
+                                         unsigned char* smem, const PathOpts& opts) {
   x.y_l = reinterpret_cast<double*>(smem);
   x.rho_l = x.y_l + N::NMAX;
   x.tile = reinterpret_cast<XT*>(x.rho_l + N::NMAX);
-  gm.xj = x.tile + 64 * N::RPL;
-  x.rows_l = reinterpret_cast<int*>(gm.xj + N::NMAX);
-  gm.slot = x.rows_l + N::NMAX;
-  gm.np = gm.slot + N::QG;
-  gm.owner = gm.np + N::QG;
-  // 16-byte aligned: the region also holds doubles in residual mode
-  gm.G = reinterpret_cast<float*>(smem + GOFF);
-  gm.cap = gram_cap;
-  gm.ns = 0;
-  gm.victim = 0;
-  gm.on = false;
+  x.rows_l = reinterpret_cast<int*>(x.tile + 64 * N::RPL);
+  pt.owner = x.rows_l + N::NMAX;
+  pt.spos = pt.owner + N::NSC;
+  pt.sfeat = pt.spos + N::NSC;
+  pt.pfeat = pt.sfeat + N::NSC;
+  pt.bslot = pt.pfeat + N::NSC;
+  pt.bfeat = pt.bslot + N::NBLD;
+  pt.stage = reinterpret_cast<float*>(pt.bfeat + N::NBLD);
+  pt.gs = reinterpret_cast<float*>(smem + GOFF);
+  pt.gs_cap = opts.gs_cap;
+  // 16-byte aligned (gs_cap is a multiple of 64): the region holds doubles
+  x.stg = pt.gs + opts.gs_cap;
+  x.stg_cap = opts.lds_cap;
 }
 
 // Persistent kernel: each wavefront pops problems from a device queue and
@@ -706,7 +1013,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     gbl<double>* bout_g = gptr(d.beta_out);
 
     typename N::Ctx x;
-    typename N::Gram gm;
+    typename N::Pat pt;
     x.X = gptr((const XT*)d.X);
     x.ldx = d.ldx;
     x.n = d.n;
@@ -714,16 +1021,35 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     x.lane = lane;
     x.slot = lane / S;
     x.seg = lane % S;
-    bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, gm, smem, opts.gram_cap);
+    bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, pt, smem, opts);
     x.nrm2 = gptr(d.nrm2);
     x.inv = gptr(d.inv);
     x.beta = gptr(d.beta);
     x.c = gptr(d.c);
     x.act = gptr(d.act);
+    pt.gc = gptr(d.gc);
+    pt.ng = gptr(d.ng);
+    pt.pslot = gptr(d.pslot);
+    pt.psup = gptr(d.psup);
+    pt.c2 = gptr(d.c2);
+    pt.ldg = d.ldg;
+    pt.ns = d.ns;
+    pt.s = 0;
+    pt.gsp = 64;
+    pt.s_t = -1;
+    pt.npf = 0;
+    pt.victim = 0;
+    pt.valid = false;
+    pt.ng_ok = false;
+    pt.tau = 0.0;
+    if (opts.pattern)
+      for (int j = lane; j < d.p; j += 64) pt.psup[j] = -1;
+    int stc[kNumStats];
+#pragma unroll
+    for (int i = 0; i < kNumStats; ++i) stc[i] = 0;
     N::setup(x, gptr(d.rows));
     const int n = d.n, p = d.p, T = d.T;
     const gbl<XT>* Y = gptr((const XT*)d.y);
-
     // ---- y into LDS; precompute ||x_j||^2 and lambda_max = ||X^T y||_inf
     double yy = 0.0;
     for (int i = lane; i < n; i += 64) {
@@ -800,19 +1126,22 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
       const double eps = opts.eps_rel * ynorm2;
       const double ynorm = sqrt(ynorm2);
       const int f = opts.f, K = opts.K;
+      const bool pat_on = opts.pattern != 0;
       for (int t = 0; t < T; ++t) {
         const double lambda = lam_g[t];
         int q = p;
         bool full = true;
         int k = 0, status = 1;
         double G = 0.0;
-        bool use_gram = false;
-        gm.on = false;  // a new lambda resets the active set and the cache
+        if (pat_on) N::pattern_new_lambda(x, pt);
+        bool c_ok = false, rho_ok = false;
+        int rejects = 0;
         for (;;) {
           if (k % f == 0 || k == K) {
             double R2, Ry, M, l1, sbx, xmax;
             int nnz = N::refresh(x, q, full, R2, Ry);
             N::sweep(x, q, full, M, l1, sbx, xmax);
+            ++stc[kStatPasses];
             GapInfo g = gap_safe(R2, Ry, l1, sbx, xmax, M, nnz, n, lambda, ynorm);
             G = g.gap;
             if (G <= eps) {
@@ -821,38 +1150,64 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
             }
             if (k == K) break;
             bool dropped;
-            const int q_old = q;
-            q = N::test_compact(x, g, q, full, dropped, gm.on ? gm.np : nullptr);
+            q = N::test_compact(x, g, q, full, dropped);
             full = false;
-            if (gm.on) N::gram_compact(x, gm, q_old, q);
-            // Gram mode when the cache holds the current nonzeros with room for
-            // newcomers (nnz of this pass bounds the coordinates that keep moving)
-            const int slots = q > 0 ? min(N::NSMAX, opts.gram_cap / q) : 0;
-            use_gram = q > 0 && q <= N::QG && slots >= 8 && slots >= nnz + max(8, nnz / 4);
+            rho_ok = true;
+            c_ok = true;
             if (dropped) {
               N::refresh(x, q, full, R2, Ry);
-              if (use_gram) N::sweep(x, q, full, M, l1, sbx, xmax);  // g at the new rho
+              c_ok = false;
             }
-            if (use_gram) N::gram_begin(x, gm, q);
+            pt.valid = false;
+            rejects = 0;
           }
-          // epochs up to the next screening pass (or the budget)
+          // epochs up to the next screening pass (or the budget): the pattern
+          // mode while it holds; a rejected epoch runs in residual mode, and
+          // after two rejections the interval stays there
           int ne = min(f - k % f, K - k);
-          int k0 = 0;
-          if (use_gram) {
-            int kstart;
-            const int done = N::gram_epochs(x, gm, q, full, lambda, ne, gm.ns, kstart);
-            k += done;
-            ne -= done;
-            if (kstart >= 0) {  // the cache thrashed: residual mode until the next pass
+          while (ne > 0) {
+            if (pat_on && rejects < 2 && q > 0) {
+              if (!pt.valid) {
+                if (!c_ok) {
+                  double M, l1, sbx, xmax;
+                  N::sweep(x, q, full, M, l1, sbx, xmax);
+                  c_ok = true;
+                }
+                if (!N::pattern_setup(x, pt, q, full, lambda, stc)) {
+                  rejects = 2;
+                  continue;
+                }
+              }
+              const int r = N::pattern_epoch(x, pt, q, full, lambda, stc);
+              if (r) {
+                ++stc[kStatPatternEpochs];
+                ++k;
+                --ne;
+                rho_ok = false;
+                if (r == 2) {
+                  stc[kStatSkipped] += ne;
+                  k += ne;
+                  ne = 0;
+                }
+                continue;
+              }
+              ++stc[kStatRejected];
+              ++rejects;
+              pt.valid = false;
+            }
+            if (!rho_ok) {
               double R2, Ry;
               N::refresh(x, q, full, R2, Ry);
-              use_gram = false;
-              gm.on = false;
-              k0 = kstart;
+              rho_ok = true;
             }
+            const int nr = (pat_on && rejects < 2) ? 1 : ne;
+            N::cd_epochs(x, q, full, lambda, nr, 0);
+            stc[kStatResidualEpochs] += nr;
+            k += nr;
+            ne -= nr;
+            c_ok = false;
+            pt.valid = false;
           }
-          if (ne > 0) N::cd_epochs(x, gm, q, full, lambda, ne, k0);
-          k += ne;
         }
         // beta^{lambda_t} and its certificate
         gbl<double>* bo = bout_g + (int64_t)t * p;
@@ -868,6 +1223,12 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
           d.status_out[t] = status;
         }
       }
+    }
+    if (opts.stats && lane == 0) {
+#pragma unroll
+      for (int i = 0; i < kNumStats; ++i)
+        if (stc[i])
+          atomicAdd(reinterpret_cast<unsigned long long*>(&opts.stats[i]), (unsigned long long)stc[i]);
     }
     if (opts.timestamps && lane == 0) {
       opts.timestamps[2 * d.orig] = t_start;
@@ -886,7 +1247,7 @@ __global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathO
   if (st->done || st->phase != 2) return;
   const int lane = threadIdx.x;
   typename N::Ctx x;
-  typename N::Gram gm;
+  typename N::Pat pt;
   x.X = gptr((const XT*)d.X);
   x.ldx = d.ldx;
   x.n = d.n;
@@ -894,7 +1255,7 @@ __global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathO
   x.lane = lane;
   x.slot = lane / S;
   x.seg = lane % S;
-  bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, gm, smem, opts.gram_cap);
+  bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, pt, smem, opts);
   x.nrm2 = gptr(d.nrm2);
   x.inv = gptr(d.inv);
   x.beta = gptr(d.beta);
@@ -908,7 +1269,7 @@ __global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathO
   const int k0 = st->k;
   const int ne = min(opts.f, opts.K - k0);
   const double lambda = gptr(d.lam)[st->t];
-  N::cd_epochs(x, gm, q, full, lambda, ne, 0);
+  N::cd_epochs(x, q, full, lambda, ne, 0);
   if (lane == 0) {
     st->k = k0 + ne;
     st->phase = 0;

@@ -39,7 +39,7 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(gs.gs_problem) == 136
     assert gs.gs_problem.lambda_min_ratio.offset == 72
     assert gs.gs_problem.lambda_out.offset == 128
-    assert ctypes.sizeof(gs.gs_opts) == 40
+    assert ctypes.sizeof(gs.gs_opts) == 48
 
 
 def test_defaults(lib):

@@ -139,10 +139,10 @@ int pattern_slots(const gs_problem* pr) {
   return std::max(1, std::min({kSlotsMax, pr->p, want}));
 }
 
-// Per-problem workspace arrays.  The pattern mode's feature-indexed arrays
-// hold ldg entries (p rounded up to 64).
+// Per-problem workspace arrays.  The pattern mode's position-indexed arrays
+// hold ldg entries (p rounded up to 256).
 void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
-  const int64_t ldg = (int64_t)align_up((size_t)pr->p, 64);
+  const int64_t ldg = (int64_t)align_up((size_t)pr->p, 256);
   const int ns = pattern_slots(pr);
   d->nrm2 = cv.take<double>(pr->p);
   d->inv = cv.take<double>(pr->p);
@@ -154,14 +154,15 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   d->gc = cv.take<float>((size_t)ns * ldg);
   d->ng = cv.take<float>(ldg);
   d->pslot = cv.take<int32_t>(ldg);
-  d->psup = cv.take<int32_t>(ldg);
+  d->npos = cv.take<int32_t>(ldg);
   d->c2 = cv.take<double>(ldg);
   d->ldg = ldg;
   d->ns = ns;
 }
 
-// LDS floats of the support's Gram block: ns columns of stride 64 or 128.
-int gs_floats(int ns) { return ns * (ns > 64 ? 128 : 64); }
+// LDS floats of the support's Gram block: up to ns columns (rounded up to 8)
+// of stride 64 or 128.
+int gs_floats(int ns) { return (ns + 7) / 8 * 8 * (ns > 64 ? 128 : 64); }
 
 struct Shared {
   ProbDesc* descs;

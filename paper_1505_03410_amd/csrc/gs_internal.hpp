@@ -32,14 +32,14 @@ struct ProbDesc {
   int32_t* act;   // 2p: active set (two buffers for the wide schedule)
   double* lam;    // T: lambdas (caller values on entry, absolute after init)
   double* rho;    // n: residual (wide schedule)
-  // pattern mode of the narrow schedule; the feature-indexed arrays hold ldg
-  // entries
-  float* gc;        // ns x ldg: Gram columns by slot, row j = feature j
-  float* ng;        // ldg: ||G_{j,S}||_2 of the zero coordinates of A
-  int32_t* pslot;   // ldg: slot holding the Gram column of feature j, or -1
-  int32_t* psup;    // ldg: index of feature j in the support list, or -1
-  double* c2;       // ldg: second buffer of the correlations c (by position)
-  int64_t ldg;      // p rounded up to a multiple of 64
+  // pattern mode of the narrow schedule; position-indexed arrays hold ldg
+  // entries, so that 256-position tiles never leave them
+  float* gc;        // ns x ldg: Gram columns by slot, row k = position k of A
+  float* ng;        // ldg: ||G_{k,S}||_2 of the zero coordinates of A
+  int32_t* pslot;   // ldg: slot holding the Gram column of position k, or -1
+  int32_t* npos;    // ldg: position after the last compaction, or -1
+  double* c2;       // ldg: second buffer of the correlations c
+  int64_t ldg;      // p rounded up to a multiple of 256
   int32_t ns;       // Gram slots of this problem (<= kSlotsMax)
   int32_t orig;     // index of the problem in the caller's array
 };

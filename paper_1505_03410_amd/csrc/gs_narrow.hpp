@@ -90,18 +90,18 @@ struct Narrow {
   // Pattern-mode state.  Scalars are wavefront-uniform; sp..u hold the
   // support members m = lane (index 0) and m = lane + 64 (index 1).
   struct Pat {
-    gbl<float>* gc;       // slot v: x_j^T x_{owner[v]} at gc[v*ldg + j] for j in A
-    gbl<float>* ng;       // feature -> ||G_{j,S}||_2 (zero coordinates of A)
-    gbl<int32_t>* pslot;  // feature -> slot, or -1
-    gbl<int32_t>* psup;   // feature -> index in S, or -1
+    gbl<float>* gc;       // slot v: x_{A[k]}^T x_{A[owner[v]]} at gc[v*ldg + k]
+    gbl<float>* ng;       // position -> ||G_{k,S}||_2 (zero coordinates of A)
+    gbl<int32_t>* pslot;  // position -> slot, or -1
+    gbl<int32_t>* npos;   // position -> position after the last compaction, or -1
     gbl<double>* c2;      // the other correlation buffer
     int64_t ldg;
     int ns;               // slots of this problem
     int gs_cap;           // LDS floats of the block
-    int* owner;           // LDS ns: feature whose column a slot holds, or -1
+    int* owner;           // LDS ns: position whose column a slot holds, or -1
     int* spos;            // LDS NSC: positions of S
     int* sfeat;           // LDS NSC: features of S when the block was built
-    int* pfeat;           // LDS NSC: features marked in psup
+    int* keep;            // LDS NSC: slots kept by a compaction
     int* bslot;           // LDS NBLD: slots of the columns being computed
     int* bfeat;           // LDS NBLD: their features
     float* stage;         // LDS NBLD x NMAX: those columns
@@ -109,7 +109,6 @@ struct Narrow {
     int s;                // |S|
     int gsp;              // column stride of gs (64 or 128)
     int s_t;              // |S| when the block was built (-1: never)
-    int npf;              // entries of pfeat
     int victim;           // round-robin cursor of the slot search
     bool valid;           // registers and block describe the current S and c
     bool ng_ok;           // ng holds the row norms for S over the current A
@@ -312,20 +311,25 @@ struct Narrow {
   }
 
   // Sphere test over A with ordered in-place compaction of A and c; screened
-  // nonzero coefficients are set to zero (dropped_nz is then set).
+  // nonzero coefficients are set to zero (dropped_nz is then set).  With np,
+  // the new position of every old one (-1 when dropped) is recorded; fv, a
+  // per-position array, moves with c.
   static __device__ __forceinline__ int test_compact(const Ctx& x, const GapInfo& g, int q, bool full,
-                                     bool& dropped_nz) {
+                                     bool& dropped_nz, gbl<int32_t>* np = nullptr,
+                                     gbl<float>* fv = nullptr) {
     int q2 = 0;
     bool dn = false;
     const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
     for (int base = 0; base < q; base += 256) {
       int jv[4];
       double cv[4], nv[4], bv[4];
+      float fw[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = base + 64 * u + x.lane;
         jv[u] = act_at(x, k, q, full);
         cv[u] = x.c[k < q ? k : q - 1];
+        fw[u] = fv ? fv[k < q ? k : q - 1] : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -346,7 +350,9 @@ struct Narrow {
         if (keep) {
           x.act[pos] = jv[u];
           x.c[pos] = cv[u];  // c of kept coordinates moves with them
+          if (fv) fv[pos] = fw[u];
         }
+        if (np && v) np[k] = keep ? pos : -1;
         q2 += __popcll(m);
       }
     }
@@ -510,12 +516,13 @@ struct Narrow {
   // ||Delta||_2 + ||delta||_2 < tau proves that every zero coordinate stays
   // at zero.  Otherwise the exact check runs over the Gram columns of S in
   // the global cache and, when it passes, moves the anchor to the new point.
+  // The global cache is indexed by position: it follows the compactions of
+  // A, and a new lambda starts it afresh.
 
-  // A new lambda: the active set restarts from all of {0..p-1}; cached
-  // columns and row norms only cover the old one.
+  // A new lambda: the active set restarts from all of {0..p-1}.
   static __device__ __forceinline__ void pattern_new_lambda(const Ctx& x, Pat& pt) {
     for (int v = x.lane; v < pt.ns; v += 64) pt.owner[v] = -1;
-    for (int j = x.lane; j < x.p; j += 64) pt.pslot[j] = -1;
+    for (int k = x.lane; k < x.p; k += 64) pt.pslot[k] = -1;
     pt.victim = 0;
     pt.valid = false;
     pt.ng_ok = false;
@@ -523,8 +530,61 @@ struct Narrow {
     __threadfence_block();
   }
 
+  // After a compaction of A from q_old positions (new positions in npos):
+  // the columns of the coordinates that stay in A with a nonzero coefficient
+  // move to their new positions, the other slots are freed.  In place,
+  // ascending: every destination is at most its source.
+  static __device__ __forceinline__ void gc_compact(const Ctx& x, Pat& pt, int q_old, int q_new) {
+    const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
+    int nk = 0;
+    for (int v0 = 0; v0 < pt.ns; v0 += 64) {
+      const int v = v0 + x.lane;
+      const int o = v < pt.ns ? pt.owner[v] : -1;
+      const int no = o >= 0 ? pt.npos[o] : -1;
+      const bool kp = no >= 0 && x.beta[x.act[no]] != 0.0;
+      wave_lds_order();
+      if (v < pt.ns) pt.owner[v] = kp ? no : -1;
+      const uint64_t m = ballot(kp);
+      if (kp) pt.keep[nk + __popcll(m & lt)] = v;
+      nk += __popcll(m);
+    }
+    wave_lds_order();
+    for (int k = x.lane; k < q_new; k += 64) pt.pslot[k] = -1;
+    for (int i = x.lane; i < nk; i += 64) {
+      const int v = pt.keep[i];
+      pt.pslot[pt.owner[v]] = v;
+    }
+    for (int base = 0; base < q_old; base += 256) {
+      int dd[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = base + 64 * t + x.lane;
+        dd[t] = k < q_old ? pt.npos[k] : -1;
+      }
+      for (int i0 = 0; i0 < nk; i0 += 8) {
+        float val[8][4];
+        gbl<float>* cols[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int v = i0 + i < nk ? __builtin_amdgcn_readfirstlane(pt.keep[i0 + i]) : 0;
+          cols[i] = pt.gc + (int64_t)v * pt.ldg + base + x.lane;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) val[i][t] = cols[i][64 * t];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i0 + i < nk)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (dd[t] >= 0) cols[i][dd[t] - base - x.lane] = val[i][t];
+      }
+    }
+    __threadfence_block();
+    wave_lds_order();
+  }
+
   // Gram columns of the nb features in bfeat into the slots bslot:
-  // gc[v*ldg + A[k]] = x_{A[k]}^T x_j for every position k < q, in one sweep.
+  // gc[v*ldg + k] = x_{A[k]}^T x_j for every position k < q, in one sweep.
   static __device__ __forceinline__ void build_cols(const Ctx& x, const Pat& pt, int q, bool full,
                                                     int nb) {
 #pragma unroll
@@ -551,12 +611,9 @@ struct Narrow {
     constexpr int UB = 2;
     for (int base = 0; base < q; base += UB * C) {
       XT xr[UB][RPL];
-      int jr[UB];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        jr[u] = act_at(x, base + u * C + x.slot, q, full);
-        L::load_raw(col(x, jr[u]), x.n, x.seg, x.ridx, xr[u]);
-      }
+      for (int u = 0; u < UB; ++u)
+        L::load_raw(col(x, act_at(x, base + u * C + x.slot, q, full)), x.n, x.seg, x.ridx, xr[u]);
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         const int k = base + u * C + x.slot;
@@ -571,67 +628,13 @@ struct Narrow {
               if (i + 1 < RPL) a1 = fmaf((float)xr[u][i + 1], v[b][i + 1], a1);
             }
             const double dsum = seg_sum<S>((double)a0 + (double)a1);
-            if (x.seg == 0 && k < q) dst[b][jr[u]] = (float)dsum;
+            if (x.seg == 0 && k < q) dst[b][k] = (float)dsum;
           }
         }
       }
     }
     __threadfence_block();
     wave_lds_order();
-  }
-
-  // Row norms ng_j = ||G_{j,S}||_2 of the zero coordinates of A and
-  // tau = min (lambda - |c_k|) / ng_k over them (c by position).
-  static __device__ __forceinline__ double row_norms_tau(const Ctx& x, const Pat& pt, int q,
-                                                         bool full, double lambda, bool recompute) {
-    const int s = pt.s;
-    double tau = INFINITY;
-    for (int base = 0; base < q; base += 256) {
-      int jv[4];
-      bool zv[4];
-      double cv[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = base + 64 * t + x.lane;
-        jv[t] = act_at(x, k, q, full);
-        cv[t] = x.c[k < q ? k : q - 1];
-        zv[t] = k < q && pt.psup[jv[t]] < 0;
-      }
-      float nv[4];
-      if (recompute) {
-        float a[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int m0 = 0; m0 < s; m0 += 4) {
-          float g[4][4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int m = m0 + u;
-            const int sl = m < s ? (m < 64 ? __builtin_amdgcn_readlane(pt.sl[0], m)
-                                           : __builtin_amdgcn_readlane(pt.sl[1], m - 64))
-                                 : 0;
-            const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) g[u][t] = m < s ? gcol[jv[t]] : 0.f;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) a[t] = fmaf(g[u][t], g[u][t], a[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          nv[t] = sqrtf(a[t]);
-          if (zv[t]) pt.ng[jv[t]] = nv[t];
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) nv[t] = pt.ng[jv[t]];
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (zv[t]) tau = fmin(tau, slack_ratio(cv[t], nv[t], lambda));
-    }
-    __threadfence_block();
-    return wave_min(tau);
   }
 
   // (lambda - |c|) / ng, with the FP32 row norm rounded up; a coordinate that
@@ -642,14 +645,77 @@ struct Narrow {
     return sl >= 0.0 ? INFINITY : -1.0;
   }
 
+  // Bit l of the result is set when position base + l is a member of S
+  // (members m0.. in ascending positions).
+  static __device__ __forceinline__ uint64_t row_members(const Pat& pt, int s, int base, int& m) {
+    uint64_t bits = 0;
+    for (; m < s; ++m) {
+      const int pm = __builtin_amdgcn_readfirstlane(pt.spos[m]);
+      if (pm >= base + 64) break;
+      bits |= 1ull << (pm - base);
+    }
+    return bits;
+  }
+
+  // Row norms ng_k = ||G_{k,S}||_2 of the zero coordinates of A (when
+  // recompute) and tau = min (lambda - |c_k|) / ng_k over them.
+  static __device__ __forceinline__ double row_norms_tau(const Ctx& x, const Pat& pt, int q,
+                                                         double lambda, bool recompute) {
+    const int s = __builtin_amdgcn_readfirstlane(pt.s);
+    double tau = INFINITY;
+    int mrow = 0;
+    for (int base = 0; base < q; base += 256) {
+      double cv[4];
+      bool zv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = base + 64 * t + x.lane;
+        cv[t] = x.c[k];
+        const uint64_t mb = row_members(pt, s, base + 64 * t, mrow);
+        zv[t] = k < q && !((mb >> x.lane) & 1ull);
+      }
+      float nv[4];
+      if (recompute) {
+        float a[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int m0 = 0; m0 < s; m0 += 8) {
+          float g[8][4];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int m = m0 + u;
+            const int sl = m < s ? (m < 64 ? __builtin_amdgcn_readlane(pt.sl[0], m)
+                                           : __builtin_amdgcn_readlane(pt.sl[1], m - 64))
+                                 : 0;
+            const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg + base + x.lane;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) g[u][t] = m < s ? gcol[64 * t] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[t] = fmaf(g[u][t], g[u][t], a[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          nv[t] = sqrtf(a[t]);
+          pt.ng[base + 64 * t + x.lane] = nv[t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) nv[t] = pt.ng[base + 64 * t + x.lane];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (zv[t]) tau = fmin(tau, slack_ratio(cv[t], nv[t], lambda));
+    }
+    __threadfence_block();
+    return wave_min(tau);
+  }
+
   // Sets up the pattern of the current coefficients over A (requires c =
   // X_A^T rho for the current beta).  Returns false when the support exceeds
   // the slots or the LDS block.
   static __device__ __forceinline__ bool pattern_setup(const Ctx& x, Pat& pt, int q, bool full,
                                                        double lambda, int (&stc)[kNumStats]) {
-    // unmark the previous support, then list the new one
-    for (int m = x.lane; m < pt.npf; m += 64) pt.psup[pt.pfeat[m]] = -1;
-    __threadfence_block();
     const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
     int s = 0;
     for (int base = 0; base < q; base += 64) {
@@ -659,33 +725,29 @@ struct Narrow {
       const bool nz = kq && x.beta[j] != 0.0;
       const uint64_t m = ballot(nz);
       const int idx = s + __popcll(m & lt);
-      if (nz && idx < NSC) {
-        pt.spos[idx] = k;
-        pt.pfeat[idx] = j;
-        pt.psup[j] = idx;
-      }
+      if (nz && idx < NSC) pt.spos[idx] = k;
       s += __popcll(m);
     }
-    pt.npf = min(s, NSC);
+    s = __builtin_amdgcn_readfirstlane(s);
     wave_lds_order();
-    __threadfence_block();
-    const int sp_stride = s > 64 ? 128 : 64;
-    if (s > pt.ns || s * sp_stride > pt.gs_cap) return false;
+    const int sps = s > 64 ? 128 : 64;
+    const int s8 = (s + 7) & ~7;
+    if (s > pt.ns || s8 * sps > pt.gs_cap) return false;
     ++stc[kStatSetups];
     pt.s = s;
-    pt.gsp = sp_stride;
+    pt.gsp = sps;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int m = x.lane + 64 * h;
       const bool v = m < s;
       const int k = v ? pt.spos[m] : 0;
       const int j = act_at(x, k, q, full);
-      pt.sp[h] = k;
+      pt.sp[h] = v ? k : 0x3fffffff;
       pt.sj[h] = j;
       pt.sb[h] = v ? x.beta[j] : 0.0;
       pt.sg[h] = pt.sb[h] > 0.0 ? 1.0 : -1.0;
       pt.id[h] = v ? (float)x.inv[j] : 0.f;
-      pt.sl[h] = v ? pt.pslot[j] : 0;
+      pt.sl[h] = v ? pt.pslot[k] : 0;
       pt.b0[h] = pt.sb[h];
       pt.u[h] = v ? (float)(x.c[k] - lambda * pt.sg[h]) * pt.id[h] : 0.f;
     }
@@ -713,19 +775,21 @@ struct Narrow {
           v = pt.victim;
           pt.victim = v + 1 < pt.ns ? v + 1 : 0;
           o = __builtin_amdgcn_readfirstlane(pt.owner[v]);
-          found = o < 0 || __builtin_amdgcn_readfirstlane(pt.psup[o]) < 0;
+          found = o < 0 || x.beta[act_at(x, o, q, full)] == 0.0;
         }
         if (!found) {
           failed = true;
           break;
         }
+        const int km = m < 64 ? __builtin_amdgcn_readlane(pt.sp[0], m)
+                              : __builtin_amdgcn_readlane(pt.sp[1], m - 64);
         const int jm = m < 64 ? __builtin_amdgcn_readlane(pt.sj[0], m)
                               : __builtin_amdgcn_readlane(pt.sj[1], m - 64);
         wave_lds_order();
         if (x.lane == 0) {
           if (o >= 0) pt.pslot[o] = -1;
-          pt.pslot[jm] = v;
-          pt.owner[v] = jm;
+          pt.pslot[km] = v;
+          pt.owner[v] = km;
           pt.bslot[nb] = v;
           pt.bfeat[nb] = jm;
         }
@@ -741,7 +805,7 @@ struct Narrow {
       stc[kStatBuilds] += nb;
     }
     if (failed) return false;
-    // the block and the row norms depend on the features of S only
+    // the block depends on the features of S only
     bool same = (s == pt.s_t);
     if (same) {
       bool diff = false;
@@ -754,22 +818,22 @@ struct Narrow {
     }
     if (!same) {
       ++stc[kStatSupportChanges];
-      for (int l = 0; l < s; ++l) {
-        const int vl = l < 64 ? __builtin_amdgcn_readlane(pt.sl[0], l)
-                              : __builtin_amdgcn_readlane(pt.sl[1], l - 64);
-        const int jl = l < 64 ? __builtin_amdgcn_readlane(pt.sj[0], l)
-                              : __builtin_amdgcn_readlane(pt.sj[1], l - 64);
+      // columns s..s8-1 are zero: the substitution runs whole groups of 8
+      for (int l = 0; l < s8; ++l) {
+        const int vl = l < s ? (l < 64 ? __builtin_amdgcn_readlane(pt.sl[0], l)
+                                       : __builtin_amdgcn_readlane(pt.sl[1], l - 64))
+                             : 0;
         const gbl<float>* gcol = pt.gc + (int64_t)vl * pt.ldg;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int m = x.lane + 64 * h;
-          if (m < sp_stride) {
-            float val = (m < s) ? gcol[pt.sj[h]] * pt.id[h] : 0.f;
+          if (m < sps) {
+            const int kk = m < s ? pt.sp[h] : 0;
+            float val = (l < s && m < s) ? gcol[kk] * pt.id[h] : 0.f;
             if (m == l) val = 1.f;
-            pt.gs[l * sp_stride + m] = val;
+            pt.gs[l * sps + m] = val;
           }
         }
-        (void)jl;
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -780,7 +844,7 @@ struct Narrow {
       pt.ng_ok = false;
       wave_lds_order();
     }
-    pt.tau = row_norms_tau(x, pt, q, full, lambda, !pt.ng_ok);
+    pt.tau = row_norms_tau(x, pt, q, lambda, !pt.ng_ok);
     pt.ng_ok = true;
     pt.valid = true;
     return true;
@@ -793,51 +857,55 @@ struct Narrow {
   // c_k - accP - accD (written to c2).  Returns true when every zero
   // coordinate stays at zero; tau_new is the slack ratio at the new anchor.
   static __device__ __forceinline__ bool pattern_exact(const Ctx& x, const Pat& pt, int q,
-                                                       bool full, double lambda,
-                                                       const float (&d)[2], const float (&dp)[2],
-                                                       double& tau_new) {
-    const int s = pt.s;
+                                                       double lambda, const float (&d)[2],
+                                                       const float (&dp)[2], double& tau_new) {
+    const int s = __builtin_amdgcn_readfirstlane(pt.s);
     bool bad = false;
     double tau = INFINITY;
     for (int base = 0; base < q; base += 256) {
-      int jv[4], mf[4];
+      int mf[4];
       double cv[4];
       float accP[4], accD[4], part[4];
-      bool isS[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int k = base + 64 * t + x.lane;
-        jv[t] = act_at(x, k, q, full);
-        cv[t] = x.c[k < q ? k : q - 1];
+        cv[t] = x.c[base + 64 * t + x.lane];
         const int bound = base + 64 * t;
         mf[t] = __popcll(ballot(x.lane < s && pt.sp[0] < bound)) +
                 __popcll(ballot(x.lane + 64 < s && pt.sp[1] < bound));
         accP[t] = accD[t] = part[t] = 0.f;
-        isS[t] = false;
       }
-      for (int m0 = 0; m0 < s; m0 += 4) {
-        float g[4][4], dm[4], pm[4];
-        int pos[4];
+      uint64_t isS[4] = {0, 0, 0, 0};
+      for (int m0 = 0; m0 < s; m0 += 8) {
+        float g[8][4], dm[8], pm[8];
+        int pos[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const int m = m0 + u;
           const bool mv = m < s;
-          const int h = m < 64 ? 0 : 1;
           const int ml = m & 63;
-          const int sl = mv ? (h ? __builtin_amdgcn_readlane(pt.sl[1], ml)
-                                 : __builtin_amdgcn_readlane(pt.sl[0], ml))
-                            : 0;
-          dm[u] = mv ? (h ? readlane_f(d[1], ml) : readlane_f(d[0], ml)) : 0.f;
-          pm[u] = mv ? (h ? readlane_f(dp[1], ml) : readlane_f(dp[0], ml)) : 0.f;
-          pos[u] = mv ? (h ? __builtin_amdgcn_readlane(pt.sp[1], ml)
-                           : __builtin_amdgcn_readlane(pt.sp[0], ml))
-                      : -1000000;
-          const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg;
+          int sl;
+          if (m < 64) {
+            sl = __builtin_amdgcn_readlane(pt.sl[0], ml);
+            dm[u] = readlane_f(d[0], ml);
+            pm[u] = readlane_f(dp[0], ml);
+            pos[u] = __builtin_amdgcn_readlane(pt.sp[0], ml);
+          } else {
+            sl = __builtin_amdgcn_readlane(pt.sl[1], ml);
+            dm[u] = readlane_f(d[1], ml);
+            pm[u] = readlane_f(dp[1], ml);
+            pos[u] = __builtin_amdgcn_readlane(pt.sp[1], ml);
+          }
+          if (!mv) {
+            sl = 0;
+            dm[u] = pm[u] = 0.f;
+            pos[u] = 0x3fffffff;
+          }
+          const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg + base + x.lane;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) g[u][t] = mv ? gcol[jv[t]] : 0.f;
+          for (int t = 0; t < 4; ++t) g[u][t] = mv ? gcol[64 * t] : 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const int m = m0 + u;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
@@ -846,8 +914,8 @@ struct Narrow {
             accD[t] = fmaf(g[u][t], dm[u], accD[t]);
             const int dd = pos[u] - (base + 64 * t);
             if (dd >= 0 && dd < 64) {  // member inside row t
+              isS[t] |= 1ull << dd;
               if (x.lane > dd) part[t] = fmaf(g[u][t], dm[u], part[t]);
-              if (x.lane == dd) isS[t] = true;
             }
           }
         }
@@ -859,10 +927,10 @@ struct Narrow {
         if (k < q) {
           const double cn = cv[t] - ((double)accP[t] + (double)accD[t]);
           pt.c2[k] = cn;
-          if (!isS[t]) {
+          if (!((isS[t] >> x.lane) & 1ull)) {
             const double vis = cv[t] - (double)accP[t] - (double)part[t];
             if (fabs(vis) > lambda) bad = true;
-            tau = fmin(tau, slack_ratio(cn, pt.ng[jv[t]], lambda));
+            tau = fmin(tau, slack_ratio(cn, pt.ng[k], lambda));
           }
         }
       }
@@ -872,42 +940,67 @@ struct Narrow {
     return ballot(bad) == 0;
   }
 
-  // One cyclic CD epoch over A by the pattern mode.  Returns 0 when the
-  // premise fails (nothing written), 1 when committed, 2 when committed and
-  // no coefficient moved (the state is a fixed point of the epoch).
-  static __device__ __forceinline__ int pattern_epoch(Ctx& x, Pat& pt, int q, bool full,
-                                                      double lambda, int (&stc)[kNumStats]) {
-    const int s = pt.s;
-    const int sps = pt.gsp;
-    float u[2] = {pt.u[0], pt.u[1]};
-    float d[2] = {0.f, 0.f};
-    const bool two = s > 64;
-    // forward substitution on the scaled block: delta_l = u_l, u -= delta_l col_l
-    for (int l0 = 0; l0 < s; l0 += 8) {
-      float t0[8], t1[8];
+  // Forward substitution on the scaled block over s8 steps (a multiple of
+  // 8; the columns beyond s are zero): delta_l = u_l, u -= delta_l col_l.
+  template <int SPS>
+  static __device__ __forceinline__ void substitute(const Ctx& x, const Pat& pt, int s8,
+                                                    float (&u)[2], float (&d)[2]) {
+    const float* base = pt.gs + x.lane;
+    float t0[8], t1[8], n0[8], n1[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      t0[v] = base[v * SPS];
+      t1[v] = SPS == 128 ? base[v * SPS + 64] : 0.f;
+    }
+    for (int l0 = 0; l0 < s8; l0 += 8) {
+      // the next group's columns load while this group's steps run
+      const float* nb = base + (l0 + 8 < s8 ? l0 + 8 : l0) * SPS;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const int l = l0 + v;
-        const float* colp = pt.gs + (l < s ? l : 0) * sps;
-        t0[v] = colp[x.lane];
-        t1[v] = two ? colp[64 + x.lane] : 0.f;
+        n0[v] = nb[v * SPS];
+        n1[v] = SPS == 128 ? nb[v * SPS + 64] : 0.f;
       }
+      if (SPS == 64 || l0 < 64) {
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int l = l0 + v;
-        if (l < s) {
-          float dl;
-          if (l < 64) {
-            dl = readlane_f(u[0], l);
-            if (x.lane == l) d[0] = dl;
-          } else {
-            dl = readlane_f(u[1], l - 64);
-            if (x.lane == l - 64) d[1] = dl;
-          }
+        for (int v = 0; v < 8; ++v) {
+          const int l = l0 + v;
+          const float dl = readlane_f(u[0], l);
+          d[0] = x.lane == l ? dl : d[0];
+          u[0] = fmaf(-t0[v], dl, u[0]);
+          if (SPS == 128) u[1] = fmaf(-t1[v], dl, u[1]);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int l = l0 + v - 64;
+          const float dl = readlane_f(u[1], l);
+          d[1] = x.lane == l ? dl : d[1];
           u[0] = fmaf(-t0[v], dl, u[0]);
           u[1] = fmaf(-t1[v], dl, u[1]);
         }
       }
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        t0[v] = n0[v];
+        t1[v] = n1[v];
+      }
+    }
+  }
+
+  // One cyclic CD epoch over A by the pattern mode.  Returns 0 when the
+  // premise fails (nothing written), 1 when committed, 2 when committed and
+  // no coefficient moved (the state is a fixed point of the epoch).
+  static __device__ __forceinline__ int pattern_epoch(Ctx& x, Pat& pt, int q, double lambda,
+                                                      int (&stc)[kNumStats]) {
+    const int s = __builtin_amdgcn_readfirstlane(pt.s);
+    const int s8 = (s + 7) & ~7;
+    float u[2] = {pt.u[0], pt.u[1]};
+    float d[2] = {0.f, 0.f};
+    if (s8 > 0) {
+      if (pt.gsp == 64)
+        substitute<64>(x, pt, s8, u, d);
+      else
+        substitute<128>(x, pt, s8, u, d);
     }
     double bn[2];
     float dp[2];
@@ -934,7 +1027,7 @@ struct Narrow {
     double tau_new = 0.0;
     if (!(reach < pt.tau)) {
       ++stc[kStatExact];
-      if (!pattern_exact(x, pt, q, full, lambda, d, dp, tau_new)) return 0;
+      if (!pattern_exact(x, pt, q, lambda, d, dp, tau_new)) return 0;
       reanchor = true;
     }
     // commit
@@ -983,8 +1076,8 @@ __device__ __forceinline__ void bind_lds(typename N::Ctx& x, typename N::Pat& pt
   pt.owner = x.rows_l + N::NMAX;
   pt.spos = pt.owner + N::NSC;
   pt.sfeat = pt.spos + N::NSC;
-  pt.pfeat = pt.sfeat + N::NSC;
-  pt.bslot = pt.pfeat + N::NSC;
+  pt.keep = pt.sfeat + N::NSC;
+  pt.bslot = pt.keep + N::NSC;
   pt.bfeat = pt.bslot + N::NBLD;
   pt.stage = reinterpret_cast<float*>(pt.bfeat + N::NBLD);
   pt.gs = reinterpret_cast<float*>(smem + GOFF);
@@ -1030,20 +1123,17 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     pt.gc = gptr(d.gc);
     pt.ng = gptr(d.ng);
     pt.pslot = gptr(d.pslot);
-    pt.psup = gptr(d.psup);
+    pt.npos = gptr(d.npos);
     pt.c2 = gptr(d.c2);
     pt.ldg = d.ldg;
     pt.ns = d.ns;
     pt.s = 0;
     pt.gsp = 64;
     pt.s_t = -1;
-    pt.npf = 0;
     pt.victim = 0;
     pt.valid = false;
     pt.ng_ok = false;
     pt.tau = 0.0;
-    if (opts.pattern)
-      for (int j = lane; j < d.p; j += 64) pt.psup[j] = -1;
     int stc[kNumStats];
 #pragma unroll
     for (int i = 0; i < kNumStats; ++i) stc[i] = 0;
@@ -1150,8 +1240,13 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
             }
             if (k == K) break;
             bool dropped;
-            q = N::test_compact(x, g, q, full, dropped);
+            const int q_old = q;
+            const bool was_full = full;
+            q = N::test_compact(x, g, q, full, dropped, pat_on ? pt.npos : nullptr,
+                                pat_on ? pt.ng : nullptr);
             full = false;
+            // (right after a new lambda no column is cached yet)
+            if (pat_on && !was_full && q != q_old) N::gc_compact(x, pt, q_old, q);
             rho_ok = true;
             c_ok = true;
             if (dropped) {
@@ -1178,7 +1273,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
                   continue;
                 }
               }
-              const int r = N::pattern_epoch(x, pt, q, full, lambda, stc);
+              const int r = N::pattern_epoch(x, pt, q, lambda, stc);
               if (r) {
                 ++stc[kStatPatternEpochs];
                 ++k;

@@ -155,6 +155,7 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   d->ng = cv.take<float>(ldg);
   d->pslot = cv.take<int32_t>(ldg);
   d->npos = cv.take<int32_t>(ldg);
+  d->pmem = cv.take<int32_t>(ldg);
   d->c2 = cv.take<double>(ldg);
   d->ldg = ldg;
   d->ns = ns;

@@ -38,6 +38,7 @@ struct ProbDesc {
   float* ng;        // ldg: ||G_{k,S}||_2 of the zero coordinates of A
   int32_t* pslot;   // ldg: slot holding the Gram column of position k, or -1
   int32_t* npos;    // ldg: position after the last compaction, or -1
+  int32_t* pmem;    // ldg: 1 when position k is in the support list, else 0
   double* c2;       // ldg: second buffer of the correlations c
   int64_t ldg;      // p rounded up to a multiple of 256
   int32_t ns;       // Gram slots of this problem (<= kSlotsMax)

@@ -53,6 +53,13 @@ namespace gs {
 __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
+// v with lane LANE replaced by the uniform value w (one v_writelane_b32).
+template <int LANE>
+__device__ __forceinline__ float writelane_f(float v, float w) {
+  int r = __float_as_int(v);
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(r) : "s"(__float_as_int(w)), "i"(LANE));
+  return __int_as_float(r);
+}
 
 template <typename XT, int VEC, int S, int NG, bool GATHER>
 struct Narrow {
@@ -94,6 +101,7 @@ struct Narrow {
     gbl<float>* ng;       // position -> ||G_{k,S}||_2 (zero coordinates of A)
     gbl<int32_t>* pslot;  // position -> slot, or -1
     gbl<int32_t>* npos;   // position -> position after the last compaction, or -1
+    gbl<int32_t>* pmem;   // position -> 1 when in S, else 0 (set up with S)
     gbl<double>* c2;      // the other correlation buffer
     int64_t ldg;
     int ns;               // slots of this problem
@@ -556,27 +564,25 @@ struct Narrow {
     }
     for (int base = 0; base < q_old; base += 256) {
       int dd[4];
+      ld4(pt.npos + base + 4 * x.lane, dd);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = base + 64 * t + x.lane;
-        dd[t] = k < q_old ? pt.npos[k] : -1;
-      }
+      for (int e = 0; e < 4; ++e)
+        if (base + 4 * x.lane + e >= q_old) dd[e] = -1;
       for (int i0 = 0; i0 < nk; i0 += 8) {
         float val[8][4];
         gbl<float>* cols[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int v = i0 + i < nk ? __builtin_amdgcn_readfirstlane(pt.keep[i0 + i]) : 0;
-          cols[i] = pt.gc + (int64_t)v * pt.ldg + base + x.lane;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) val[i][t] = cols[i][64 * t];
+          cols[i] = pt.gc + (int64_t)v * pt.ldg;
+          ld4(cols[i] + base + 4 * x.lane, val[i]);
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i)
           if (i0 + i < nk)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (dd[t] >= 0) cols[i][dd[t] - base - x.lane] = val[i][t];
+            for (int e = 0; e < 4; ++e)
+              if (dd[e] >= 0) cols[i][dd[e]] = val[i][e];
       }
     }
     __threadfence_block();
@@ -637,6 +643,23 @@ struct Narrow {
     wave_lds_order();
   }
 
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ void ld4(const gbl<float>* p, float (&o)[4]) {
+    const f4 v = *reinterpret_cast<const gbl<f4>*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+  static __device__ __forceinline__ void ld4(const gbl<double>* p, double (&o)[4]) {
+    const d2 a = *reinterpret_cast<const gbl<d2>*>(p);
+    const d2 b = *reinterpret_cast<const gbl<d2>*>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+  static __device__ __forceinline__ void ld4(const gbl<int32_t>* p, int (&o)[4]) {
+    const i4 v = *reinterpret_cast<const gbl<i4>*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+
   // (lambda - |c|) / ng, with the FP32 row norm rounded up; a coordinate that
   // no support column touches stays at zero iff |c| <= lambda.
   static __device__ __forceinline__ double slack_ratio(double c, float ng, double lambda) {
@@ -645,36 +668,20 @@ struct Narrow {
     return sl >= 0.0 ? INFINITY : -1.0;
   }
 
-  // Bit l of the result is set when position base + l is a member of S
-  // (members m0.. in ascending positions).
-  static __device__ __forceinline__ uint64_t row_members(const Pat& pt, int s, int base, int& m) {
-    uint64_t bits = 0;
-    for (; m < s; ++m) {
-      const int pm = __builtin_amdgcn_readfirstlane(pt.spos[m]);
-      if (pm >= base + 64) break;
-      bits |= 1ull << (pm - base);
-    }
-    return bits;
-  }
-
   // Row norms ng_k = ||G_{k,S}||_2 of the zero coordinates of A (when
-  // recompute) and tau = min (lambda - |c_k|) / ng_k over them.
+  // recompute) and tau = min (lambda - |c_k|) / ng_k over them.  Lane
+  // positions base + 4 lane + e.
   static __device__ __forceinline__ double row_norms_tau(const Ctx& x, const Pat& pt, int q,
                                                          double lambda, bool recompute) {
     const int s = __builtin_amdgcn_readfirstlane(pt.s);
     double tau = INFINITY;
-    int mrow = 0;
     for (int base = 0; base < q; base += 256) {
+      const int k0 = base + 4 * x.lane;
       double cv[4];
-      bool zv[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = base + 64 * t + x.lane;
-        cv[t] = x.c[k];
-        const uint64_t mb = row_members(pt, s, base + 64 * t, mrow);
-        zv[t] = k < q && !((mb >> x.lane) & 1ull);
-      }
+      int mb[4];
       float nv[4];
+      ld4(x.c + k0, cv);
+      ld4(pt.pmem + k0, mb);
       if (recompute) {
         float a[4] = {0.f, 0.f, 0.f, 0.f};
         for (int m0 = 0; m0 < s; m0 += 8) {
@@ -685,27 +692,24 @@ struct Narrow {
             const int sl = m < s ? (m < 64 ? __builtin_amdgcn_readlane(pt.sl[0], m)
                                            : __builtin_amdgcn_readlane(pt.sl[1], m - 64))
                                  : 0;
-            const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg + base + x.lane;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) g[u][t] = m < s ? gcol[64 * t] : 0.f;
+            ld4(pt.gc + (int64_t)sl * pt.ldg + k0, g[u]);
+            if (m >= s) g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0.f;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[t] = fmaf(g[u][t], g[u][t], a[t]);
+            for (int e = 0; e < 4; ++e) a[e] = fmaf(g[u][e], g[u][e], a[e]);
         }
+        typedef float f4v __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          nv[t] = sqrtf(a[t]);
-          pt.ng[base + 64 * t + x.lane] = nv[t];
-        }
+        for (int e = 0; e < 4; ++e) nv[e] = sqrtf(a[e]);
+        *reinterpret_cast<gbl<f4v>*>(pt.ng + k0) = f4v{nv[0], nv[1], nv[2], nv[3]};
       } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) nv[t] = pt.ng[base + 64 * t + x.lane];
+        ld4(pt.ng + k0, nv);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (zv[t]) tau = fmin(tau, slack_ratio(cv[t], nv[t], lambda));
+      for (int e = 0; e < 4; ++e)
+        if (k0 + e < q && !mb[e]) tau = fmin(tau, slack_ratio(cv[e], nv[e], lambda));
     }
     __threadfence_block();
     return wave_min(tau);
@@ -718,17 +722,26 @@ struct Narrow {
                                                        double lambda, int (&stc)[kNumStats]) {
     const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
     int s = 0;
-    for (int base = 0; base < q; base += 64) {
-      const int k = base + x.lane;
-      const bool kq = k < q;
-      const int j = act_at(x, k, q, full);
-      const bool nz = kq && x.beta[j] != 0.0;
-      const uint64_t m = ballot(nz);
-      const int idx = s + __popcll(m & lt);
-      if (nz && idx < NSC) pt.spos[idx] = k;
-      s += __popcll(m);
+    for (int base = 0; base < q; base += 256) {
+      int jv[4];
+      double bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) jv[t] = act_at(x, base + 64 * t + x.lane, q, full);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[t] = x.beta[jv[t]];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = base + 64 * t + x.lane;
+        const bool nz = k < q && bv[t] != 0.0;
+        const uint64_t m = ballot(nz);
+        const int idx = s + __popcll(m & lt);
+        if (nz && idx < NSC) pt.spos[idx] = k;
+        if (k < q) pt.pmem[k] = nz ? 1 : 0;
+        s += __popcll(m);
+      }
     }
     s = __builtin_amdgcn_readfirstlane(s);
+    __threadfence_block();
     wave_lds_order();
     const int sps = s > 64 ? 128 : 64;
     const int s8 = (s + 7) & ~7;
@@ -850,12 +863,43 @@ struct Narrow {
     return true;
   }
 
+  // Loads the Gram entries of members m0..m0+7 (< hi) at the lane's four
+  // positions k0..k0+3, with their steps d and offsets dp.
+  static __device__ __forceinline__ void member_group(const Pat& pt, int m0, int hi, int k0,
+                                                      const float (&d)[2], const float (&dp)[2],
+                                                      float (&g)[8][4], float (&dm)[8],
+                                                      float (&pm)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int m = m0 + u;
+      const int ml = m & 63;
+      int sl;
+      if (m < 64) {
+        sl = __builtin_amdgcn_readlane(pt.sl[0], ml);
+        dm[u] = readlane_f(d[0], ml);
+        pm[u] = readlane_f(dp[0], ml);
+      } else {
+        sl = __builtin_amdgcn_readlane(pt.sl[1], ml);
+        dm[u] = readlane_f(d[1], ml);
+        pm[u] = readlane_f(dp[1], ml);
+      }
+      if (m >= hi) {
+        sl = 0;
+        dm[u] = pm[u] = 0.f;
+      }
+      ld4(pt.gc + (int64_t)sl * pt.ldg + k0, g[u]);
+      if (m >= hi) g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0.f;
+    }
+  }
+
   // The exact zero-coordinate check of an epoch (steps d, previous offset dp
   // = beta_S - beta0, both FP32): for every position k, with accP = G_{k,S} dp
   // and accD = G_{k,S} d, the coordinate's correlation at its visit is
   // c_k - accP - (accD over members before k); the new anchor value is
   // c_k - accP - accD (written to c2).  Returns true when every zero
   // coordinate stays at zero; tau_new is the slack ratio at the new anchor.
+  // Lane positions base + 4 lane + e; the members split into those before
+  // the 256-position block, inside it and after it.
   static __device__ __forceinline__ bool pattern_exact(const Ctx& x, const Pat& pt, int q,
                                                        double lambda, const float (&d)[2],
                                                        const float (&dp)[2], double& tau_new) {
@@ -863,128 +907,132 @@ struct Narrow {
     bool bad = false;
     double tau = INFINITY;
     for (int base = 0; base < q; base += 256) {
-      int mf[4];
+      const int k0 = base + 4 * x.lane;
+      const int lo = __popcll(ballot(x.lane < s && pt.sp[0] < base)) +
+                     __popcll(ballot(x.lane + 64 < s && pt.sp[1] < base));
+      const int hi = __popcll(ballot(x.lane < s && pt.sp[0] < base + 256)) +
+                     __popcll(ballot(x.lane + 64 < s && pt.sp[1] < base + 256));
       double cv[4];
-      float accP[4], accD[4], part[4];
+      int mb[4];
+      ld4(x.c + k0, cv);
+      ld4(pt.pmem + k0, mb);
+      float accP[4] = {0.f, 0.f, 0.f, 0.f}, accD[4] = {0.f, 0.f, 0.f, 0.f}, part[4];
+      float g[8][4], dm[8], pm[8];
+      // members before the block: every position sees their steps
+      for (int m0 = 0; m0 < lo; m0 += 8) {
+        member_group(pt, m0, lo, k0, d, dp, g, dm, pm);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        cv[t] = x.c[base + 64 * t + x.lane];
-        const int bound = base + 64 * t;
-        mf[t] = __popcll(ballot(x.lane < s && pt.sp[0] < bound)) +
-                __popcll(ballot(x.lane + 64 < s && pt.sp[1] < bound));
-        accP[t] = accD[t] = part[t] = 0.f;
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            accP[e] = fmaf(g[u][e], pm[u], accP[e]);
+            accD[e] = fmaf(g[u][e], dm[u], accD[e]);
+          }
       }
-      uint64_t isS[4] = {0, 0, 0, 0};
-      for (int m0 = 0; m0 < s; m0 += 8) {
-        float g[8][4], dm[8], pm[8];
-        int pos[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) part[e] = accD[e];
+      // members inside: position k sees the steps of those before it
+      for (int m0 = lo; m0 < hi; m0 += 8) {
+        member_group(pt, m0, hi, k0, d, dp, g, dm, pm);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int m = m0 + u;
-          const bool mv = m < s;
-          const int ml = m & 63;
-          int sl;
-          if (m < 64) {
-            sl = __builtin_amdgcn_readlane(pt.sl[0], ml);
-            dm[u] = readlane_f(d[0], ml);
-            pm[u] = readlane_f(dp[0], ml);
-            pos[u] = __builtin_amdgcn_readlane(pt.sp[0], ml);
-          } else {
-            sl = __builtin_amdgcn_readlane(pt.sl[1], ml);
-            dm[u] = readlane_f(d[1], ml);
-            pm[u] = readlane_f(dp[1], ml);
-            pos[u] = __builtin_amdgcn_readlane(pt.sp[1], ml);
-          }
-          if (!mv) {
-            sl = 0;
-            dm[u] = pm[u] = 0.f;
-            pos[u] = 0x3fffffff;
-          }
-          const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg + base + x.lane;
+          const int pos = m < 64 ? __builtin_amdgcn_readlane(pt.sp[0], m & 63)
+                                 : __builtin_amdgcn_readlane(pt.sp[1], m & 63);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) g[u][t] = mv ? gcol[64 * t] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int m = m0 + u;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (m == mf[t]) part[t] = accD[t];  // members before row t are summed
-            accP[t] = fmaf(g[u][t], pm[u], accP[t]);
-            accD[t] = fmaf(g[u][t], dm[u], accD[t]);
-            const int dd = pos[u] - (base + 64 * t);
-            if (dd >= 0 && dd < 64) {  // member inside row t
-              isS[t] |= 1ull << dd;
-              if (x.lane > dd) part[t] = fmaf(g[u][t], dm[u], part[t]);
-            }
+          for (int e = 0; e < 4; ++e) {
+            accP[e] = fmaf(g[u][e], pm[u], accP[e]);
+            accD[e] = fmaf(g[u][e], dm[u], accD[e]);
+            const float w = (m < hi && pos < k0 + e) ? dm[u] : 0.f;
+            part[e] = fmaf(g[u][e], w, part[e]);
           }
         }
       }
+      // members after the block
+      for (int m0 = hi; m0 < s; m0 += 8) {
+        member_group(pt, m0, s, k0, d, dp, g, dm, pm);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (mf[t] >= s) part[t] = accD[t];
-        const int k = base + 64 * t + x.lane;
-        if (k < q) {
-          const double cn = cv[t] - ((double)accP[t] + (double)accD[t]);
-          pt.c2[k] = cn;
-          if (!((isS[t] >> x.lane) & 1ull)) {
-            const double vis = cv[t] - (double)accP[t] - (double)part[t];
-            if (fabs(vis) > lambda) bad = true;
-            tau = fmin(tau, slack_ratio(cn, pt.ng[k], lambda));
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            accP[e] = fmaf(g[u][e], pm[u], accP[e]);
+            accD[e] = fmaf(g[u][e], dm[u], accD[e]);
           }
+      }
+      typedef double d2v __attribute__((ext_vector_type(2)));
+      double cn[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cn[e] = cv[e] - ((double)accP[e] + (double)accD[e]);
+        if (k0 + e < q && !mb[e]) {
+          const double vis = cv[e] - (double)accP[e] - (double)part[e];
+          if (fabs(vis) > lambda) bad = true;
         }
       }
+      // positions >= q of the block hold values nobody reads
+      *reinterpret_cast<gbl<d2v>*>(pt.c2 + k0) = d2v{cn[0], cn[1]};
+      *reinterpret_cast<gbl<d2v>*>(pt.c2 + k0 + 2) = d2v{cn[2], cn[3]};
+      float nv[4];
+      ld4(pt.ng + k0, nv);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (k0 + e < q && !mb[e]) tau = fmin(tau, slack_ratio(cn[e], nv[e], lambda));
     }
     __threadfence_block();
     tau_new = wave_min(tau);
     return ballot(bad) == 0;
   }
 
-  // Forward substitution on the scaled block over s8 steps (a multiple of
-  // 8; the columns beyond s are zero): delta_l = u_l, u -= delta_l col_l.
-  template <int SPS>
-  static __device__ __forceinline__ void substitute(const Ctx& x, const Pat& pt, int s8,
-                                                    float (&u)[2], float (&d)[2]) {
-    const float* base = pt.gs + x.lane;
-    float t0[8], t1[8], n0[8], n1[8];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      t0[v] = base[v * SPS];
-      t1[v] = SPS == 128 ? base[v * SPS + 64] : 0.f;
-    }
-    for (int l0 = 0; l0 < s8; l0 += 8) {
-      // the next group's columns load while this group's steps run
-      const float* nb = base + (l0 + 8 < s8 ? l0 + 8 : l0) * SPS;
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        n0[v] = nb[v * SPS];
-        n1[v] = SPS == 128 ? nb[v * SPS + 64] : 0.f;
-      }
-      if (SPS == 64 || l0 < 64) {
+  // Forward substitution on the scaled block: delta_l = u_l, u -= delta_l
+  // col_l, for l < s8 (a multiple of 8; the columns beyond s are zero).
+  // Group G holds the steps 8G..8G+7 with compile-time lanes; its columns
+  // were loaded by the previous group, which also loads the next ones.
+  template <int SPS, int G>
+  static __device__ __forceinline__ void subst_group(const Ctx& x, const Pat& pt, int s8,
+                                                     float (&u)[2], float (&d)[2],
+                                                     const float (&t0)[8], const float (&t1)[8]) {
+    if constexpr (G * 8 < (SPS == 64 ? 64 : 128)) {
+      if (G * 8 < s8) {
+        float n0[8], n1[8];
+        const float* nb = pt.gs + x.lane + ((G + 1) * 8 < s8 ? (G + 1) * 8 : G * 8) * SPS;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-          const int l = l0 + v;
-          const float dl = readlane_f(u[0], l);
-          d[0] = x.lane == l ? dl : d[0];
+          n0[v] = nb[v * SPS];
+          n1[v] = SPS == 128 ? nb[v * SPS + 64] : 0.f;
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          constexpr int H = G * 8 >= 64 ? 1 : 0;
+          const float dl = readlane_f(u[H], (G * 8 + v) & 63);
+          switch (v) {  // compile-time lane of the step
+            case 0: d[H] = writelane_f<(G * 8 + 0) & 63>(d[H], dl); break;
+            case 1: d[H] = writelane_f<(G * 8 + 1) & 63>(d[H], dl); break;
+            case 2: d[H] = writelane_f<(G * 8 + 2) & 63>(d[H], dl); break;
+            case 3: d[H] = writelane_f<(G * 8 + 3) & 63>(d[H], dl); break;
+            case 4: d[H] = writelane_f<(G * 8 + 4) & 63>(d[H], dl); break;
+            case 5: d[H] = writelane_f<(G * 8 + 5) & 63>(d[H], dl); break;
+            case 6: d[H] = writelane_f<(G * 8 + 6) & 63>(d[H], dl); break;
+            default: d[H] = writelane_f<(G * 8 + 7) & 63>(d[H], dl); break;
+          }
           u[0] = fmaf(-t0[v], dl, u[0]);
           if (SPS == 128) u[1] = fmaf(-t1[v], dl, u[1]);
         }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int l = l0 + v - 64;
-          const float dl = readlane_f(u[1], l);
-          d[1] = x.lane == l ? dl : d[1];
-          u[0] = fmaf(-t0[v], dl, u[0]);
-          u[1] = fmaf(-t1[v], dl, u[1]);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        t0[v] = n0[v];
-        t1[v] = n1[v];
+        subst_group<SPS, G + 1>(x, pt, s8, u, d, n0, n1);
       }
     }
+  }
+
+  template <int SPS>
+  static __device__ __forceinline__ void substitute(const Ctx& x, const Pat& pt, int s8,
+                                                    float (&u)[2], float (&d)[2]) {
+    float t0[8], t1[8];
+    const float* b0 = pt.gs + x.lane;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      t0[v] = b0[v * SPS];
+      t1[v] = SPS == 128 ? b0[v * SPS + 64] : 0.f;
+    }
+    subst_group<SPS, 0>(x, pt, s8, u, d, t0, t1);
   }
 
   // One cyclic CD epoch over A by the pattern mode.  Returns 0 when the
@@ -1124,6 +1172,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     pt.ng = gptr(d.ng);
     pt.pslot = gptr(d.pslot);
     pt.npos = gptr(d.npos);
+    pt.pmem = gptr(d.pmem);
     pt.c2 = gptr(d.c2);
     pt.ldg = d.ldg;
     pt.ns = d.ns;

@@ -101,7 +101,9 @@ enum {
   GS_STAT_PASSES,             /* screening passes                             */
   GS_STAT_SKIPPED,            /* epochs skipped at an exact fixed point       */
   GS_STAT_EXACT,              /* pattern epochs whose zero coordinates needed
-                                 the exact check (the norm bound did not hold) */
+                                 the exact check over the whole active set   */
+  GS_STAT_NEAR,               /* pattern epochs where the norm bound left at
+                                 most 64 zero coordinates, checked exactly   */
   GS_NSTATS
 };
 

@@ -62,7 +62,7 @@ class gs_opts(ctypes.Structure):
 
 # Names of the GS_NSTATS counters of gs_opts.stats, in index order.
 STAT_NAMES = ["pattern_epochs", "residual_epochs", "rejected", "builds", "setups",
-              "support_changes", "passes", "skipped", "exact_checks"]
+              "support_changes", "passes", "skipped", "exact_checks", "near_checks"]
 
 EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
            "lasso_solve_batch", "screen_workspace_size", "screen", "gs_timing_enable",

@@ -139,8 +139,8 @@ int pattern_slots(const gs_problem* pr) {
   return std::max(1, std::min({kSlotsMax, pr->p, want}));
 }
 
-// Per-problem workspace arrays.  The pattern mode's position-indexed arrays
-// hold ldg entries (p rounded up to 256).
+// Per-problem workspace arrays.  The pattern mode's arrays hold ldg entries
+// (p rounded up to 256).
 void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   const int64_t ldg = (int64_t)align_up((size_t)pr->p, 256);
   const int ns = pattern_slots(pr);
@@ -154,7 +154,6 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   d->gc = cv.take<float>((size_t)ns * ldg);
   d->ng = cv.take<float>(ldg);
   d->pslot = cv.take<int32_t>(ldg);
-  d->npos = cv.take<int32_t>(ldg);
   d->pmem = cv.take<int32_t>(ldg);
   d->c2 = cv.take<double>(ldg);
   d->ldg = ldg;

@@ -32,12 +32,11 @@ struct ProbDesc {
   int32_t* act;   // 2p: active set (two buffers for the wide schedule)
   double* lam;    // T: lambdas (caller values on entry, absolute after init)
   double* rho;    // n: residual (wide schedule)
-  // pattern mode of the narrow schedule; position-indexed arrays hold ldg
-  // entries, so that 256-position tiles never leave them
-  float* gc;        // ns x ldg: Gram columns by slot, row k = position k of A
+  // pattern mode of the narrow schedule; the arrays hold ldg entries, so
+  // that 256-position tiles never leave them
+  float* gc;        // ns x ldg: Gram columns by slot, row j = feature j
   float* ng;        // ldg: ||G_{k,S}||_2 of the zero coordinates of A
-  int32_t* pslot;   // ldg: slot holding the Gram column of position k, or -1
-  int32_t* npos;    // ldg: position after the last compaction, or -1
+  int32_t* pslot;   // ldg: slot holding the Gram column of feature j, or -1
   int32_t* pmem;    // ldg: 1 when position k is in the support list, else 0
   double* c2;       // ldg: second buffer of the correlations c
   int64_t ldg;      // p rounded up to a multiple of 256
@@ -59,6 +58,7 @@ enum {
   kStatPasses,             // screening passes
   kStatSkipped,            // epochs skipped at an exact fixed point
   kStatExact,              // pattern epochs that needed the exact zero-coordinate check
+  kStatNear,               // pattern epochs that checked at most 64 coordinates exactly
   kNumStats
 };
 

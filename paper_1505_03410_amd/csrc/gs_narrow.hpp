@@ -97,19 +97,18 @@ struct Narrow {
   // Pattern-mode state.  Scalars are wavefront-uniform; sp..u hold the
   // support members m = lane (index 0) and m = lane + 64 (index 1).
   struct Pat {
-    gbl<float>* gc;       // slot v: x_{A[k]}^T x_{A[owner[v]]} at gc[v*ldg + k]
+    gbl<float>* gc;       // slot v: x_j^T x_{owner[v]} at gc[v*ldg + j] for features j of A
     gbl<float>* ng;       // position -> ||G_{k,S}||_2 (zero coordinates of A)
-    gbl<int32_t>* pslot;  // position -> slot, or -1
-    gbl<int32_t>* npos;   // position -> position after the last compaction, or -1
+    gbl<int32_t>* pslot;  // feature -> slot, or -1
     gbl<int32_t>* pmem;   // position -> 1 when in S, else 0 (set up with S)
     gbl<double>* c2;      // the other correlation buffer
     int64_t ldg;
     int ns;               // slots of this problem
     int gs_cap;           // LDS floats of the block
-    int* owner;           // LDS ns: position whose column a slot holds, or -1
+    int* owner;           // LDS ns: feature whose column a slot holds, or -1
     int* spos;            // LDS NSC: positions of S
     int* sfeat;           // LDS NSC: features of S when the block was built
-    int* keep;            // LDS NSC: slots kept by a compaction
+    int* cand;            // LDS 64: zero coordinates whose bound failed
     int* bslot;           // LDS NBLD: slots of the columns being computed
     int* bfeat;           // LDS NBLD: their features
     float* stage;         // LDS NBLD x NMAX: those columns
@@ -522,15 +521,17 @@ struct Narrow {
   // restricted to members before k), Delta = beta_S - beta0; its size is at
   // most |c0_k| + ng_k (||Delta||_2 + ||delta||_2) by Cauchy-Schwarz, so
   // ||Delta||_2 + ||delta||_2 < tau proves that every zero coordinate stays
-  // at zero.  Otherwise the exact check runs over the Gram columns of S in
-  // the global cache and, when it passes, moves the anchor to the new point.
-  // The global cache is indexed by position: it follows the compactions of
-  // A, and a new lambda starts it afresh.
+  // at zero.  Otherwise the bound is applied coordinate by coordinate, and
+  // the few coordinates it leaves open (at most 64) get the exact value at
+  // their visit from the Gram columns of S in the global cache; with more,
+  // the exact check covers all of A and moves the anchor to the new point.
+  // The global cache is indexed by feature and only holds the rows of the
+  // current lambda's active set, so a new lambda starts it afresh.
 
   // A new lambda: the active set restarts from all of {0..p-1}.
   static __device__ __forceinline__ void pattern_new_lambda(const Ctx& x, Pat& pt) {
     for (int v = x.lane; v < pt.ns; v += 64) pt.owner[v] = -1;
-    for (int k = x.lane; k < x.p; k += 64) pt.pslot[k] = -1;
+    for (int j = x.lane; j < x.p; j += 64) pt.pslot[j] = -1;
     pt.victim = 0;
     pt.valid = false;
     pt.ng_ok = false;
@@ -538,59 +539,8 @@ struct Narrow {
     __threadfence_block();
   }
 
-  // After a compaction of A from q_old positions (new positions in npos):
-  // the columns of the coordinates that stay in A with a nonzero coefficient
-  // move to their new positions, the other slots are freed.  In place,
-  // ascending: every destination is at most its source.
-  static __device__ __forceinline__ void gc_compact(const Ctx& x, Pat& pt, int q_old, int q_new) {
-    const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
-    int nk = 0;
-    for (int v0 = 0; v0 < pt.ns; v0 += 64) {
-      const int v = v0 + x.lane;
-      const int o = v < pt.ns ? pt.owner[v] : -1;
-      const int no = o >= 0 ? pt.npos[o] : -1;
-      const bool kp = no >= 0 && x.beta[x.act[no]] != 0.0;
-      wave_lds_order();
-      if (v < pt.ns) pt.owner[v] = kp ? no : -1;
-      const uint64_t m = ballot(kp);
-      if (kp) pt.keep[nk + __popcll(m & lt)] = v;
-      nk += __popcll(m);
-    }
-    wave_lds_order();
-    for (int k = x.lane; k < q_new; k += 64) pt.pslot[k] = -1;
-    for (int i = x.lane; i < nk; i += 64) {
-      const int v = pt.keep[i];
-      pt.pslot[pt.owner[v]] = v;
-    }
-    for (int base = 0; base < q_old; base += 256) {
-      int dd[4];
-      ld4(pt.npos + base + 4 * x.lane, dd);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (base + 4 * x.lane + e >= q_old) dd[e] = -1;
-      for (int i0 = 0; i0 < nk; i0 += 8) {
-        float val[8][4];
-        gbl<float>* cols[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int v = i0 + i < nk ? __builtin_amdgcn_readfirstlane(pt.keep[i0 + i]) : 0;
-          cols[i] = pt.gc + (int64_t)v * pt.ldg;
-          ld4(cols[i] + base + 4 * x.lane, val[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (i0 + i < nk)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (dd[e] >= 0) cols[i][dd[e]] = val[i][e];
-      }
-    }
-    __threadfence_block();
-    wave_lds_order();
-  }
-
   // Gram columns of the nb features in bfeat into the slots bslot:
-  // gc[v*ldg + k] = x_{A[k]}^T x_j for every position k < q, in one sweep.
+  // gc[v*ldg + A[k]] = x_{A[k]}^T x_j for every position k < q, in one sweep.
   static __device__ __forceinline__ void build_cols(const Ctx& x, const Pat& pt, int q, bool full,
                                                     int nb) {
 #pragma unroll
@@ -617,9 +567,12 @@ struct Narrow {
     constexpr int UB = 2;
     for (int base = 0; base < q; base += UB * C) {
       XT xr[UB][RPL];
+      int jr[UB];
 #pragma unroll
-      for (int u = 0; u < UB; ++u)
-        L::load_raw(col(x, act_at(x, base + u * C + x.slot, q, full)), x.n, x.seg, x.ridx, xr[u]);
+      for (int u = 0; u < UB; ++u) {
+        jr[u] = act_at(x, base + u * C + x.slot, q, full);
+        L::load_raw(col(x, jr[u]), x.n, x.seg, x.ridx, xr[u]);
+      }
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         const int k = base + u * C + x.slot;
@@ -634,7 +587,7 @@ struct Narrow {
               if (i + 1 < RPL) a1 = fmaf((float)xr[u][i + 1], v[b][i + 1], a1);
             }
             const double dsum = seg_sum<S>((double)a0 + (double)a1);
-            if (x.seg == 0 && k < q) dst[b][k] = (float)dsum;
+            if (x.seg == 0 && k < q) dst[b][jr[u]] = (float)dsum;
           }
         }
       }
@@ -683,6 +636,9 @@ struct Narrow {
       ld4(x.c + k0, cv);
       ld4(pt.pmem + k0, mb);
       if (recompute) {
+        int jv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) jv[e] = act_at(x, k0 + e, q, false);
         float a[4] = {0.f, 0.f, 0.f, 0.f};
         for (int m0 = 0; m0 < s; m0 += 8) {
           float g[8][4];
@@ -692,8 +648,9 @@ struct Narrow {
             const int sl = m < s ? (m < 64 ? __builtin_amdgcn_readlane(pt.sl[0], m)
                                            : __builtin_amdgcn_readlane(pt.sl[1], m - 64))
                                  : 0;
-            ld4(pt.gc + (int64_t)sl * pt.ldg + k0, g[u]);
-            if (m >= s) g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0.f;
+            const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) g[u][e] = m < s ? gcol[jv[e]] : 0.f;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
@@ -760,7 +717,7 @@ struct Narrow {
       pt.sb[h] = v ? x.beta[j] : 0.0;
       pt.sg[h] = pt.sb[h] > 0.0 ? 1.0 : -1.0;
       pt.id[h] = v ? (float)x.inv[j] : 0.f;
-      pt.sl[h] = v ? pt.pslot[k] : 0;
+      pt.sl[h] = v ? pt.pslot[j] : 0;
       pt.b0[h] = pt.sb[h];
       pt.u[h] = v ? (float)(x.c[k] - lambda * pt.sg[h]) * pt.id[h] : 0.f;
     }
@@ -788,21 +745,19 @@ struct Narrow {
           v = pt.victim;
           pt.victim = v + 1 < pt.ns ? v + 1 : 0;
           o = __builtin_amdgcn_readfirstlane(pt.owner[v]);
-          found = o < 0 || x.beta[act_at(x, o, q, full)] == 0.0;
+          found = o < 0 || x.beta[o] == 0.0;
         }
         if (!found) {
           failed = true;
           break;
         }
-        const int km = m < 64 ? __builtin_amdgcn_readlane(pt.sp[0], m)
-                              : __builtin_amdgcn_readlane(pt.sp[1], m - 64);
         const int jm = m < 64 ? __builtin_amdgcn_readlane(pt.sj[0], m)
                               : __builtin_amdgcn_readlane(pt.sj[1], m - 64);
         wave_lds_order();
         if (x.lane == 0) {
           if (o >= 0) pt.pslot[o] = -1;
-          pt.pslot[km] = v;
-          pt.owner[v] = km;
+          pt.pslot[jm] = v;
+          pt.owner[v] = jm;
           pt.bslot[nb] = v;
           pt.bfeat[nb] = jm;
         }
@@ -841,8 +796,7 @@ struct Narrow {
         for (int h = 0; h < 2; ++h) {
           const int m = x.lane + 64 * h;
           if (m < sps) {
-            const int kk = m < s ? pt.sp[h] : 0;
-            float val = (l < s && m < s) ? gcol[kk] * pt.id[h] : 0.f;
+            float val = (l < s && m < s) ? gcol[pt.sj[h]] * pt.id[h] : 0.f;
             if (m == l) val = 1.f;
             pt.gs[l * sps + m] = val;
           }
@@ -864,8 +818,9 @@ struct Narrow {
   }
 
   // Loads the Gram entries of members m0..m0+7 (< hi) at the lane's four
-  // positions k0..k0+3, with their steps d and offsets dp.
-  static __device__ __forceinline__ void member_group(const Pat& pt, int m0, int hi, int k0,
+  // features jv, with their steps d and offsets dp.
+  static __device__ __forceinline__ void member_group(const Pat& pt, int m0, int hi,
+                                                      const int (&jv)[4],
                                                       const float (&d)[2], const float (&dp)[2],
                                                       float (&g)[8][4], float (&dm)[8],
                                                       float (&pm)[8]) {
@@ -887,8 +842,9 @@ struct Narrow {
         sl = 0;
         dm[u] = pm[u] = 0.f;
       }
-      ld4(pt.gc + (int64_t)sl * pt.ldg + k0, g[u]);
-      if (m >= hi) g[u][0] = g[u][1] = g[u][2] = g[u][3] = 0.f;
+      const gbl<float>* gcol = pt.gc + (int64_t)sl * pt.ldg;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) g[u][e] = m < hi ? gcol[jv[e]] : 0.f;
     }
   }
 
@@ -913,14 +869,16 @@ struct Narrow {
       const int hi = __popcll(ballot(x.lane < s && pt.sp[0] < base + 256)) +
                      __popcll(ballot(x.lane + 64 < s && pt.sp[1] < base + 256));
       double cv[4];
-      int mb[4];
+      int mb[4], jv[4];
       ld4(x.c + k0, cv);
       ld4(pt.pmem + k0, mb);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) jv[e] = act_at(x, k0 + e, q, false);
       float accP[4] = {0.f, 0.f, 0.f, 0.f}, accD[4] = {0.f, 0.f, 0.f, 0.f}, part[4];
       float g[8][4], dm[8], pm[8];
       // members before the block: every position sees their steps
       for (int m0 = 0; m0 < lo; m0 += 8) {
-        member_group(pt, m0, lo, k0, d, dp, g, dm, pm);
+        member_group(pt, m0, lo, jv, d, dp, g, dm, pm);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -933,7 +891,7 @@ struct Narrow {
       for (int e = 0; e < 4; ++e) part[e] = accD[e];
       // members inside: position k sees the steps of those before it
       for (int m0 = lo; m0 < hi; m0 += 8) {
-        member_group(pt, m0, hi, k0, d, dp, g, dm, pm);
+        member_group(pt, m0, hi, jv, d, dp, g, dm, pm);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int m = m0 + u;
@@ -950,7 +908,7 @@ struct Narrow {
       }
       // members after the block
       for (int m0 = hi; m0 < s; m0 += 8) {
-        member_group(pt, m0, s, k0, d, dp, g, dm, pm);
+        member_group(pt, m0, s, jv, d, dp, g, dm, pm);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -980,6 +938,77 @@ struct Narrow {
     }
     __threadfence_block();
     tau_new = wave_min(tau);
+    return ballot(bad) == 0;
+  }
+
+  // Zero coordinates of A for which |c0_k| + ng_k R <= lambda fails (R the
+  // reach of the steps since the anchor); the first 64 positions go to cand.
+  // Returns their number.
+  static __device__ __forceinline__ int bound_filter(const Ctx& x, const Pat& pt, int q,
+                                                     double lambda, double R) {
+    const uint64_t lt = (x.lane == 0) ? 0ull : (~0ull >> (64 - x.lane));
+    int n = 0;
+    for (int base = 0; base < q; base += 256) {
+      const int k0 = base + 4 * x.lane;
+      double cv[4];
+      int mb[4];
+      float nv[4];
+      ld4(x.c + k0, cv);
+      ld4(pt.pmem + k0, mb);
+      ld4(pt.ng + k0, nv);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool f = k0 + e < q && !mb[e] && !(slack_ratio(cv[e], nv[e], lambda) > R);
+        const uint64_t m = ballot(f);
+        const int idx = n + __popcll(m & lt);
+        if (f && idx < 64) pt.cand[idx] = k0 + e;
+        n += __popcll(m);
+      }
+    }
+    wave_lds_order();
+    return __builtin_amdgcn_readfirstlane(n);
+  }
+
+  // The exact correlation at its visit of each of the n (<= 64) coordinates
+  // in cand, one per lane: c0_k - sum_m G_km (dp_m + [member m before k] d_m).
+  // Returns true when all of them stay at zero.
+  static __device__ __forceinline__ bool cand_check(const Ctx& x, const Pat& pt, int q, int n,
+                                                   double lambda, const float (&d)[2],
+                                                   const float (&dp)[2]) {
+    const int s = __builtin_amdgcn_readfirstlane(pt.s);
+    const bool mine = x.lane < n;
+    const int k = mine ? pt.cand[x.lane] : 0;
+    const int j = act_at(x, k, q, false);
+    const double c0 = x.c[k];
+    float acc = 0.f;
+    for (int m0 = 0; m0 < s; m0 += 8) {
+      float g[8], w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int m = m0 + u;
+        const int ml = m & 63;
+        int sl, pos;
+        float dm, pm;
+        if (m < 64) {
+          sl = __builtin_amdgcn_readlane(pt.sl[0], ml);
+          pos = __builtin_amdgcn_readlane(pt.sp[0], ml);
+          dm = readlane_f(d[0], ml);
+          pm = readlane_f(dp[0], ml);
+        } else {
+          sl = __builtin_amdgcn_readlane(pt.sl[1], ml);
+          pos = __builtin_amdgcn_readlane(pt.sp[1], ml);
+          dm = readlane_f(d[1], ml);
+          pm = readlane_f(dp[1], ml);
+        }
+        const bool mv = m < s;
+        const gbl<float>* gcol = pt.gc + (int64_t)(mv ? sl : 0) * pt.ldg;
+        g[u] = mv ? gcol[j] : 0.f;
+        w[u] = mv ? pm + (pos < k ? dm : 0.f) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fmaf(g[u], w[u], acc);
+    }
+    const bool bad = mine && fabs(c0 - (double)acc) > lambda;
     return ballot(bad) == 0;
   }
 
@@ -1074,9 +1103,15 @@ struct Narrow {
     bool reanchor = false;
     double tau_new = 0.0;
     if (!(reach < pt.tau)) {
-      ++stc[kStatExact];
-      if (!pattern_exact(x, pt, q, lambda, d, dp, tau_new)) return 0;
-      reanchor = true;
+      const int nc = bound_filter(x, pt, q, lambda, reach);
+      if (nc <= 64) {
+        ++stc[kStatNear];
+        if (nc > 0 && !cand_check(x, pt, q, nc, lambda, d, dp)) return 0;
+      } else {
+        ++stc[kStatExact];
+        if (!pattern_exact(x, pt, q, lambda, d, dp, tau_new)) return 0;
+        reanchor = true;
+      }
     }
     // commit
 #pragma unroll
@@ -1124,8 +1159,8 @@ __device__ __forceinline__ void bind_lds(typename N::Ctx& x, typename N::Pat& pt
   pt.owner = x.rows_l + N::NMAX;
   pt.spos = pt.owner + N::NSC;
   pt.sfeat = pt.spos + N::NSC;
-  pt.keep = pt.sfeat + N::NSC;
-  pt.bslot = pt.keep + N::NSC;
+  pt.cand = pt.sfeat + N::NSC;
+  pt.bslot = pt.cand + N::NSC;
   pt.bfeat = pt.bslot + N::NBLD;
   pt.stage = reinterpret_cast<float*>(pt.bfeat + N::NBLD);
   pt.gs = reinterpret_cast<float*>(smem + GOFF);
@@ -1171,7 +1206,6 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     pt.gc = gptr(d.gc);
     pt.ng = gptr(d.ng);
     pt.pslot = gptr(d.pslot);
-    pt.npos = gptr(d.npos);
     pt.pmem = gptr(d.pmem);
     pt.c2 = gptr(d.c2);
     pt.ldg = d.ldg;
@@ -1289,13 +1323,8 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
             }
             if (k == K) break;
             bool dropped;
-            const int q_old = q;
-            const bool was_full = full;
-            q = N::test_compact(x, g, q, full, dropped, pat_on ? pt.npos : nullptr,
-                                pat_on ? pt.ng : nullptr);
+            q = N::test_compact(x, g, q, full, dropped, nullptr, pat_on ? pt.ng : nullptr);
             full = false;
-            // (right after a new lambda no column is cached yet)
-            if (pat_on && !was_full && q != q_old) N::gc_compact(x, pt, q_old, q);
             rho_ok = true;
             c_ok = true;
             if (dropped) {

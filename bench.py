@@ -42,11 +42,12 @@ def bench_path(gs, torch, synth, steps, warmup):
     for _ in range(warmup):
         r = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3, workspace=ws)
         ws = r["workspace"]
+    stats = torch.zeros(len(gs.STAT_NAMES), dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
     gs.timing_reset()
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3, workspace=ws)
+        r = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3, workspace=ws, stats=stats)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     path_ms, path_n = gs.timing_query("path")
@@ -55,8 +56,9 @@ def bench_path(gs, torch, synth, steps, warmup):
     yy = float((y.astype("float64") ** 2).sum())
     ok = bool((st == 0).all() and (gap <= 1e-8 * yy).all())
     epochs = int(r["epochs"].sum())
+    st = {k: int(v) // steps for k, v in zip(gs.STAT_NAMES, stats.cpu().tolist())}
     return dict(seconds=el / steps, ok=ok, epochs=epochs, path_ms=path_ms / max(path_n, 1),
-                path_launches=path_n, n=X.shape[0], p=X.shape[1])
+                path_launches=path_n, n=X.shape[0], p=X.shape[1], stats=st)
 
 
 def bench_sweep(gs, torch, synth, reps):
@@ -86,6 +88,17 @@ def bench_sweep(gs, torch, synth, reps):
     return dict(avg_us=avg_s * 1e6, launches=cnt, bytes=nbytes, gbs=gbs, n=n, p=p)
 
 
+def copy_calibration(torch, mb, reps):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    nel = int(mb * 1e6) // 4
+    a = torch.ones(nel, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    _log(f"copy: {reps} x {nel * 4} bytes")
+
+
 def cpu_baseline(synth, reps):
     import numpy as np
     import oracle
@@ -109,6 +122,9 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-path", action="store_true")
+    ap.add_argument("--copy-mb", type=float, default=0.0,
+                    help="only run a plain device copy of this many MB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the library solves "
@@ -123,11 +139,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.copy_mb > 0:
+        copy_calibration(torch, a.copy_mb, 5)
+        return
     gs.load_library()
     gs.timing_enable(True)
-    _log("path: c1 72x7129, 100 lambdas")
-    path = bench_path(gs, torch, synth, a.steps, a.warmup)
-    _log(f"path: {path['seconds']:.4f} s/path, ok={path['ok']}")
+    path = None
+    if not a.no_path:
+        _log("path: c1 72x7129, 100 lambdas")
+        path = bench_path(gs, torch, synth, a.steps, a.warmup)
+        _log(f"path: {path['seconds']:.4f} s/path, ok={path['ok']}")
     roof = None
     sweep = None
     if not a.no_sweep:
@@ -146,6 +167,9 @@ def main():
         cpu = {"value": round(cb["value"], 4), "unit": "s", "cores": 1, "kind": "oracle",
                "sample": f"whole c1 path (100 lambdas), median of {cb['reps']} runs, "
                          "FP64 C oracle, one thread"}
+    if path is None:
+        print(json.dumps({"roofline": roof}), flush=True)
+        return
     line = {
         "metric": "Lasso path seconds to gap<=1e-8||y||^2 (c1 72x7129); X^T theta HBM GB/s",
         "value": round(path["seconds"], 5),
@@ -167,7 +191,8 @@ def main():
         "path_kernel": {"kernel": "k_path_narrow", "bound": "latency",
                         "avg_ms": round(path["path_ms"], 3), "launches": path["path_launches"],
                         "epochs_per_path": path["epochs"],
-                        "epochs_per_s": round(path["epochs"] / path["seconds"], 1)},
+                        "epochs_per_s": round(path["epochs"] / path["seconds"], 1),
+                        "counters_per_path": path["stats"]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

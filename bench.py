@@ -28,6 +28,22 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the sweep kernel from the FETCH_SIZE and WRITE_SIZE
+# counter runs in profiles/k_wide_sweep_c4_hbm_counters.md (scaled by a plain
+# copy of known size), valid while the kernel's sources hash to SWEEP_SRC_SHA1.
+SWEEP_TRAFFIC_BYTES = 403.4e6
+SWEEP_SRC_SHA1 = "af8e92c689e6f7ab"
+SWEEP_SRCS = ("paper_1505_03410_amd/csrc/gs_wide.hpp", "paper_1505_03410_amd/csrc/gs_device.hpp")
+
+
+def sweep_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for f in SWEEP_SRCS:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return SWEEP_TRAFFIC_BYTES if h.hexdigest()[:16] == SWEEP_SRC_SHA1 else None
+
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -157,7 +173,7 @@ def main():
         _log(f"sweep: {sweep['avg_us']:.1f} us, {sweep['gbs']:.0f} GB/s")
         roof = {"bound": "hbm", "kernel": "k_wide_sweep<float,4,4>",
                 "achieved": round(sweep["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(sweep["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(sweep["gbs"] / HBM_PEAK_GBS, 4), "traffic": sweep_traffic(),
                 "bytes_per_launch": sweep["bytes"], "avg_us": round(sweep["avg_us"], 2),
                 "launches": sweep["launches"], "workload": "1000x100000 FP32 full sweep"}
     cpu = None

@@ -104,6 +104,76 @@ def bench_sweep(gs, torch, synth, reps):
     return dict(avg_us=avg_s * 1e6, launches=cnt, bytes=nbytes, gbs=gbs, n=n, p=p)
 
 
+def _latency(gs, ts):
+    """Per-problem latency from device wall-clock timestamps (start, end):
+    completion minus the earliest start, in ms, as p50 / p99 / max."""
+    import numpy as np
+    t = ts.cpu().numpy().reshape(-1, 2).astype(np.float64)
+    hz = gs.wallclock_hz()
+    lat = (t[:, 1] - t[:, 0].min()) / hz * 1e3
+    return dict(p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3),
+                max_ms=round(float(lat.max()), 3))
+
+
+def bench_c2(gs, torch, synth, reps):
+    """256 row subsamples (36 rows) of the c1 design, 100 lambdas each, as one
+    graph-captured batch; selection counts on the device."""
+    d = synth.c2()
+    X, y, rows = d["X"], d["y"], d["rows"]
+    Xd = gs.colmajor_to_device(X)
+    yd = torch.from_numpy(y).cuda()
+    B, T = rows.shape[0], 100
+    probs = [dict(X=Xd, y=yd, rows=torch.from_numpy(rows[b]).cuda(), T=T, lambda_min_ratio=1e-2)
+             for b in range(B)]
+    counts = torch.zeros((T, X.shape[1]), dtype=torch.int32, device="cuda")
+    ts = torch.zeros(2 * B, dtype=torch.int64, device="cuda")
+    plan = gs.BatchPlan(probs, select_counts=counts, timestamps=ts)
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ok = all(bool((o["status"] == 0).all()) for o in plan.outputs)
+    lat = _latency(gs, ts)
+    plan.close()
+    return dict(seconds=round(el, 4), paths_per_s=round(B / el, 1), certified=ok, **lat,
+                workload="c2: 256 row subsamples (36 rows) of 72x7129, T=100, ratio 1e-2, "
+                         "one graph-captured batch")
+
+
+def bench_c3(gs, torch, synth, tune):
+    """512 independent problems of uneven n, p (one lambda each, cold start)."""
+    import numpy as np
+    params = synth.c3_params()
+    probs, keep = [], []
+    for pr in params:
+        d = synth.c3_problem(pr)
+        Xd = gs.colmajor_to_device(d["X"])
+        yd = torch.from_numpy(d["y"]).cuda()
+        keep.append((Xd, yd))
+        probs.append(dict(X=Xd, y=yd, T=1, lambdas=[d["lambda_ratio"]], relative=True))
+    _log(f"c3: {len(probs)} problems uploaded")
+    tiles = None
+    if tune:
+        ch = gs.autotune(probs, max_lambdas=1, sample=2)
+        tiles = sorted(set(ch))
+    B = len(probs)
+    ts = torch.zeros(2 * B, dtype=torch.int64, device="cuda")
+    gs.lasso_solve_batch(probs, timestamps=ts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = gs.lasso_solve_batch(probs, timestamps=ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ok = all(bool((o["status"] == 0).all()) for o in outs)
+    return dict(seconds=round(el, 4), certified=ok, tiles=tiles, **_latency(gs, ts),
+                workload="c3: 512 problems, n log-U[50,2000], p log-U[1000,50000], "
+                         "lambda/lambda_max U[0.01,0.5]")
+
+
 def copy_calibration(torch, mb, reps):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     nel = int(mb * 1e6) // 4
@@ -139,6 +209,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-path", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--c3", action="store_true", help="also run the 512-problem uneven batch")
+    ap.add_argument("--tune", action="store_true", help="autotune tiles before the c3 batch")
     ap.add_argument("--copy-mb", type=float, default=0.0,
                     help="only run a plain device copy of this many MB (counter calibration)")
     a = ap.parse_args()
@@ -176,6 +249,16 @@ def main():
                 "frac": round(sweep["gbs"] / HBM_PEAK_GBS, 4), "traffic": sweep_traffic(),
                 "bytes_per_launch": sweep["bytes"], "avg_us": round(sweep["avg_us"], 2),
                 "launches": sweep["launches"], "workload": "1000x100000 FP32 full sweep"}
+    c2 = None
+    if not a.no_c2 and path is not None:
+        _log("c2: 256 row subsamples, graph-captured batch")
+        c2 = bench_c2(gs, torch, synth, 3)
+        _log(f"c2: {c2['seconds']:.3f} s, {c2['paths_per_s']} paths/s, p99 {c2['p99_ms']} ms")
+    c3 = None
+    if a.c3:
+        _log("c3: 512 uneven problems")
+        c3 = bench_c3(gs, torch, synth, a.tune)
+        _log(f"c3: {c3['seconds']:.3f} s, p50 {c3['p50_ms']} ms, p99 {c3['p99_ms']} ms")
     cpu = None
     if not a.no_cpu:
         _log("cpu baseline: oracle, whole c1 path")
@@ -211,6 +294,7 @@ def main():
                         "counters_per_path": path["stats"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": {"c2": c2, "c3": c3},
     }
     print(json.dumps(line), flush=True)
 

@@ -185,6 +185,44 @@ int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace,
 int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts,
                       void* workspace, size_t ws_bytes, void* stream);
 
+/* A batch recorded once and replayed: lasso_batch_plan checks the problems,
+ * uploads their descriptors and lambdas into the workspace (on `stream`,
+ * which it synchronizes), and captures the persistent launches of
+ * lasso_solve_batch into a HIP graph; lasso_batch_run replays that graph on
+ * any stream, each replay solving the whole batch again from the inputs
+ * (select_counts keep accumulating over replays; timestamps are
+ * overwritten).  The plan refers to the caller's workspace, inputs and
+ * outputs, which must stay valid and unchanged in size while it is used;
+ * their contents (X, y, beta_init) may change between replays.  The plan is
+ * host memory owned by the caller; lasso_batch_plan_free releases it.
+ * Returns the codes of lasso_solve_batch, or GS_EHIP when capture fails. */
+typedef struct gs_batch_plan gs_batch_plan;
+int lasso_batch_plan(const gs_problem* probs, int32_t B, const gs_opts* opts,
+                     void* workspace, size_t ws_bytes, void* stream,
+                     gs_batch_plan** plan);
+int lasso_batch_run(gs_batch_plan* plan, void* stream);
+void lasso_batch_plan_free(gs_batch_plan* plan);
+
+/* Tile autotuner of the batched launch.  Problems fall into classes (dtype,
+ * row list or not, 16-byte loads or not, and the smallest compiled column
+ * layout that holds n rows).  For each class present in probs it times every
+ * candidate layout (the smallest one of each lane split S that holds the
+ * class) on up to `sample` of its most expensive problems, each solved for
+ * its first min(T, max_lambdas) lambdas, and records the fastest; later
+ * calls in this process (lasso_path's narrow schedule, lasso_solve_batch,
+ * lasso_batch_plan) use the recorded layout.  The sampled problems' outputs
+ * are overwritten with those partial runs.  choice_out (optional, host, 2B
+ * int32): the chosen (S, NG) of each problem.  Synchronizes `stream`.
+ * gs_tune_save / gs_tune_load write and read the recorded choices as JSON
+ * (GS_EINVAL when the file cannot be opened or holds no valid entry);
+ * gs_tune_reset forgets them. */
+int gs_autotune(const gs_problem* probs, int32_t B, const gs_opts* opts,
+                void* workspace, size_t ws_bytes, void* stream,
+                int32_t max_lambdas, int32_t sample, int32_t* choice_out);
+int gs_tune_save(const char* path);
+int gs_tune_load(const char* path);
+void gs_tune_reset(void);
+
 /* Bytes of workspace that screen() needs. */
 size_t screen_workspace_size(int32_t n, int32_t p);
 

@@ -65,7 +65,9 @@ STAT_NAMES = ["pattern_epochs", "residual_epochs", "rejected", "builds", "setups
               "support_changes", "passes", "skipped", "exact_checks", "near_checks"]
 
 EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
-           "lasso_solve_batch", "screen_workspace_size", "screen", "gs_timing_enable",
+           "lasso_solve_batch", "lasso_batch_plan", "lasso_batch_run", "lasso_batch_plan_free",
+           "gs_autotune", "gs_tune_save", "gs_tune_load", "gs_tune_reset",
+           "screen_workspace_size", "screen", "gs_timing_enable",
            "gs_timing_reset", "gs_timing_query", "lasso_strerror"]
 
 _lib = None
@@ -92,6 +94,22 @@ def load_library(path: str = LIB_PATH):
     lib.lasso_solve_batch.argtypes = [P(gs_problem), ctypes.c_int32, P(gs_opts), vp,
                                       ctypes.c_size_t, vp]
     lib.lasso_solve_batch.restype = ctypes.c_int
+    lib.lasso_batch_plan.argtypes = [P(gs_problem), ctypes.c_int32, P(gs_opts), vp,
+                                     ctypes.c_size_t, vp, P(vp)]
+    lib.lasso_batch_plan.restype = ctypes.c_int
+    lib.lasso_batch_run.argtypes = [vp, vp]
+    lib.lasso_batch_run.restype = ctypes.c_int
+    lib.lasso_batch_plan_free.argtypes = [vp]
+    lib.lasso_batch_plan_free.restype = None
+    lib.gs_autotune.argtypes = [P(gs_problem), ctypes.c_int32, P(gs_opts), vp, ctypes.c_size_t,
+                                vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.gs_autotune.restype = ctypes.c_int
+    lib.gs_tune_save.argtypes = [ctypes.c_char_p]
+    lib.gs_tune_save.restype = ctypes.c_int
+    lib.gs_tune_load.argtypes = [ctypes.c_char_p]
+    lib.gs_tune_load.restype = ctypes.c_int
+    lib.gs_tune_reset.argtypes = []
+    lib.gs_tune_reset.restype = None
     lib.screen_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.screen_workspace_size.restype = ctypes.c_size_t
     lib.screen.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
@@ -274,12 +292,8 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
     return out
 
 
-def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10,
-                      max_epochs: int = 100000, select_counts=None, timestamps=None,
-                      cd_mode="auto", stream=None, workspace=None, stats=None):
-    """Many paths in one persistent launch.  ``problems`` is a list of dicts
-    with keys X, y and optionally T, lambdas, relative, lambda_min_ratio,
-    beta_init, rows.  Returns the list of PathResults."""
+def _batch_args(problems, eps_rel, screen_every, max_epochs, select_counts, timestamps,
+                cd_mode, stats, workspace):
     lib = load_library()
     B = len(problems)
     arr = (gs_problem * B)()
@@ -298,11 +312,86 @@ def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10
     need = lib.lasso_workspace_size(arr, B, ctypes.byref(o))
     dev = problems[0]["X"].device
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
-    rc = lib.lasso_solve_batch(arr, B, ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))
-    _check(rc)
     for out in outs:
         out["workspace"] = ws
+    return lib, arr, o, outs, keep, ws
+
+
+def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10,
+                      max_epochs: int = 100000, select_counts=None, timestamps=None,
+                      cd_mode="auto", stream=None, workspace=None, stats=None):
+    """Many paths in one persistent launch.  ``problems`` is a list of dicts
+    with keys X, y and optionally T, lambdas, relative, lambda_min_ratio,
+    beta_init, rows.  Returns the list of PathResults."""
+    lib, arr, o, outs, _keep, ws = _batch_args(problems, eps_rel, screen_every, max_epochs,
+                                               select_counts, timestamps, cd_mode, stats,
+                                               workspace)
+    rc = lib.lasso_solve_batch(arr, len(problems), ctypes.byref(o), _ptr(ws), ws.numel(),
+                               _stream_ptr(stream))
+    _check(rc)
     return outs
+
+
+class BatchPlan:
+    """A batch captured into a HIP graph (lasso_batch_plan); ``run()`` replays
+    it.  ``outputs`` are the per-problem result tensors every replay fills."""
+
+    def __init__(self, problems, *, eps_rel=1e-8, screen_every=10, max_epochs=100000,
+                 select_counts=None, timestamps=None, cd_mode="auto", stream=None,
+                 workspace=None, stats=None):
+        lib, arr, o, outs, keep, ws = _batch_args(problems, eps_rel, screen_every, max_epochs,
+                                                  select_counts, timestamps, cd_mode, stats,
+                                                  workspace)
+        self._lib = lib
+        self._keep = (arr, o, keep, problems, select_counts, timestamps, stats)
+        self.outputs = outs
+        self.workspace = ws
+        h = ctypes.c_void_p()
+        rc = lib.lasso_batch_plan(arr, len(problems), ctypes.byref(o), _ptr(ws), ws.numel(),
+                                  _stream_ptr(stream), ctypes.byref(h))
+        _check(rc, allow_not_converged=False)
+        self._h = h
+
+    def run(self, stream=None):
+        rc = self._lib.lasso_batch_run(self._h, _stream_ptr(stream))
+        _check(rc, allow_not_converged=False)
+        return self.outputs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lasso_batch_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def autotune(problems, *, max_lambdas: int = 5, sample: int = 4, eps_rel: float = 1e-8,
+             screen_every: int = 10, max_epochs: int = 100000, cd_mode="auto", stream=None,
+             workspace=None):
+    """Runs the tile autotuner (gs_autotune) on the problem classes present in
+    ``problems``; returns the chosen (S, NG) per problem.  The recorded choice
+    applies to later calls in this process."""
+    lib, arr, o, _outs, _keep, ws = _batch_args(problems, eps_rel, screen_every, max_epochs,
+                                                None, None, cd_mode, None, workspace)
+    B = len(problems)
+    ch = (ctypes.c_int32 * (2 * B))()
+    rc = lib.gs_autotune(arr, B, ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream),
+                         int(max_lambdas), int(sample), ch)
+    _check(rc, allow_not_converged=False)
+    return [(ch[2 * b], ch[2 * b + 1]) for b in range(B)]
+
+
+def tune_save(path: str):
+    _check(load_library().gs_tune_save(path.encode()), allow_not_converged=False)
+
+
+def tune_load(path: str):
+    _check(load_library().gs_tune_load(path.encode()), allow_not_converged=False)
+
+
+def tune_reset():
+    load_library().gs_tune_reset()
 
 
 def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=None,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -105,13 +106,33 @@ const NarrowEntry* narrow_table(int dtype, bool gather, bool vec, int* count) {
   return kNarrowF64S;
 }
 
-// Smallest compiled narrow configuration that holds n rows.
+// ---- tile choice.  A class of problems is (table, smallest entry that holds
+// n); the autotuner may map a class to another entry of the same table that
+// also holds n.  Keys: (table base pointer, smallest index).
+std::mutex g_tune_mu;
+std::map<std::pair<const NarrowEntry*, int>, int> g_tuned;
+// set while the autotuner times one candidate (this thread only)
+thread_local const NarrowEntry* g_force = nullptr;
+
+int smallest_fit(const NarrowEntry* tab, int cnt, int n) {
+  for (int i = 0; i < cnt; ++i)
+    if (tab[i].cfg.nmax() >= n) return i;
+  return -1;
+}
+
+// The narrow configuration of a problem: the tuned one of its class, else the
+// smallest compiled one that holds n rows.
 const NarrowEntry* pick_narrow(const gs_problem* pr) {
   int cnt = 0;
   const NarrowEntry* tab = narrow_table(pr->dtype, pr->rows != nullptr, vec_ok(pr), &cnt);
-  for (int i = 0; i < cnt; ++i)
-    if (tab[i].cfg.nmax() >= pr->n) return &tab[i];
-  return nullptr;
+  const int i0 = smallest_fit(tab, cnt, pr->n);
+  if (i0 < 0) return nullptr;
+  if (g_force) return g_force;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find({tab, i0});
+  if (it != g_tuned.end() && it->second < cnt && tab[it->second].cfg.nmax() >= pr->n)
+    return &tab[it->second];
+  return &tab[i0];
 }
 
 const WideEntry* pick_wide(const gs_problem* pr) {
@@ -150,6 +171,7 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   d->c = cv.take<double>(ldg);
   d->act = cv.take<int32_t>(2 * (size_t)pr->p);
   d->lam = cv.take<double>(pr->T);
+  d->lam_in = cv.take<double>(pr->T);
   d->rho = cv.take<double>(pr->n);
   d->gc = cv.take<float>((size_t)ns * ldg);
   d->ng = cv.take<float>(ldg);
@@ -323,7 +345,7 @@ int lds_cap_for(const NarrowEntry* e, int count, int gs) {
 // Upload the lambdas of each problem into its workspace copy.
 int upload_lambdas(const gs_problem* pr, const ProbDesc* d, hipStream_t s) {
   if (pr->lambdas)
-    HIPCHK(hipMemcpyAsync(d->lam, pr->lambdas, sizeof(double) * pr->T, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d->lam_in, pr->lambdas, sizeof(double) * pr->T, hipMemcpyHostToDevice, s));
   return GS_OK;
 }
 
@@ -464,32 +486,65 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   return GS_OK;
 }
 
-int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po,
-                  hipStream_t s) {
-  HIPCHK(fill_i32(sh.queues, 0, 64, s));
+// One persistent launch of a group: its kernel, grid, LDS and arguments.
+struct Launch {
+  const void* kernel;
+  int grid;
+  size_t lds;
+  const ProbDesc* descs;
+  int B;
+  int* queue;
+  PathOpts po;
+};
+
+// LDS split and grid of every group; sets the kernels' LDS limits (not a
+// stream operation, so it stays outside graph capture).
+int configure_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po,
+                     std::vector<Launch>* out) {
+  out->clear();
   for (size_t g = 0; g < groups.size(); ++g) {
     const Group& G = groups[g];
-    const ProbDesc* d = sh.descs + G.first;
-    int B = G.count;
-    int* q = sh.queues + g;
-    PathOpts pg = po;
+    Launch L;
+    L.kernel = G.e->path_kernel;
+    L.descs = sh.descs + G.first;
+    L.B = G.count;
+    L.queue = sh.queues + g;
+    L.po = po;
     // the support's Gram block first (when the CU's share holds it), then
     // the residual mode's staging region
     const size_t per_wave = device_lds_per_cu() /
                             std::max(1, (G.count + device_cus() - 1) / device_cus());
-    pg.gs_cap = (po.pattern && G.e->lds_bytes + sizeof(float) * (size_t)G.gs + 1024 <= per_wave)
-                    ? G.gs
-                    : 0;
-    pg.lds_cap = lds_cap_for(G.e, G.count, pg.gs_cap);
-    const size_t lds =
-        G.e->lds_bytes + sizeof(float) * ((size_t)pg.gs_cap + (size_t)pg.lds_cap);
-    HIPCHK(hipFuncSetAttribute(G.e->path_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    void* a[] = {&d, &B, &q, &pg};
-    const int grid = std::max(1, std::min(G.count, narrow_slots(G.e, lds)));
-    HIPCHK(timed_launch(kTimePath, G.e->path_kernel, dim3(grid), dim3(64), a, lds, s));
+    L.po.gs_cap =
+        (po.pattern && G.e->lds_bytes + sizeof(float) * (size_t)G.gs + 1024 <= per_wave) ? G.gs
+                                                                                           : 0;
+    L.po.lds_cap = lds_cap_for(G.e, G.count, L.po.gs_cap);
+    L.lds = G.e->lds_bytes + sizeof(float) * ((size_t)L.po.gs_cap + (size_t)L.po.lds_cap);
+    HIPCHK(hipFuncSetAttribute(L.kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
+    L.grid = std::max(1, std::min(G.count, narrow_slots(G.e, L.lds)));
+    out->push_back(L);
   }
   return GS_OK;
+}
+
+// Queue reset (a fill kernel, no memset node) and the group launches.
+int enqueue_groups(const Shared& sh, std::vector<Launch>& launches, hipStream_t s, bool timed) {
+  HIPCHK(fill_i32(sh.queues, 0, 64, s));
+  for (Launch& L : launches) {
+    void* a[] = {&L.descs, &L.B, &L.queue, &L.po};
+    if (timed)
+      HIPCHK(timed_launch(kTimePath, L.kernel, dim3(L.grid), dim3(64), a, L.lds, s));
+    else
+      HIPCHK(launch(L.kernel, dim3(L.grid), dim3(64), a, L.lds, s));
+  }
+  return GS_OK;
+}
+
+int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts po,
+                  hipStream_t s) {
+  std::vector<Launch> launches;
+  int rc = configure_groups(sh, groups, po, &launches);
+  if (rc) return rc;
+  return enqueue_groups(sh, launches, s, true);
 }
 
 }  // namespace
@@ -655,6 +710,234 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, cons
     HIPCHK(launch(kWideFin, dim3(1), dim3(64), a, 0, s));
   }
   return GS_OK;
+}
+
+// ------------------------------------------------------------ batch plans
+
+struct gs_batch_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int lasso_batch_plan(const gs_problem* probs, int32_t B, const gs_opts* opts, void* workspace,
+                     size_t ws_bytes, void* stream, gs_batch_plan** plan) {
+  if (!plan) return GS_EINVAL;
+  *plan = nullptr;
+  gs_opts def;
+  gs_opts_default(&def);
+  if (!opts) opts = &def;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Shared sh;
+  std::vector<Group> groups;
+  int rc = prepare_batch(probs, B, opts, workspace, ws_bytes, s, &sh, &groups);
+  if (rc) return rc;
+  std::vector<Launch> launches;
+  rc = configure_groups(sh, groups, path_opts(opts, true), &launches);
+  if (rc) return rc;
+  // the uploads above are ordered before every replay on `stream`; capture
+  // the launches on a private stream
+  HIPCHK(hipStreamSynchronize(s));
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  gs_batch_plan* p = new gs_batch_plan;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue_groups(sh, launches, cs, false);
+    hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+    if (rc == GS_OK && e2 != hipSuccess) rc = fail_hip(e2, "hipStreamEndCapture");
+  } else {
+    rc = fail_hip(e, "hipStreamBeginCapture");
+  }
+  if (rc == GS_OK) {
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = fail_hip(e, "hipGraphInstantiate");
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != GS_OK) {
+    lasso_batch_plan_free(p);
+    return rc;
+  }
+  *plan = p;
+  return GS_OK;
+}
+
+int lasso_batch_run(gs_batch_plan* plan, void* stream) {
+  if (!plan || !plan->exec) return GS_EINVAL;
+  HIPCHK(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+  return GS_OK;
+}
+
+void lasso_batch_plan_free(gs_batch_plan* plan) {
+  if (!plan) return;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
+}
+
+// --------------------------------------------------------------- autotuner
+
+int gs_autotune(const gs_problem* probs, int32_t B, const gs_opts* opts, void* workspace,
+                size_t ws_bytes, void* stream, int32_t max_lambdas, int32_t sample,
+                int32_t* choice_out) {
+  gs_opts def;
+  gs_opts_default(&def);
+  if (!opts) opts = &def;
+  if (!probs || B < 1 || max_lambdas < 1 || sample < 1) return GS_EINVAL;
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  for (int b = 0; b < B; ++b) {
+    rc = check_problem(&probs[b]);
+    if (rc) return rc;
+  }
+  if (!workspace) return GS_EWORKSPACE;
+  if (ws_bytes < path_ws(probs, B)) return GS_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gs_opts o = *opts;
+  o.select_counts = nullptr;
+  o.timestamps = nullptr;
+  o.stats = nullptr;
+  // classes present in the batch
+  std::map<std::pair<const NarrowEntry*, int>, std::vector<int>> classes;
+  for (int b = 0; b < B; ++b) {
+    int cnt = 0;
+    const NarrowEntry* tab = narrow_table(probs[b].dtype, probs[b].rows != nullptr,
+                                          vec_ok(&probs[b]), &cnt);
+    const int i0 = smallest_fit(tab, cnt, probs[b].n);
+    if (i0 < 0) return GS_EUNSUPPORTED;
+    classes[{tab, i0}].push_back(b);
+  }
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  for (auto& kv : classes) {
+    const NarrowEntry* tab = kv.first.first;
+    const int i0 = kv.first.second;
+    int cnt = 0;
+    narrow_table(probs[kv.second[0]].dtype, probs[kv.second[0]].rows != nullptr,
+                 vec_ok(&probs[kv.second[0]]), &cnt);
+    std::vector<int> mem = kv.second;
+    std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) {
+      return (double)probs[a].n * probs[a].p > (double)probs[b].n * probs[b].p;
+    });
+    if ((int)mem.size() > sample) mem.resize(sample);
+    int nmax = 0;
+    for (int b : mem) nmax = std::max(nmax, probs[b].n);
+    std::vector<gs_problem> sp;
+    for (int b : mem) {
+      gs_problem q = probs[b];
+      q.T = std::min(q.T, max_lambdas);
+      sp.push_back(q);
+    }
+    // candidates: the smallest entry of each lane split S that holds the class
+    std::vector<int> cand;
+    std::vector<int> seenS;
+    for (int i = i0; i < cnt; ++i) {
+      if (tab[i].cfg.nmax() < nmax) continue;
+      if (std::find(seenS.begin(), seenS.end(), tab[i].cfg.S) != seenS.end()) continue;
+      seenS.push_back(tab[i].cfg.S);
+      cand.push_back(i);
+    }
+    int best = i0;
+    float best_ms = 1e30f;
+    for (int c : cand) {
+      g_force = &tab[c];
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && rc == GS_OK; ++rep) {  // the first run loads the code
+        Shared sh;
+        std::vector<Group> groups;
+        rc = prepare_batch(sp.data(), (int)sp.size(), &o, workspace, ws_bytes, s, &sh, &groups);
+        std::vector<Launch> launches;
+        if (rc == GS_OK) rc = configure_groups(sh, groups, path_opts(&o, true), &launches);
+        if (rc == GS_OK && hipEventRecord(ea, s) != hipSuccess) rc = GS_EHIP;
+        if (rc == GS_OK) rc = enqueue_groups(sh, launches, s, false);
+        if (rc == GS_OK && hipEventRecord(eb, s) != hipSuccess) rc = GS_EHIP;
+        if (rc == GS_OK && hipEventSynchronize(eb) != hipSuccess) rc = GS_EHIP;
+        if (rc == GS_OK && hipEventElapsedTime(&ms, ea, eb) != hipSuccess) rc = GS_EHIP;
+      }
+      g_force = nullptr;
+      if (rc) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    if (rc) break;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[kv.first] = best;
+    }
+    if (choice_out)
+      for (int b : kv.second) {
+        choice_out[2 * b] = tab[best].cfg.S;
+        choice_out[2 * b + 1] = tab[best].cfg.NG;
+      }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  return rc;
+}
+
+void gs_tune_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+}
+
+int gs_tune_save(const char* path) {
+  if (!path) return GS_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return GS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::fprintf(f, "{\"tiles\": [");
+  bool first = true;
+  for (auto& kv : g_tuned) {
+    const NarrowEntry& a = kv.first.first[kv.first.second];
+    const NarrowEntry& c = kv.first.first[kv.second];
+    std::fprintf(f, "%s\n  {\"dtype\": %d, \"vec\": %d, \"gather\": %d, \"S\": %d, \"NG\": %d, "
+                 "\"to_S\": %d, \"to_NG\": %d}",
+                 first ? "" : ",", a.cfg.dtype, a.cfg.vec, a.cfg.gather ? 1 : 0, a.cfg.S, a.cfg.NG,
+                 c.cfg.S, c.cfg.NG);
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  return GS_OK;
+}
+
+int gs_tune_load(const char* path) {
+  if (!path) return GS_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return GS_EINVAL;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  // one object per line of the form written by gs_tune_save
+  int loaded = 0;
+  size_t pos = 0;
+  while ((pos = text.find("{\"dtype\"", pos)) != std::string::npos) {
+    int dt, vec, ga, S, NG, tS, tNG;
+    if (std::sscanf(text.c_str() + pos,
+                    "{\"dtype\": %d, \"vec\": %d, \"gather\": %d, \"S\": %d, \"NG\": %d, "
+                    "\"to_S\": %d, \"to_NG\": %d}",
+                    &dt, &vec, &ga, &S, &NG, &tS, &tNG) == 7) {
+      int cnt = 0;
+      const bool vok = vec > 1;
+      const NarrowEntry* tab = narrow_table(dt == 1 ? GS_F64 : GS_F32, ga != 0, vok, &cnt);
+      int from = -1, to = -1;
+      for (int i = 0; i < cnt; ++i) {
+        if (tab[i].cfg.S == S && tab[i].cfg.NG == NG) from = i;
+        if (tab[i].cfg.S == tS && tab[i].cfg.NG == tNG) to = i;
+      }
+      if (from >= 0 && to >= 0 && tab[to].cfg.nmax() >= tab[from].cfg.nmax()) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[{tab, from}] = to;
+        ++loaded;
+      }
+    }
+    pos += 8;
+  }
+  return loaded > 0 ? GS_OK : GS_EINVAL;
 }
 
 void gs_timing_enable(int on) { g_timing = on != 0; }

@@ -30,7 +30,8 @@ struct ProbDesc {
   double* beta;   // p: working coefficients (FP64)
   double* c;      // p: x_j^T rho of the last sweep, indexed by position in A
   int32_t* act;   // 2p: active set (two buffers for the wide schedule)
-  double* lam;    // T: lambdas (caller values on entry, absolute after init)
+  double* lam;    // T: the absolute lambdas of the path (set by the kernels)
+  double* lam_in; // T: caller lambdas (absolute or relative), read only
   double* rho;    // n: residual (wide schedule)
   // pattern mode of the narrow schedule; the arrays hold ldg entries, so
   // that 256-position tiles never leave them

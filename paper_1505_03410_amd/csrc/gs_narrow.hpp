@@ -1273,7 +1273,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     for (int t = lane; t < T; t += 64) {
       double lam;
       if (d.has_lambdas)
-        lam = lam_g[t] * (d.lambda_relative ? lmax : 1.0);
+        lam = gptr(d.lam_in)[t] * (d.lambda_relative ? lmax : 1.0);
       else
         lam = (T == 1) ? lmax : lmax * pow(d.lambda_min_ratio, (double)t / (double)(T - 1));
       lam_g[t] = lam;

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
   for (int t = threadIdx.x; t < T; t += 256) {
     double lam;
     if (d.has_lambdas)
-      lam = d.lam[t] * (d.lambda_relative ? mx : 1.0);
+      lam = d.lam_in[t] * (d.lambda_relative ? mx : 1.0);
     else
       lam = (T == 1) ? mx : mx * pow(d.lambda_min_ratio, (double)t / (double)(T - 1));
     d.lam[t] = lam;

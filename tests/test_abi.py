@@ -132,3 +132,40 @@ def test_screen_invalid(lib):
 def test_strerror(lib):
     for c in (0, 1, -1, -2, -3, -4, 99):
         assert isinstance(gs.strerror(c), str) and gs.strerror(c)
+
+
+def test_plan_and_tuner_argument_checks(lib, tmp_path):
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    pr = _prob()
+    h = ctypes.c_void_p()
+    assert lib.lasso_batch_plan(ctypes.byref(pr), 0, ctypes.byref(o), ctypes.c_void_p(4096),
+                                1 << 30, None, ctypes.byref(h)) == gs.GS_EINVAL
+    assert lib.lasso_batch_plan(ctypes.byref(pr), 1, ctypes.byref(o), ctypes.c_void_p(4096),
+                                1 << 30, None, None) == gs.GS_EINVAL
+    assert lib.lasso_batch_run(None, None) == gs.GS_EINVAL
+    lib.lasso_batch_plan_free(None)
+    ch = (ctypes.c_int32 * 2)()
+    assert lib.gs_autotune(ctypes.byref(pr), 0, ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30,
+                           None, 3, 2, ch) == gs.GS_EINVAL
+    assert lib.gs_autotune(ctypes.byref(pr), 1, ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30,
+                           None, 0, 2, ch) == gs.GS_EINVAL
+    assert lib.gs_autotune(ctypes.byref(pr), 1, ctypes.byref(o), None, 0, None, 3, 2,
+                           ch) == gs.GS_EWORKSPACE
+    lib.gs_tune_reset()
+    path = str(tmp_path / "tiles.json")
+    assert lib.gs_tune_save(path.encode()) == gs.GS_OK
+    import json
+    assert json.load(open(path)) == {"tiles": []}
+    assert lib.gs_tune_load(path.encode()) == gs.GS_EINVAL  # no entry
+    assert lib.gs_tune_load(str(tmp_path / "missing.json").encode()) == gs.GS_EINVAL
+    # a valid entry (dtype 0, 16-byte loads, S=4 NG=5 -> S=16 NG=3) loads and saves back
+    with open(path, "w") as f:
+        f.write('{"tiles": [\n  {"dtype": 0, "vec": 4, "gather": 0, "S": 4, "NG": 5, '
+                '"to_S": 16, "to_NG": 3}\n]}\n')
+    assert lib.gs_tune_load(path.encode()) == gs.GS_OK
+    out = str(tmp_path / "back.json")
+    assert lib.gs_tune_save(out.encode()) == gs.GS_OK
+    t = json.load(open(out))["tiles"]
+    assert t == [{"dtype": 0, "vec": 4, "gather": 0, "S": 4, "NG": 5, "to_S": 16, "to_NG": 3}]
+    lib.gs_tune_reset()

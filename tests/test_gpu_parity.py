@@ -335,3 +335,67 @@ def test_determinism_and_resume(torch, orc):
     torch.cuda.synchronize()
     for k in ("beta", "gap", "epochs", "nactive"):
         assert np.array_equal(_np(c[k]), _np(a[k])[6:]), k
+
+
+# ---------------------------------------------------- graph plans, autotuner
+
+def test_batch_plan_replays_match(torch, orc):
+    """A batch captured into a graph and replayed several times, with eager
+    work and synchronizations between the replays: every replay reproduces
+    the eager lasso_solve_batch results bit for bit, and those match the
+    oracle."""
+    d = synth.c2(B=8)
+    X, y, rows = d["X"], d["y"], d["rows"]
+    Xd, yd = _dev(torch, X, y)
+    T = 30
+    probs = [dict(X=Xd, y=yd, rows=torch.from_numpy(rows[b]).cuda(), T=T, lambda_min_ratio=1e-2)
+             for b in range(rows.shape[0])]
+    eager = gs.lasso_solve_batch(probs)
+    torch.cuda.synchronize()
+    ref = [(_np(o["beta"]).copy(), _np(o["gap"]).copy(), _np(o["epochs"]).copy()) for o in eager]
+    for b in (0, 5):
+        _check_path(X[rows[b]], y[rows[b]], eager[b], orc, _np(eager[b]["lambdas"]))
+    counts = torch.zeros((T, X.shape[1]), dtype=torch.int32, device="cuda")
+    plan = gs.BatchPlan(probs, select_counts=counts)
+    try:
+        for rep in range(3):
+            for o in plan.outputs:
+                o["beta"].fill_(7.0)
+                o["gap"].fill_(-1.0)
+            junk = torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            outs = plan.run()
+            torch.cuda.synchronize()
+            assert float(junk) == float(junk)
+            for b, o in enumerate(outs):
+                np.testing.assert_array_equal(_np(o["beta"]), ref[b][0])
+                np.testing.assert_array_equal(_np(o["gap"]), ref[b][1])
+                np.testing.assert_array_equal(_np(o["epochs"]), ref[b][2])
+        sel = sum((r[0] != 0).astype(np.int32) for r in ref)
+        np.testing.assert_array_equal(_np(counts), 3 * sel)  # counts accumulate per replay
+    finally:
+        plan.close()
+
+
+def test_autotune_choices_and_results(torch, orc):
+    """The autotuner picks, per class, a compiled layout that holds the
+    class's rows; solving after tuning still matches the oracle."""
+    gs.tune_reset()
+    cases = [(36, 400, 11), (72, 600, 12), (150, 500, 13), (300, 700, 14)]
+    probs, data = [], []
+    for n, p, seed in cases:
+        dd = synth.gaussian(seed, n, p)
+        X, y = dd["X"].astype(np.float32), dd["y"].astype(np.float32)
+        Xd, yd = _dev(torch, X, y)
+        probs.append(dict(X=Xd, y=yd, T=8, lambda_min_ratio=0.05))
+        data.append((X, y))
+    choice = gs.autotune(probs, max_lambdas=3, sample=2)
+    for (n, _p, _s), (S, NG) in zip(cases, choice):
+        vec = 4 if n % 4 == 0 else 1  # 16-byte loads need n a multiple of 4
+        assert S in (4, 16, 64) and NG >= 1
+        assert S * NG * vec >= n
+    outs = gs.lasso_solve_batch(probs)
+    torch.cuda.synchronize()
+    for (X, y), o in zip(data, outs):
+        _check_path(X, y, o, orc, _np(o["lambdas"]))
+    gs.tune_reset()

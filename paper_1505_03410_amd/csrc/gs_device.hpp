@@ -119,8 +119,15 @@ __device__ __forceinline__ uint64_t ballot(bool b) { return __ballot(b); }
 // ---- vector types for 16-byte loads
 template <typename XT, int VEC>
 struct VecLoad;
+// go_nt: the same load marked non-temporal (streamed data that is read once
+// should not displace cached data).
 template <>
 struct VecLoad<float, 4> {
+  __device__ static void go_nt(const float* p, float* o) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
   __device__ static void go(const float* p, float* o) {
     float4 v = *reinterpret_cast<const float4*>(p);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
@@ -133,6 +140,11 @@ struct VecLoad<float, 4> {
 };
 template <>
 struct VecLoad<double, 2> {
+  __device__ static void go_nt(const double* p, double* o) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    o[0] = v.x; o[1] = v.y;
+  }
   __device__ static void go(const double* p, double* o) {
     double2 v = *reinterpret_cast<const double2*>(p);
     o[0] = v.x; o[1] = v.y;
@@ -145,6 +157,7 @@ struct VecLoad<double, 2> {
 };
 template <typename XT>
 struct VecLoad<XT, 1> {
+  __device__ static void go_nt(const XT* p, XT* o) { o[0] = __builtin_nontemporal_load(p); }
   __device__ static void go(const XT* p, XT* o) { o[0] = p[0]; }
   __device__ static void go(const gbl<XT>* p, XT* o) { o[0] = p[0]; }
 };
@@ -192,6 +205,17 @@ struct ColLayout {
         const int r0 = (seg + S * m) * VEC;
         VecLoad<XT, VEC>::go(col + (r0 < n ? r0 : 0), &xv[m * VEC]);
       }
+    }
+  }
+
+  // load_raw for a column that is streamed once (non-temporal loads; no row
+  // list).
+  __device__ static __forceinline__ void load_raw_nt(const XT* col, int n, int seg,
+                                                     XT (&xv)[RPL]) {
+#pragma unroll
+    for (int m = 0; m < NG; ++m) {
+      const int r0 = (seg + S * m) * VEC;
+      VecLoad<XT, VEC>::go_nt(col + (r0 < n ? r0 : 0), &xv[m * VEC]);
     }
   }
 

@@ -274,7 +274,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
     }
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u)
-      L::load_raw(X + (int64_t)jj[u] * d.ldx, d.n, lane, nullptr, xv[u]);
+      L::load_raw_nt(X + (int64_t)jj[u] * d.ldx, d.n, lane, xv[u]);
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
       double a = 0.0, s2 = 0.0;

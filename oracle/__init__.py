@@ -195,16 +195,34 @@ def bf16_round(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def mlp_forward(params, U):
+def mlp_forward(params, U, round_h1=None):
     """4 -> 64 -> 64 -> 2 perceptron with ReLU hidden layers.
     params: dict W1 (64x4), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2).
-    U: (m, 4) inputs.  Returns outputs (m, 2) and the cache for backward."""
+    U: (m, 4) inputs.  Returns outputs (m, 2) and the cache for backward.
+    round_h1 (optional): a rounding applied to the first hidden layer before
+    it enters the second (the cache then holds the rounded values)."""
     h1p = U @ params["W1"].T + params["b1"]
     h1 = np.maximum(h1p, 0.0)
+    if round_h1 is not None:
+        h1 = round_h1(h1)
     h2p = h1 @ params["W2"].T + params["b2"]
     h2 = np.maximum(h2p, 0.0)
     out = h2 @ params["W3"].T + params["b3"]
     return out, (U, h1p, h1, h2p, h2)
+
+
+def bf16_params(params):
+    """The weights as the device network uses them: every weight matrix
+    rounded to bfloat16, biases kept."""
+    return {k: (bf16_round(v) if k.startswith("W") else np.asarray(v, dtype=np.float64))
+            for k, v in params.items()}
+
+
+def mlp_forward_bf16(params, U):
+    """The forward pass at the device's precision points: bfloat16 weight
+    matrices and a bfloat16 first hidden layer entering the second layer
+    (the matrix-core operands); everything else exact."""
+    return mlp_forward(bf16_params(params), U, round_h1=bf16_round)
 
 
 def mlp_loss(out, tgt_step, tgt_support, mask_step):

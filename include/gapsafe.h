@@ -247,6 +247,92 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
            double* radius_out, double* c_out, void* workspace,
            size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Learned warm start.  A small network proposes, at each lambda_t of a path,
+ * a starting point for Algorithm 1 in place of beta^{lambda_{t-1}}.  GAP SAFE
+ * screening is safe for any primal point (Theorem 2), so a proposal can only
+ * change the time to the certified gap, never the answer; the driver keeps it
+ * only when its duality gap is smaller than the plain warm start's.
+ *
+ * Network: 4 -> 64 -> 64 -> 2 with ReLU hidden layers.  Parameters are one
+ * FP32 array of GS_MLP_PARAMS values: W1 (64x4, row-major, row = hidden
+ * unit) at 0, b1 at 256, W2 (64x64, row = output unit) at 320, b2 at 4416,
+ * W3 (2x64) at 4480, b3 at 4608.  Evaluation rounds W1, W2, W3 and the first
+ * hidden layer (the input of the second layer, which runs on the matrix
+ * cores) to bfloat16 (nearest, ties to even) and accumulates in FP32.
+ * Outputs per feature: o0 = the scaled start beta0_j ||x_j|| / ||y||, o1 =
+ * the logit of "beta_j != 0 at lambda_t".
+ * Inputs per feature j at (beta, lambda), with c_j = x_j^T (y - X beta):
+ *   u_j = (|c_j| / lambda, lambda / lambda_max, beta_j ||x_j|| / ||y||, bmc_j)
+ * where bmc_j is the block max correlation below.
+ * All pointers are device pointers unless marked [host]; calls are
+ * asynchronous on `stream` unless stated.  Errors: GS_EINVAL for a bad size,
+ * pointer or value, GS_EWORKSPACE for a missing or small workspace, GS_EHIP
+ * for a launch failure. */
+enum { GS_MLP_PARAMS = 4610 };
+
+/* bmc_j = max over k != j in j's block of |x_j^T x_k| / (||x_j|| ||x_k||);
+ * blocks are `block` (1..64) contiguous columns, the last one possibly
+ * shorter; 0 for a block of one column or a zero column.  X as in gs_problem
+ * (column-major, ldx >= n); bmc: p floats.  FP32 accumulation. */
+int gs_block_corr(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
+                  int32_t block, float* bmc, void* stream);
+
+/* Network outputs for m feature rows: U is m x 4 (row-major), out m x 2. */
+int gs_mlp_forward(const float* params, const float* U, int32_t m, float* out,
+                   void* stream);
+
+/* Training.  targets is m x 3 (row-major): (step target, support target in
+ * {0, 1}, mask of the step term).  Loss = (1/m) sum_j [ BCE(o1_j, support_j)
+ * + mask_j (o0_j - step_j)^2 ], differentiated through the evaluation above
+ * (the bfloat16 roundings pass gradients unchanged).  The workspace holds one
+ * partial gradient per 64 rows, summed in a fixed order, so results are
+ * deterministic.
+ *   gs_mlp_grad: grad (GS_MLP_PARAMS floats) and loss (1 float), either
+ *   optional.
+ *   gs_mlp_adam: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ *   correction for step t >= 1) of params with moments adam_m, adam_v (each
+ *   GS_MLP_PARAMS floats, zero before step 1) from grad.
+ *   gs_mlp_train_step: gs_mlp_grad then gs_mlp_adam in two launches; loss
+ *   optional. */
+size_t gs_mlp_train_workspace_size(int32_t m);
+int gs_mlp_grad(const float* params, const float* U, const float* targets, int32_t m,
+                float* grad, float* loss, void* workspace, size_t ws_bytes, void* stream);
+int gs_mlp_adam(float* params, float* adam_m, float* adam_v, const float* grad, int32_t t,
+                float lr, void* stream);
+int gs_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t t, float lr,
+                      const float* U, const float* targets, int32_t m, float* loss,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* The network inputs u_j for j < p into U (p x 4): c, beta_prev, nrm2
+ * (||x_j||^2) are p FP64 values, bmc p floats; lambda, lambda_max, ynorm
+ * (||y||) positive and finite. */
+int gs_warm_features(int32_t p, const double* c, const double* beta_prev,
+                     const double* nrm2, const float* bmc, double lambda,
+                     double lambda_max, double ynorm, float* U, void* stream);
+
+/* A path (Algorithm 1 over the problem's lambda grid) whose warm start at
+ * each lambda_t, t >= 1, comes from the network:
+ *   1. a screening pass at beta^{lambda_{t-1}} over all p gives the safe set
+ *      A_plain and c;
+ *   2. the network maps u_j to (o0_j, o1_j); beta0_j = o0_j ||y|| / ||x_j||
+ *      where j is in A_plain and o1_j > 0, else 0 (coordinates outside
+ *      A_plain are zero at the optimum);
+ *   3. the duality gaps of beta0 and of beta^{lambda_{t-1}} on the problem
+ *      reduced to A_plain are compared, and the smaller one's point starts
+ *      lambda_t (ties keep the plain start);
+ *   4. Algorithm 1 runs for lambda_t from there, exactly as in lasso_path.
+ * With params NULL every lambda starts from beta^{lambda_{t-1}} (the plain
+ * path, run one lambda at a time).  The problem has no row subsample and all
+ * its outputs; block (1..64) is the bmc block width.  learned_out (optional,
+ * T int32) receives 1 where the network's start was taken, else 0.
+ * Synchronizes `stream` (the lambda grid and the active set sizes are read
+ * on the host).  Returns the codes of lasso_path. */
+size_t lasso_path_learned_workspace_size(const gs_problem* prob);
+int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float* params,
+                       int32_t block, int32_t* learned_out, void* workspace,
+                       size_t ws_bytes, void* stream);
+
 /* Optional kernel timing for benchmarks (off by default).  When on, the
  * library records a pair of HIP events on the launch stream around each
  * launch of the named kernels and accumulates their elapsed time:

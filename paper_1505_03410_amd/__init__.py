@@ -68,7 +68,15 @@ EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_
            "lasso_solve_batch", "lasso_batch_plan", "lasso_batch_run", "lasso_batch_plan_free",
            "gs_autotune", "gs_tune_save", "gs_tune_load", "gs_tune_reset",
            "screen_workspace_size", "screen", "gs_timing_enable",
-           "gs_timing_reset", "gs_timing_query", "lasso_strerror"]
+           "gs_timing_reset", "gs_timing_query", "lasso_strerror",
+           "gs_block_corr", "gs_mlp_forward", "gs_mlp_train_workspace_size", "gs_mlp_grad",
+           "gs_mlp_adam", "gs_mlp_train_step", "gs_warm_features",
+           "lasso_path_learned_workspace_size", "lasso_path_learned"]
+
+MLP_PARAMS = 4610
+# offsets of the parameter array (include/gapsafe.h): name -> (offset, shape)
+MLP_LAYOUT = {"W1": (0, (64, 4)), "b1": (256, (64,)), "W2": (320, (64, 64)),
+              "b2": (4416, (64,)), "W3": (4480, (2, 64)), "b3": (4608, (2,))}
 
 _lib = None
 
@@ -124,6 +132,25 @@ def load_library(path: str = LIB_PATH):
     lib.gs_timing_query.restype = ctypes.c_int
     lib.lasso_strerror.argtypes = [ctypes.c_int]
     lib.lasso_strerror.restype = ctypes.c_char_p
+    i32, i64, sz, f32, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float, ctypes.c_double
+    lib.gs_block_corr.argtypes = [i32, i32, i64, i32, vp, i32, vp, vp]
+    lib.gs_block_corr.restype = ctypes.c_int
+    lib.gs_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+    lib.gs_mlp_forward.restype = ctypes.c_int
+    lib.gs_mlp_train_workspace_size.argtypes = [i32]
+    lib.gs_mlp_train_workspace_size.restype = sz
+    lib.gs_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp, sz, vp]
+    lib.gs_mlp_grad.restype = ctypes.c_int
+    lib.gs_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, vp]
+    lib.gs_mlp_adam.restype = ctypes.c_int
+    lib.gs_mlp_train_step.argtypes = [vp, vp, vp, i32, f32, vp, vp, i32, vp, vp, sz, vp]
+    lib.gs_mlp_train_step.restype = ctypes.c_int
+    lib.gs_warm_features.argtypes = [i32, vp, vp, vp, vp, f64, f64, f64, vp, vp]
+    lib.gs_warm_features.restype = ctypes.c_int
+    lib.lasso_path_learned_workspace_size.argtypes = [P(gs_problem)]
+    lib.lasso_path_learned_workspace_size.restype = sz
+    lib.lasso_path_learned.argtypes = [P(gs_problem), P(gs_opts), vp, i32, vp, vp, sz, vp]
+    lib.lasso_path_learned.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -445,3 +472,151 @@ def timing_query(kernel: str):
 
 def wallclock_hz() -> float:
     return load_library().gs_wallclock_hz()
+
+
+# ------------------------------------------------------- learned warm start
+
+def _f32_dev(t, shape_last=None, name="tensor"):
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"{name} must have shape (m, {shape_last})")
+    return t
+
+
+def mlp_params_to_flat(params, device="cuda"):
+    """dict W1, b1, W2, b2, W3, b3 (arrays) -> flat float32 device tensor."""
+    torch = _torch()
+    flat = np.zeros(MLP_PARAMS, dtype=np.float32)
+    for k, (off, shp) in MLP_LAYOUT.items():
+        a = np.asarray(params[k], dtype=np.float32)
+        if a.shape != shp:
+            raise ValueError(f"{k} must have shape {shp}")
+        flat[off:off + a.size] = a.reshape(-1)
+    return torch.from_numpy(flat).to(device)
+
+
+def mlp_flat_to_params(flat):
+    """flat parameter array (tensor or numpy) -> dict of float64 numpy arrays."""
+    a = flat.detach().cpu().numpy() if hasattr(flat, "detach") else np.asarray(flat)
+    return {k: a[off:off + int(np.prod(shp))].astype(np.float64).reshape(shp)
+            for k, (off, shp) in MLP_LAYOUT.items()}
+
+
+def block_corr(X, block: int = 50, stream=None):
+    """Block max correlation of the columns of X (gs_block_corr): p floats."""
+    torch = _torch()
+    n, p, ld = _design(X)
+    out = torch.empty(p, dtype=torch.float32, device=X.device)
+    _check(load_library().gs_block_corr(n, p, ld, _dtype_code(X), _ptr(X), int(block), _ptr(out),
+                                        _stream_ptr(stream)), allow_not_converged=False)
+    return out
+
+
+def mlp_forward(params, U, stream=None):
+    """Network outputs (m, 2) for inputs U (m, 4) (gs_mlp_forward)."""
+    torch = _torch()
+    _f32_dev(params, name="params")
+    _f32_dev(U, 4, "U")
+    out = torch.empty((U.shape[0], 2), dtype=torch.float32, device=U.device)
+    _check(load_library().gs_mlp_forward(_ptr(params), _ptr(U), U.shape[0], _ptr(out),
+                                         _stream_ptr(stream)), allow_not_converged=False)
+    return out
+
+
+def _train_ws(m, workspace, device):
+    need = load_library().gs_mlp_train_workspace_size(m)
+    if workspace is not None and workspace.numel() >= need:
+        return workspace
+    return _workspace(need, device)
+
+
+def mlp_grad(params, U, targets, stream=None, workspace=None):
+    """(gradient (MLP_PARAMS,), loss (1,)) of the training loss (gs_mlp_grad)."""
+    torch = _torch()
+    _f32_dev(params, name="params")
+    _f32_dev(U, 4, "U")
+    _f32_dev(targets, 3, "targets")
+    m = U.shape[0]
+    if targets.shape[0] != m:
+        raise ValueError("U and targets must have the same number of rows")
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=U.device)
+    loss = torch.empty(1, dtype=torch.float32, device=U.device)
+    ws = _train_ws(m, workspace, U.device)
+    _check(load_library().gs_mlp_grad(_ptr(params), _ptr(U), _ptr(targets), m, _ptr(g),
+                                      _ptr(loss), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+           allow_not_converged=False)
+    return g, loss
+
+
+def mlp_adam(params, adam_m, adam_v, grad, t: int, lr: float, stream=None):
+    """One Adam step in place (gs_mlp_adam)."""
+    for a, nm in ((params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v"), (grad, "grad")):
+        _f32_dev(a, name=nm)
+    _check(load_library().gs_mlp_adam(_ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(grad),
+                                      int(t), float(lr), _stream_ptr(stream)),
+           allow_not_converged=False)
+
+
+def mlp_train_step(params, adam_m, adam_v, t: int, lr: float, U, targets, loss=None,
+                   stream=None, workspace=None):
+    """Forward, backward and one Adam step in place (gs_mlp_train_step)."""
+    for a, nm in ((params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+        _f32_dev(a, name=nm)
+    _f32_dev(U, 4, "U")
+    _f32_dev(targets, 3, "targets")
+    m = U.shape[0]
+    ws = _train_ws(m, workspace, U.device)
+    _check(load_library().gs_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(t),
+                                            float(lr), _ptr(U), _ptr(targets), m, _ptr(loss),
+                                            _ptr(ws), ws.numel(), _stream_ptr(stream)),
+           allow_not_converged=False)
+    return ws
+
+
+def warm_features(c, beta_prev, nrm2, bmc, lam, lam_max, ynorm, stream=None):
+    """Network inputs (p, 4) at (beta_prev, lam) (gs_warm_features)."""
+    torch = _torch()
+    p = c.numel()
+    for a, nm in ((c, "c"), (beta_prev, "beta_prev"), (nrm2, "nrm2")):
+        if a.dtype != torch.float64 or not a.is_contiguous() or a.numel() != p:
+            raise ValueError(f"{nm} must be p contiguous float64 values")
+    _f32_dev(bmc, name="bmc")
+    U = torch.empty((p, 4), dtype=torch.float32, device=c.device)
+    _check(load_library().gs_warm_features(p, _ptr(c), _ptr(beta_prev), _ptr(nrm2), _ptr(bmc),
+                                           float(lam), float(lam_max), float(ynorm), _ptr(U),
+                                           _stream_ptr(stream)), allow_not_converged=False)
+    return U
+
+
+def lasso_path_learned(X, y, params=None, *, block: int = 50, T: int = 100,
+                       lambdas: Optional[Sequence[float]] = None, relative: bool = False,
+                       lambda_min_ratio: float = 1e-3, beta_init=None, eps_rel: float = 1e-8,
+                       screen_every: int = 10, max_epochs: int = 100000, schedule="auto",
+                       cd_mode="auto", stream=None, out=None, workspace=None, stats=None):
+    """A path whose warm starts come from the network ``params`` (flat
+    float32 device tensor; None = plain starts, one lambda at a time); see
+    lasso_path_learned in include/gapsafe.h.  Synchronizes the stream.  The
+    result has the entries of lasso_path plus ``learned`` (T int32, 1 where
+    the network's start was taken)."""
+    torch = _torch()
+    lib = load_library()
+    pr, out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
+                              lambda_min_ratio=lambda_min_ratio, beta_init=beta_init,
+                              rows=None, out=out)
+    if params is not None:
+        _f32_dev(params, name="params")
+        if params.numel() != MLP_PARAMS:
+            raise ValueError(f"params must hold {MLP_PARAMS} values")
+    o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode, stats=stats)
+    need = lib.lasso_path_learned_workspace_size(ctypes.byref(pr))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+    learned = torch.empty(pr.T, dtype=torch.int32, device=X.device)
+    rc = lib.lasso_path_learned(ctypes.byref(pr), ctypes.byref(o), _ptr(params), int(block),
+                                _ptr(learned), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc)
+    out["rc"] = rc
+    out["learned"] = learned
+    out["workspace"] = ws
+    return out

@@ -549,6 +549,8 @@ int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts p
 
 }  // namespace
 
+int gs::set_hip_error(hipError_t e, const char* where) { return fail_hip(e, where); }
+
 // ======================================================================= ABI
 
 extern "C" {

@@ -75,6 +75,15 @@ struct PathOpts {
   long long* stats;        // kNumStats or null
 };
 
+// Parameters of the warm-start network (4 -> 64 -> 64 -> 2), one FP32 array:
+// W1 (64x4, row = hidden unit), b1, W2 (64x64, row = output unit), b2,
+// W3 (2x64), b3.
+constexpr int kMlpW1 = 0, kMlpB1 = 256, kMlpW2 = 320, kMlpB2 = 4416, kMlpW3 = 4480,
+              kMlpB3 = 4608, kMlpParams = 4610;
+
+// Records the text of a HIP failure for lasso_strerror and returns GS_EHIP.
+int set_hip_error(hipError_t e, const char* where);
+
 // Scalars of the wide schedule's state machine (one problem).
 struct WideState {
   // set by init

@@ -169,3 +169,48 @@ def test_plan_and_tuner_argument_checks(lib, tmp_path):
     t = json.load(open(out))["tiles"]
     assert t == [{"dtype": 0, "vec": 4, "gather": 0, "S": 4, "NG": 5, "to_S": 16, "to_NG": 3}]
     lib.gs_tune_reset()
+
+
+def test_learned_warm_start_argument_checks(lib):
+    """The learned-warm-start entry points reject bad arguments before any
+    launch (fake device pointers are never dereferenced)."""
+    fake = ctypes.c_void_p(4096)
+    assert lib.gs_block_corr(8, 20, 8, gs.GS_F32, fake, 0, fake, None) == gs.GS_EINVAL
+    assert lib.gs_block_corr(8, 20, 8, gs.GS_F32, fake, 65, fake, None) == gs.GS_EINVAL
+    assert lib.gs_block_corr(8, 20, 4, gs.GS_F32, fake, 50, fake, None) == gs.GS_EINVAL
+    assert lib.gs_block_corr(8, 20, 8, 7, fake, 50, fake, None) == gs.GS_EINVAL
+    assert lib.gs_mlp_forward(fake, fake, -1, fake, None) == gs.GS_EINVAL
+    assert lib.gs_mlp_forward(None, fake, 5, fake, None) == gs.GS_EINVAL
+    assert lib.gs_mlp_forward(None, None, 0, None, None) == gs.GS_OK  # nothing to do
+    assert lib.gs_mlp_train_workspace_size(0) == 0
+    # one partial gradient + loss per 64 rows, 256-byte aligned
+    assert lib.gs_mlp_train_workspace_size(64) == (4611 * 4 + 255) // 256 * 256
+    assert lib.gs_mlp_train_workspace_size(65) == (2 * 4611 * 4 + 255) // 256 * 256
+    assert lib.gs_mlp_grad(fake, fake, fake, 64, fake, fake, None, 0, None) == gs.GS_EWORKSPACE
+    assert lib.gs_mlp_grad(fake, fake, fake, 64, fake, fake, fake, 100, None) == gs.GS_EWORKSPACE
+    assert lib.gs_mlp_grad(fake, fake, None, 64, fake, fake, fake, 1 << 20, None) == gs.GS_EINVAL
+    assert lib.gs_mlp_adam(fake, fake, fake, fake, 0, 1e-3, None) == gs.GS_EINVAL
+    assert lib.gs_mlp_adam(fake, fake, fake, fake, 1, float("nan"), None) == gs.GS_EINVAL
+    assert lib.gs_mlp_train_step(fake, fake, fake, 0, 1e-3, fake, fake, 64, None, fake,
+                                 1 << 20, None) == gs.GS_EINVAL
+    assert lib.gs_warm_features(10, fake, fake, fake, fake, 0.0, 1.0, 1.0, fake,
+                                None) == gs.GS_EINVAL
+    assert lib.gs_warm_features(10, fake, fake, fake, fake, 1.0, 1.0, float("inf"), fake,
+                                None) == gs.GS_EINVAL
+    o = gs.gs_opts()
+    lib.gs_opts_default(ctypes.byref(o))
+    pr = _prob()
+    need = lib.lasso_path_learned_workspace_size(ctypes.byref(pr))
+    assert need >= lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
+    assert lib.lasso_path_learned_workspace_size(None) == 0
+    rows = _prob(rows=4096)
+    assert lib.lasso_path_learned_workspace_size(ctypes.byref(rows)) == 0
+    assert lib.lasso_path_learned(ctypes.byref(rows), ctypes.byref(o), fake, 50, None, fake,
+                                  need, None) == gs.GS_EINVAL
+    assert lib.lasso_path_learned(ctypes.byref(pr), ctypes.byref(o), fake, 0, None, fake,
+                                  need, None) == gs.GS_EINVAL
+    assert lib.lasso_path_learned(ctypes.byref(pr), ctypes.byref(o), fake, 50, None, fake,
+                                  need - 1, None) == gs.GS_EWORKSPACE
+    big = _prob(n=4096, ldx=4096)
+    assert lib.lasso_path_learned(ctypes.byref(big), ctypes.byref(o), fake, 50, None, fake,
+                                  1 << 40, None) == gs.GS_EUNSUPPORTED

@@ -174,6 +174,67 @@ def bench_c3(gs, torch, synth, tune):
                          "lambda/lambda_max U[0.01,0.5]")
 
 
+def bench_c4(gs, torch, synth, params_file, piece, nl, seed=4):
+    """Learned against plain warm starts on the C4 workload (1000 x 100000
+    FP32, blocks of 50 columns with correlation 0.7, the grid of 100 lambdas
+    down to lambda_max/1000, every lambda to gap <= 1e-8 ||y||^2), over the
+    first `nl` lambdas of the grid.  Both paths run in pieces of `piece`
+    lambdas (each piece warm-started from the previous one's last solution)
+    so that progress shows; the learned time includes the block correlations,
+    features, inference and the extra gap checks."""
+    import numpy as np
+    d = synth.c4(seed=seed)
+    Xd = gs.colmajor_to_device(d["X"])
+    yd = torch.from_numpy(d["y"]).cuda()
+    yy = float((d["y"].astype(np.float64) ** 2).sum())
+    rel = 1e-3 ** (np.arange(100) / 99)
+    P = None
+    if params_file:
+        P = torch.from_numpy(np.load(params_file).astype(np.float32)).cuda()
+
+    def run(name, learned):
+        prev, ws, res = None, None, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(0, nl, piece):
+            sub = rel[k:min(k + piece, nl)]
+            if learned:
+                r = gs.lasso_path_learned(Xd, yd, P, lambdas=sub, relative=True,
+                                          beta_init=prev, workspace=ws)
+            else:
+                r = gs.lasso_path(Xd, yd, lambdas=sub, relative=True, beta_init=prev,
+                                  workspace=ws)
+            ws = r["workspace"]
+            prev = r["beta"][-1].contiguous()
+            ep = r["epochs"].cpu().numpy()
+            res.append(r)
+            _log(f"c4 {name}: lambdas {k}..{k + len(sub) - 1} epochs {int(ep.sum())} "
+                 f"at {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cat = lambda key: np.concatenate([x[key].cpu().numpy() for x in res])
+        st, gap, ep = cat("status"), cat("gap"), cat("epochs")
+        out = dict(seconds=round(el, 3), epochs=int(ep.sum()),
+                   certified=bool((st == 0).all() and (gap <= 1e-8 * yy).all()),
+                   epochs_per_lambda=[int(e) for e in ep])
+        if learned:
+            fl = cat("learned")
+            out["network_start_fraction"] = round(float(fl[1:].mean()), 3)
+            out["network_start_lambdas"] = int(fl.sum())
+        return out
+
+    plain = run("plain", False)
+    res = {"workload": "c4: n=1000 p=100000 FP32, 2000 blocks of 50 columns with "
+                       "correlation 0.7, 50-sparse truth, SNR 5, seed %d; lambdas 0..%d of "
+                       "the T=100 grid lambda_max..lambda_max/1000 (down to lambda_max/%.0f), "
+                       "eps=1e-8||y||^2" % (seed, nl - 1, 1.0 / rel[nl - 1]),
+           "piece": piece, "lambdas": nl, "plain": plain}
+    if P is not None:
+        res["learned"] = run("learned", True)
+        res["params"] = os.path.relpath(params_file, ROOT)
+    return res
+
+
 def copy_calibration(torch, mb, reps):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     nel = int(mb * 1e6) // 4
@@ -212,6 +273,14 @@ def main():
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--c3", action="store_true", help="also run the 512-problem uneven batch")
     ap.add_argument("--tune", action="store_true", help="autotune tiles before the c3 batch")
+    ap.add_argument("--c4", action="store_true",
+                    help="also compare learned and plain warm starts on the c4 path")
+    ap.add_argument("--c4-params", default=os.path.join(ROOT, "paper_1505_03410_amd",
+                                                        "warm_mlp.npy"))
+    ap.add_argument("--c4-piece", type=int, default=5)
+    ap.add_argument("--c4-lambdas", type=int, default=60,
+                    help="lambdas of the 100-point c4 grid to solve (the tail beyond 60 "
+                         "takes tens of minutes per path)")
     ap.add_argument("--copy-mb", type=float, default=0.0,
                     help="only run a plain device copy of this many MB (counter calibration)")
     a = ap.parse_args()
@@ -259,6 +328,11 @@ def main():
         _log("c3: 512 uneven problems")
         c3 = bench_c3(gs, torch, synth, a.tune)
         _log(f"c3: {c3['seconds']:.3f} s, p50 {c3['p50_ms']} ms, p99 {c3['p99_ms']} ms")
+    c4 = None
+    if a.c4:
+        _log("c4: learned vs plain warm starts, 1000x100000, 100 lambdas")
+        pf = a.c4_params if a.c4_params and os.path.exists(a.c4_params) else None
+        c4 = bench_c4(gs, torch, synth, pf, a.c4_piece, a.c4_lambdas)
     cpu = None
     if not a.no_cpu:
         _log("cpu baseline: oracle, whole c1 path")
@@ -267,7 +341,7 @@ def main():
                "sample": f"whole c1 path (100 lambdas), median of {cb['reps']} runs, "
                          "FP64 C oracle, one thread"}
     if path is None:
-        print(json.dumps({"roofline": roof}), flush=True)
+        print(json.dumps({"roofline": roof, "learned_warm_start": c4}), flush=True)
         return
     line = {
         "metric": "Lasso path seconds to gap<=1e-8||y||^2 (c1 72x7129); X^T theta HBM GB/s",
@@ -295,6 +369,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": {"c2": c2, "c3": c3},
+        "learned_warm_start": c4,
     }
     print(json.dumps(line), flush=True)
 

@@ -260,8 +260,14 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
  * W3 (2x64) at 4480, b3 at 4608.  Evaluation rounds W1, W2, W3 and the first
  * hidden layer (the input of the second layer, which runs on the matrix
  * cores) to bfloat16 (nearest, ties to even) and accumulates in FP32.
- * Outputs per feature: o0 = the scaled start beta0_j ||x_j|| / ||y||, o1 =
- * the logit of "beta_j != 0 at lambda_t".
+ * Outputs per feature: o0 = the change of the coefficient from the previous
+ * point in units of lambda_t / ||x_j||^2, (beta0_j - beta_prev_j) ||x_j||^2 /
+ * lambda_t, o1 = the logit of "beta_j != 0 at lambda_t".  (Predicting the
+ * change rather than the value keeps the proposal as precise as the previous
+ * point where the network proposes no change: a value passed through BF16
+ * weights would carry a relative error of about 2^-8.  In these units the
+ * change of a support coefficient is of the order of the relative lambda
+ * step, whatever the scale of X and y.)
  * Inputs per feature j at (beta, lambda), with c_j = x_j^T (y - X beta):
  *   u_j = (|c_j| / lambda, lambda / lambda_max, beta_j ||x_j|| / ||y||, bmc_j)
  * where bmc_j is the block max correlation below.
@@ -312,17 +318,19 @@ int gs_warm_features(int32_t p, const double* c, const double* beta_prev,
                      double lambda_max, double ynorm, float* U, void* stream);
 
 /* A path (Algorithm 1 over the problem's lambda grid) whose warm start at
- * each lambda_t, t >= 1, comes from the network:
- *   1. a screening pass at beta^{lambda_{t-1}} over all p gives the safe set
- *      A_plain and c;
- *   2. the network maps u_j to (o0_j, o1_j); beta0_j = o0_j ||y|| / ||x_j||
- *      where j is in A_plain and o1_j > 0, else 0 (coordinates outside
- *      A_plain are zero at the optimum);
+ * each lambda_t with a previous point comes from the network (t >= 1, and
+ * t = 0 when beta_init is given: the previous point is then beta_init, so a
+ * path may be run in consecutive pieces):
+ *   1. a screening pass at the previous point beta^{lambda_{t-1}} over all
+ *      p gives the safe set A_plain and c;
+ *   2. the network maps u_j to (o0_j, o1_j); beta0_j = beta_prev_j +
+ *      o0_j lambda_t / ||x_j||^2 where j is in A_plain and o1_j > 0, else 0
+ *      (coordinates outside A_plain are zero at the optimum);
  *   3. the duality gaps of beta0 and of beta^{lambda_{t-1}} on the problem
  *      reduced to A_plain are compared, and the smaller one's point starts
  *      lambda_t (ties keep the plain start);
  *   4. Algorithm 1 runs for lambda_t from there, exactly as in lasso_path.
- * With params NULL every lambda starts from beta^{lambda_{t-1}} (the plain
+ * With params NULL every lambda starts from the previous point (the plain
  * path, run one lambda at a time).  The problem has no row subsample and all
  * its outputs; block (1..64) is the bmc block width.  learned_out (optional,
  * T int32) receives 1 where the network's start was taken, else 0.

@@ -387,14 +387,16 @@ __global__ __launch_bounds__(256) void k_absmax_ynorm(const double* __restrict__
 
 // The network's start, on the first q positions of act (the plain pass's
 // safe active set; everything else was zeroed beforehand): where the support
-// logit is positive, beta0_j = o0_j ||y|| / ||x_j||.
+// logit is positive, beta0_j = beta_prev_j + o0_j lambda / ||x_j||^2 (the
+// network predicts the change of the coefficient in units of
+// lambda / ||x_j||^2), else 0.
 __global__ void k_warm_set(const float* __restrict__ out, const int32_t* __restrict__ act, int q,
-                           const double* __restrict__ nrm2, double ynorm,
-                           double* __restrict__ beta0) {
+                           const double* __restrict__ bprev, const double* __restrict__ nrm2,
+                           double lam, double* __restrict__ beta0) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < q; k += gridDim.x * blockDim.x) {
     const int j = act[k];
     if (out[(int64_t)j * 2 + 1] > 0.f && nrm2[j] > 0.0)
-      beta0[j] = (double)out[(int64_t)j * 2] * ynorm / sqrt(nrm2[j]);
+      beta0[j] = bprev[j] + (double)out[(int64_t)j * 2] * lam / nrm2[j];
   }
 }
 
@@ -673,7 +675,7 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
   for (int t = 0; t < T; ++t) {
     const double* bprev = t == 0 ? prob->beta_init : prob->beta_out + (t - 1) * P;
     const double* startp = bprev;
-    if (params && t > 0) {
+    if (params && bprev) {
       // plain screening pass at the previous solution: A_plain and c
       rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], nullptr, 0, w.act, w.q,
                   w.scal + 2, w.scal + 4, w.scal + 5, w.c, w.inner, w.inner_bytes, s);
@@ -691,7 +693,7 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
         rc = last_launch("k_fill_f64");
         if (rc) return rc;
         hipLaunchKernelGGL(k_warm_set, dim3(grid_for(q, 256)), dim3(256), 0, s, w.out, w.act, q,
-                           w.nrm2, ynorm, w.beta0);
+                           bprev, w.nrm2, lam[t], w.beta0);
         rc = last_launch("k_warm_set");
         if (rc) return rc;
         // both candidates' gaps on the reduced problem over A_plain

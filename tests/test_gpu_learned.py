@@ -294,11 +294,11 @@ def test_learned_path_plain_mode_certified(torch, orc):
     assert np.all(_np(got["learned"]) == 0)
 
 
-@pytest.mark.parametrize("kind", ["random", "copy_prev", "huge"])
+@pytest.mark.parametrize("kind", ["random", "no_change", "huge"])
 def test_learned_path_any_network_certified(torch, orc, kind):
     """Whatever the network proposes, every lambda ends certified with the
-    plain path's guarantees: a random network, one that proposes the
-    previous solution again, and one whose proposals are absurdly large
+    plain path's guarantees: a random network, one that proposes no change
+    to the previous solution, and one whose proposals are absurdly large
     (which must never be taken)."""
     X, y = _c4_small(22)
     rng = np.random.default_rng(23)
@@ -306,11 +306,12 @@ def test_learned_path_any_network_certified(torch, orc, kind):
         P = _random_params(rng)
     else:
         P = {k: np.zeros(s) for k, (_, s) in gs.MLP_LAYOUT.items()}
-        # h0 = relu(u2), h1 = relu(-u2), passed through; o0 = h0 - h1 = u2;
-        # o1 = h0 + h1 - 2^-20 > 0 exactly where beta_prev != 0
+        # h0 = relu(u2), h1 = relu(-u2), passed through the second layer;
+        # o0 = 0 (no change); o1 = h0 + h1 - 2^-20 > 0 exactly where
+        # beta_prev != 0, so the proposal is the previous point restricted
+        # to the safe set
         P["W1"][0, 2], P["W1"][1, 2] = 1.0, -1.0
         P["W2"][0, 0], P["W2"][1, 1] = 1.0, 1.0
-        P["W3"][0, 0], P["W3"][0, 1] = 1.0, -1.0
         P["W3"][1, 0], P["W3"][1, 1] = 1.0, 1.0
         P["b3"][1] = -2.0 ** -20
         if kind == "huge":
@@ -323,6 +324,11 @@ def test_learned_path_any_network_certified(torch, orc, kind):
     assert flags[0] == 0 and set(np.unique(flags)) <= {0, 1}
     if kind == "huge":
         assert np.all(flags == 0)
+    if kind == "no_change":
+        # the proposal differs from the previous point only where that point
+        # has nonzeros outside the safe set; there the smaller gap may win,
+        # elsewhere the tie keeps the plain start
+        assert flags.sum() <= len(flags) - 1
 
 
 def test_learned_path_wide_c4_shape(torch, orc):
@@ -334,3 +340,22 @@ def test_learned_path_wide_c4_shape(torch, orc):
     got = gs.lasso_path_learned(Xd, yd, gs.mlp_params_to_flat(P), T=8, lambda_min_ratio=0.1)
     lams = _np(got["lambdas"])
     _check_path(X, y, got, orc, lams)
+
+
+def test_learned_path_in_pieces(torch, orc):
+    """A path run in two pieces (the second warm-started from the first's
+    last solution, where the network may already propose) certifies every
+    lambda of the whole grid."""
+    X, y = _c4_small(26)
+    Xd, yd = _dev(torch, X, y)
+    P = gs.mlp_params_to_flat(_random_params(np.random.default_rng(27)))
+    rel = 0.01 ** (np.arange(16) / 15)
+    a = gs.lasso_path_learned(Xd, yd, P, lambdas=rel[:7], relative=True)
+    b = gs.lasso_path_learned(Xd, yd, P, lambdas=rel[7:], relative=True,
+                              beta_init=a["beta"][-1].contiguous())
+    got = {k: torch.cat([a[k], b[k]]) for k in ("beta", "gap", "status", "lambdas")}
+    lams = _np(got["lambdas"])
+    lmax = orc.precompute(X, y)["lambda_max"]
+    np.testing.assert_allclose(lams, lmax * rel, rtol=1e-12)
+    _check_path(X, y, got, orc, lams)
+    assert _np(a["learned"])[0] == 0

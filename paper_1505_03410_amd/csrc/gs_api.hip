@@ -386,7 +386,7 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
     for (int i = 0; i < chunk; ++i) {
       void* ar[] = {&d, &st, &wb, &zero};
       HIPCHK(launch(kWideRefresh[dt], dim3(1), dim3(kRefreshThreads), ar, 0, s));
-      void* as[] = {&d, &st, &wb, &zero};
+      void* as[] = {&d, &st, &wb};
       HIPCHK(timed_launch(kTimeSweep, w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), as,
                           0, s));
       void* ag[] = {&d, &st, &wb, &nsweep, &zero, &nd, &nd, &nd, &po};
@@ -690,8 +690,8 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, cons
   int nsweep = std::max(1, std::min(kWideSweepBlocks, (q + kSweepWaves * kSweepU - 1) /
                                                           (kSweepWaves * kSweepU)));
   {
-    void* a[] = {&d, &st, &wb, &one};
-    HIPCHK(timed_launch(kTimeSweep, w->sweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0,
+    void* a[] = {&d, &st, &wb};
+    HIPCHK(timed_launch(kTimeSweep, w->sweep_nrm_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0,
                         s));
   }
   {

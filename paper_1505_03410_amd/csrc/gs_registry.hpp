@@ -15,7 +15,8 @@ struct NarrowEntry {
 struct WideEntry {
   int dtype, vec, NG;       // sweep layout: 64 lanes over rows
   const void* pre_kernel;   // k_wide_pre<...>
-  const void* sweep_kernel; // k_wide_sweep<...>
+  const void* sweep_kernel; // k_wide_sweep<..., false>
+  const void* sweep_nrm_kernel;  // k_wide_sweep<..., true>: also ||x_j||^2
   int nmax() const { return 64 * NG * vec; }
 };
 

@@ -162,7 +162,8 @@ const void* const kFillI32 = reinterpret_cast<const void*>(&k_fill_i32);
   {                                                                             \
     sizeof(XT) == 8 ? 1 : 0, VEC, NG,                                           \
         reinterpret_cast<const void*>(&k_wide_pre<XT, VEC, NG>),                \
-        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG>)               \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, false>),       \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, true>)         \
   }
 
 // Ordered by dtype, vector width, then capacity (64 * NG * VEC rows).

@@ -20,7 +20,14 @@
 namespace gs {
 
 constexpr int kSweepWaves = 4;      // waves per sweep block
-constexpr int kSweepU = 4;          // columns in flight per wave
+// Columns in flight per wave of the sweep.  Two keep the 1000-row FP32
+// layout at 4 waves per SIMD without spills (about 110 VGPRs); four need
+// about 150 VGPRs (3 waves per SIMD) and measured about 5% slower on the
+// 1000 x 100000 sweep.
+#ifndef GS_SWEEP_U
+#define GS_SWEEP_U 2
+#endif
+constexpr int kSweepU = GS_SWEEP_U;
 constexpr int kTestTile = 2048;     // entries per test/compact block
 constexpr int kRefreshThreads = 1024;
 
@@ -238,11 +245,12 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
 }
 
 // ---- the sweep: c_k = x_{A[k]}^T rho for the k of A, per-block partials
-// (max |c|, ||beta||_1, sum |beta_j| ||x_j||, max ||x_j||).  When
-// with_nrm2 is set the column norms are computed here too (screen()).
-template <typename XT, int VEC, int NG>
+// (max |c|, ||beta||_1, sum |beta_j| ||x_j||, max ||x_j||).  With WN the
+// column norms are computed here too (screen()).
+template <typename XT, int VEC, int NG, bool WN>
 __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, WideState* st,
-                                                                 WideBufs wb, int with_nrm2) {
+                                                                 WideBufs wb) {
+  constexpr bool with_nrm2 = WN;
   using L = ColLayout<XT, VEC, 64, NG, false>;
   constexpr int RPL = L::RPL;
   __shared__ double sh[64 * kSweepWaves];
@@ -267,10 +275,18 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
   for (int base = wid * kSweepU; base < q; base += W * kSweepU) {
     XT xv[kSweepU][RPL];
     int jj[kSweepU];
+    double nrv[kSweepU], bv[kSweepU];
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
       const int k = base + u < q ? base + u : q - 1;
       jj[u] = full ? k : act[k];
+    }
+    // the per-column scalars travel with the column loads, so one memory
+    // round trip serves the whole step
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      nrv[u] = with_nrm2 ? 0.0 : d.nrm2[jj[u]];
+      bv[u] = d.beta[jj[u]];
     }
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u)
@@ -292,8 +308,8 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
         const int j = jj[u];
         d.c[base + u] = a;
         if (with_nrm2) d.nrm2[j] = s2;
-        const double nr = with_nrm2 ? s2 : d.nrm2[j];
-        const double b = d.beta[j];
+        const double nr = with_nrm2 ? s2 : nrv[u];
+        const double b = bv[u];
         Ml = fmax(Ml, fabs(a));
         l1 += fabs(b);
         sb += fabs(b) * sqrt(nr);

@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the sweep kernel from the FETCH_SIZE and WRITE_SIZE
 # counter runs in profiles/k_wide_sweep_c4_hbm_counters.md (scaled by a plain
 # copy of known size), valid while the kernel's sources hash to SWEEP_SRC_SHA1.
-SWEEP_TRAFFIC_BYTES = 403.4e6
-SWEEP_SRC_SHA1 = "af8e92c689e6f7ab"
+SWEEP_TRAFFIC_BYTES = 408.8e6
+SWEEP_SRC_SHA1 = "9c0d1b35e3d7c287"
 SWEEP_SRCS = ("paper_1505_03410_amd/csrc/gs_wide.hpp", "paper_1505_03410_amd/csrc/gs_device.hpp")
 
 

@@ -149,12 +149,14 @@ def bench_c3(gs, torch, synth, tune):
     import numpy as np
     params = synth.c3_params()
     probs, keep = [], []
-    for pr in params:
+    for i, pr in enumerate(params):
         d = synth.c3_problem(pr)
         Xd = gs.colmajor_to_device(d["X"])
         yd = torch.from_numpy(d["y"]).cuda()
         keep.append((Xd, yd))
         probs.append(dict(X=Xd, y=yd, T=1, lambdas=[d["lambda_ratio"]], relative=True))
+        if (i + 1) % 64 == 0:
+            _log(f"c3: {i + 1} problems drawn and uploaded")
     _log(f"c3: {len(probs)} problems uploaded")
     tiles = None
     if tune:
@@ -162,8 +164,10 @@ def bench_c3(gs, torch, synth, tune):
         tiles = sorted(set(ch))
     B = len(probs)
     ts = torch.zeros(2 * B, dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
     gs.lasso_solve_batch(probs, timestamps=ts)
     torch.cuda.synchronize()
+    _log(f"c3: warm-up batch solved in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     outs = gs.lasso_solve_batch(probs, timestamps=ts)
     torch.cuda.synchronize()
@@ -341,7 +345,8 @@ def main():
                "sample": f"whole c1 path (100 lambdas), median of {cb['reps']} runs, "
                          "FP64 C oracle, one thread"}
     if path is None:
-        print(json.dumps({"roofline": roof, "learned_warm_start": c4}), flush=True)
+        print(json.dumps({"roofline": roof, "batched": {"c2": c2, "c3": c3},
+                          "learned_warm_start": c4}), flush=True)
         return
     line = {
         "metric": "Lasso path seconds to gap<=1e-8||y||^2 (c1 72x7129); X^T theta HBM GB/s",

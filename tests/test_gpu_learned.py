@@ -359,3 +359,29 @@ def test_learned_path_in_pieces(torch, orc):
     np.testing.assert_allclose(lams, lmax * rel, rtol=1e-12)
     _check_path(X, y, got, orc, lams)
     assert _np(a["learned"])[0] == 0
+
+
+def test_trained_network_against_plain_start(torch, orc):
+    """The committed trained network on a held-out c4-structured problem
+    (seed 20000, p = 4000, the first 30 lambdas of the c4 grid): both paths
+    certify every lambda; the network's start is taken only where its reduced
+    gap is smaller, and up to the first lambda where it is taken the two runs
+    are the same computation (identical epochs)."""
+    import os
+    wfile = os.path.join(os.path.dirname(gs.__file__), "warm_mlp.npy")
+    P = torch.from_numpy(np.load(wfile).astype(np.float32)).cuda()
+    assert P.numel() == gs.MLP_PARAMS
+    X, y = _c4_small(20000, p=4000, n=1000)
+    Xd, yd = _dev(torch, X, y)
+    rel = 1e-3 ** (np.arange(100) / 99)
+    plain = gs.lasso_path_learned(Xd, yd, None, lambdas=rel[:30], relative=True)
+    learned = gs.lasso_path_learned(Xd, yd, P, lambdas=rel[:30], relative=True)
+    lams = _np(plain["lambdas"])
+    _check_path(X, y, plain, orc, lams)
+    _check_path(X, y, learned, orc, lams)
+    flags = _np(learned["learned"])
+    ep_p, ep_l = _np(plain["epochs"]), _np(learned["epochs"])
+    first = int(np.argmax(flags)) if flags.any() else len(flags)
+    assert np.array_equal(ep_p[:first], ep_l[:first])
+    print(f"trained network: started {int(flags.sum())} of {len(flags) - 1} lambdas, "
+          f"epochs {int(ep_l.sum())} learned vs {int(ep_p.sum())} plain")

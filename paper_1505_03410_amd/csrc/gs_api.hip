@@ -433,7 +433,8 @@ size_t path_ws(const gs_problem* probs, int B) {
 struct Group {
   const NarrowEntry* e;
   int first, count;
-  int gs;  // LDS floats of the largest support Gram block in the group
+  int gs;       // LDS floats of the largest support Gram block in the group
+  double cost;  // sum of n p T over the group's problems
 };
 
 int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, size_t ws_bytes,
@@ -477,8 +478,9 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   for (int i = 0; i < B; ++i) {
     sorted[i] = descs[order[i]];
     const NarrowEntry* e = cfg[order[i]];
-    if (groups->empty() || groups->back().e != e) groups->push_back({e, i, 0, 0});
+    if (groups->empty() || groups->back().e != e) groups->push_back({e, i, 0, 0, 0.0});
     groups->back().count++;
+    groups->back().cost += cost(order[i]);
     groups->back().gs = std::max(groups->back().gs, gs_floats(sorted[i].ns));
   }
   if ((int)groups->size() > 63) return GS_EUNSUPPORTED;
@@ -495,6 +497,7 @@ struct Launch {
   int B;
   int* queue;
   PathOpts po;
+  double cost;
 };
 
 // LDS split and grid of every group; sets the kernels' LDS limits (not a
@@ -510,6 +513,7 @@ int configure_groups(const Shared& sh, const std::vector<Group>& groups, PathOpt
     L.B = G.count;
     L.queue = sh.queues + g;
     L.po = po;
+    L.cost = G.cost;
     // the support's Gram block first (when the CU's share holds it), then
     // the residual mode's staging region
     const size_t per_wave = device_lds_per_cu() /
@@ -526,15 +530,70 @@ int configure_groups(const Shared& sh, const std::vector<Group>& groups, PathOpt
   return GS_OK;
 }
 
-// Queue reset (a fill kernel, no memset node) and the group launches.
+// Side streams (default priority) and fork/join events of one device, made
+// once and kept for the process: the group launches of a batch spread over
+// the caller's stream and these, so that groups of different tile
+// configurations run side by side instead of one after another.
+constexpr int kSideStreams = 3;
+struct SidePool {
+  hipStream_t st[kSideStreams];
+  hipEvent_t fork, join[kSideStreams];
+};
+std::mutex g_side_mu;
+std::map<int, SidePool> g_side;
+
+int side_pool(SidePool** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  auto it = g_side.find(dev);
+  if (it == g_side.end()) {
+    SidePool p{};
+    for (int i = 0; i < kSideStreams; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&p.st[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming));
+    it = g_side.emplace(dev, p).first;
+  }
+  *out = &it->second;
+  return GS_OK;
+}
+
+// Queue reset (a fill kernel, no memset node) and the group launches.  With
+// several groups, the heaviest goes first onto the least loaded of the
+// caller's stream and the side streams, which fork from the caller's stream
+// after the reset and join it at the end (also under graph capture).
 int enqueue_groups(const Shared& sh, std::vector<Launch>& launches, hipStream_t s, bool timed) {
   HIPCHK(fill_i32(sh.queues, 0, 64, s));
-  for (Launch& L : launches) {
+  const int nl = (int)launches.size();
+  SidePool* sp = nullptr;
+  const int nside = nl > 1 ? std::min(nl - 1, kSideStreams) : 0;
+  if (nside > 0) {
+    int rc = side_pool(&sp);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(sp->fork, s));
+    for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(sp->st[i], sp->fork, 0));
+  }
+  std::vector<int> order(nl);
+  for (int i = 0; i < nl; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return launches[a].cost > launches[b].cost; });
+  std::vector<double> load(nside + 1, 0.0);
+  for (int i : order) {
+    Launch& L = launches[i];
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[k] += L.cost;
+    hipStream_t ls = k == 0 ? s : sp->st[k - 1];
     void* a[] = {&L.descs, &L.B, &L.queue, &L.po};
     if (timed)
-      HIPCHK(timed_launch(kTimePath, L.kernel, dim3(L.grid), dim3(64), a, L.lds, s));
+      HIPCHK(timed_launch(kTimePath, L.kernel, dim3(L.grid), dim3(64), a, L.lds, ls));
     else
-      HIPCHK(launch(L.kernel, dim3(L.grid), dim3(64), a, L.lds, s));
+      HIPCHK(launch(L.kernel, dim3(L.grid), dim3(64), a, L.lds, ls));
+  }
+  for (int i = 0; i < nside; ++i) {
+    HIPCHK(hipEventRecord(sp->join[i], sp->st[i]));
+    HIPCHK(hipStreamWaitEvent(s, sp->join[i], 0));
   }
   return GS_OK;
 }

@@ -399,3 +399,38 @@ def test_autotune_choices_and_results(torch, orc):
     for (X, y), o in zip(data, outs):
         _check_path(X, y, o, orc, _np(o["lambdas"]))
     gs.tune_reset()
+
+
+def test_batch_mixed_configs_concurrent_groups(torch, orc):
+    """A batch whose problems need different tile configurations (row counts
+    from 40 to 1000, FP32 and FP64): the groups run side by side on several
+    streams, eagerly and from a captured graph; every path certifies against
+    the oracle and the graph replays reproduce the eager results bit for
+    bit."""
+    shapes = [(40, 300, np.float32), (300, 800, np.float32), (1000, 600, np.float32),
+              (203, 500, np.float32), (50, 500, np.float64), (120, 2000, np.float32)]
+    probs, host = [], []
+    for i, (n, p, dt) in enumerate(shapes):
+        d = synth.gaussian(700 + i, n, p, k=10, sigma=0.3)
+        X, y = d["X"].astype(dt), d["y"].astype(dt)
+        Xd, yd = _dev(torch, X, y)
+        probs.append(dict(X=Xd, y=yd, T=8, lambda_min_ratio=0.05))
+        host.append((X, y))
+    eager = gs.lasso_solve_batch(probs)
+    torch.cuda.synchronize()
+    for (X, y), o in zip(host, eager):
+        _check_path(X, y, o, orc, _np(o["lambdas"]))
+    ref = [(_np(o["beta"]).copy(), _np(o["epochs"]).copy()) for o in eager]
+    plan = gs.BatchPlan(probs)
+    try:
+        for rep in range(2):
+            for o in plan.outputs:
+                o["beta"].fill_(3.0)
+            torch.cuda.synchronize()
+            outs = plan.run()
+            torch.cuda.synchronize()
+            for b, o in enumerate(outs):
+                np.testing.assert_array_equal(_np(o["beta"]), ref[b][0])
+                np.testing.assert_array_equal(_np(o["epochs"]), ref[b][1])
+    finally:
+        plan.close()

@@ -32,7 +32,10 @@ int fail_hip(hipError_t e, const char* where) {
   } while (0)
 
 constexpr int kMaxN = 2048;
-constexpr int kWideSweepBlocks = 2048;
+#ifndef GS_SWEEP_BLOCKS
+#define GS_SWEEP_BLOCKS 2048
+#endif
+constexpr int kWideSweepBlocks = GS_SWEEP_BLOCKS;
 constexpr int kWidePreBlocks = 1024;
 // n*p above which GS_SCHED_AUTO spreads one path over the whole GPU.
 constexpr double kWideThreshold = 16.0 * 1024 * 1024;

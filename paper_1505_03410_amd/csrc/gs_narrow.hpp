@@ -424,46 +424,53 @@ struct Narrow {
     wave_lds_order();
   }
 
-  // One step of the 3-deep load ring: chunk at `base` sits in st[CUR]; the
-  // loads of chunk base+2C go into st[(CUR+2)%3] with the index fetched one
-  // step earlier, and the index of chunk base+3C is requested.
+  // Depth of the load ring: with one column per chunk (S = 64) a chunk's
+  // work is short against the latency of its column, so more columns are in
+  // flight where a stage is small enough (up to 64 bytes per lane) to stay
+  // in registers.
+  static constexpr int RING = (C == 1 && RPL * sizeof(XT) <= 64) ? 6 : 3;
+
+  // Steps CUR.. of one round of the RING-deep load ring.  The chunk at
+  // P = base + CUR C sits in st[CUR]; the loads of chunk P + (RING-1) C go
+  // into the stage freed last round, with the index fetched one step
+  // earlier, and the index of chunk P + RING C is requested.
   template <int CUR, bool POSL>
-  static __device__ __forceinline__ void ring_step(const Ctx& x, int base, int q, bool full,
-                                                   double lambda, double* pb,
-                                                   const double* pinv, Stage (&st)[3],
-                                                   int (&ix)[3], double (&r)[RPL]) {
-    constexpr int NXT = (CUR + 2) % 3;
-    fetch_j<POSL>(x, base + 2 * C + x.slot, ix[NXT], q, pb, pinv, st[NXT]);
-    ix[CUR] = act_at(x, base + 3 * C + x.slot, q, full);
-    resolve<POSL>(x, st[CUR], lambda, pb, r);
+  static __device__ __forceinline__ bool ring_steps(const Ctx& x, int base, int q, bool full,
+                                                    double lambda, double* pb,
+                                                    const double* pinv, Stage (&st)[RING],
+                                                    int (&ix)[RING], double (&r)[RPL]) {
+    if constexpr (CUR < RING) {
+      constexpr int NXT = (CUR + RING - 1) % RING;
+      const int P = base + CUR * C;
+      fetch_j<POSL>(x, P + (RING - 1) * C + x.slot, ix[NXT], q, pb, pinv, st[NXT]);
+      ix[CUR] = act_at(x, P + RING * C + x.slot, q, full);
+      resolve<POSL>(x, st[CUR], lambda, pb, r);
+      if (P + C >= q) return true;
+      return ring_steps<CUR + 1, POSL>(x, base, q, full, lambda, pb, pinv, st, ix, r);
+    } else {
+      return false;
+    }
   }
 
   // One cyclic CD epoch over A (Algorithm 1):
   //   beta_j <- ST(lambda/||x_j||^2, beta_j + x_j^T rho / ||x_j||^2),
   //   rho    <- rho - (beta_j' - beta_j) x_j.
   // The epoch may start at position k0 > 0: positions before k0 are left
-  // alone.
+  // alone.  Positions past the end are clamped to the last one (q >= 1).
   template <bool POSL>
   static __device__ __forceinline__ void cd_epoch(const Ctx& x, int q, bool full, double lambda, double* pb,
                                   const double* pinv, double (&r)[RPL], int k0) {
     if (q <= k0) return;
     const int b0 = k0 - k0 % C;
-    Stage st[3];
-    int ix[3];
-    ix[0] = act_at(x, b0 + x.slot, q, full);
-    ix[1] = act_at(x, b0 + C + x.slot, q, full);
-    ix[2] = act_at(x, b0 + 2 * C + x.slot, q, full);
-    fetch_j<POSL>(x, b0 + x.slot, ix[0], q, pb, pinv, st[0]);
+    Stage st[RING];
+    int ix[RING];
+#pragma unroll
+    for (int i = 0; i < RING; ++i) ix[i] = act_at(x, b0 + i * C + x.slot, q, full);
+#pragma unroll
+    for (int i = 0; i + 1 < RING; ++i) fetch_j<POSL>(x, b0 + i * C + x.slot, ix[i], q, pb, pinv, st[i]);
     st[0].v = st[0].v && b0 + x.slot >= k0;
-    fetch_j<POSL>(x, b0 + C + x.slot, ix[1], q, pb, pinv, st[1]);
-    for (int base = b0;; base += 3 * C) {
-      ring_step<0, POSL>(x, base, q, full, lambda, pb, pinv, st, ix, r);
-      if (base + C >= q) break;
-      ring_step<1, POSL>(x, base + C, q, full, lambda, pb, pinv, st, ix, r);
-      if (base + 2 * C >= q) break;
-      ring_step<2, POSL>(x, base + 2 * C, q, full, lambda, pb, pinv, st, ix, r);
-      if (base + 3 * C >= q) break;
-    }
+    for (int base = b0;; base += RING * C)
+      if (ring_steps<0, POSL>(x, base, q, full, lambda, pb, pinv, st, ix, r)) break;
   }
 
   // ne residual-mode epochs (the first one from position k0), the residual

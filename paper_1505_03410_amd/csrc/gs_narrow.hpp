@@ -92,6 +92,7 @@ struct Narrow {
     gbl<double>* beta;
     gbl<double>* c;             // correlations by position (one of two buffers)
     gbl<int32_t>* act;
+    const cst<int32_t>* act_c;  // act, read-only view (kernels that never write A)
   };
 
   // Pattern-mode state.  Scalars are wavefront-uniform; sp..u hold the
@@ -430,23 +431,43 @@ struct Narrow {
   // in registers.
   static constexpr int RING = (C == 1 && RPL * sizeof(XT) <= 64) ? 6 : 3;
 
+  // The column index at position k of A for the load ring.  With CA (A is
+  // not written while the kernel runs) and one column per chunk the
+  // position is wave-uniform and the index comes by a scalar load: a vector
+  // load of it would be counted in order with the column loads in flight,
+  // and waiting for it would wait for all of them.
+  // With POSL the indices were staged in LDS (pa) with the coefficients.
+  template <bool POSL, bool CA>
+  static __device__ __forceinline__ int ring_ix(const Ctx& x, int k, int q, bool full,
+                                                const int* pa) {
+    if constexpr (POSL) {
+      return pa[k < q ? k : q - 1];
+    } else if constexpr (CA && C == 1) {
+      const int kk = __builtin_amdgcn_readfirstlane(k < q ? k : q - 1);
+      return full ? kk : x.act_c[kk];
+    } else {
+      return act_at(x, k, q, full);
+    }
+  }
+
   // Steps CUR.. of one round of the RING-deep load ring.  The chunk at
   // P = base + CUR C sits in st[CUR]; the loads of chunk P + (RING-1) C go
   // into the stage freed last round, with the index fetched one step
   // earlier, and the index of chunk P + RING C is requested.
-  template <int CUR, bool POSL>
+  template <int CUR, bool POSL, bool CA>
   static __device__ __forceinline__ bool ring_steps(const Ctx& x, int base, int q, bool full,
                                                     double lambda, double* pb,
-                                                    const double* pinv, Stage (&st)[RING],
-                                                    int (&ix)[RING], double (&r)[RPL]) {
+                                                    const double* pinv, const int* pa,
+                                                    Stage (&st)[RING], int (&ix)[RING],
+                                                    double (&r)[RPL]) {
     if constexpr (CUR < RING) {
       constexpr int NXT = (CUR + RING - 1) % RING;
       const int P = base + CUR * C;
       fetch_j<POSL>(x, P + (RING - 1) * C + x.slot, ix[NXT], q, pb, pinv, st[NXT]);
-      ix[CUR] = act_at(x, P + RING * C + x.slot, q, full);
+      ix[CUR] = ring_ix<POSL, CA>(x, P + RING * C + x.slot, q, full, pa);
       resolve<POSL>(x, st[CUR], lambda, pb, r);
       if (P + C >= q) return true;
-      return ring_steps<CUR + 1, POSL>(x, base, q, full, lambda, pb, pinv, st, ix, r);
+      return ring_steps<CUR + 1, POSL, CA>(x, base, q, full, lambda, pb, pinv, pa, st, ix, r);
     } else {
       return false;
     }
@@ -457,45 +478,50 @@ struct Narrow {
   //   rho    <- rho - (beta_j' - beta_j) x_j.
   // The epoch may start at position k0 > 0: positions before k0 are left
   // alone.  Positions past the end are clamped to the last one (q >= 1).
-  template <bool POSL>
+  template <bool POSL, bool CA>
   static __device__ __forceinline__ void cd_epoch(const Ctx& x, int q, bool full, double lambda, double* pb,
-                                  const double* pinv, double (&r)[RPL], int k0) {
+                                  const double* pinv, const int* pa, double (&r)[RPL], int k0) {
     if (q <= k0) return;
     const int b0 = k0 - k0 % C;
     Stage st[RING];
     int ix[RING];
 #pragma unroll
-    for (int i = 0; i < RING; ++i) ix[i] = act_at(x, b0 + i * C + x.slot, q, full);
+    for (int i = 0; i < RING; ++i) ix[i] = ring_ix<POSL, CA>(x, b0 + i * C + x.slot, q, full, pa);
 #pragma unroll
     for (int i = 0; i + 1 < RING; ++i) fetch_j<POSL>(x, b0 + i * C + x.slot, ix[i], q, pb, pinv, st[i]);
     st[0].v = st[0].v && b0 + x.slot >= k0;
     for (int base = b0;; base += RING * C)
-      if (ring_steps<0, POSL>(x, base, q, full, lambda, pb, pinv, st, ix, r)) break;
+      if (ring_steps<0, POSL, CA>(x, base, q, full, lambda, pb, pinv, pa, st, ix, r)) break;
   }
 
   // ne residual-mode epochs (the first one from position k0), the residual
-  // taken from and returned to LDS.  With room for 16 q bytes in the staging
-  // region, beta and 1/||x||^2 of the active positions are staged in LDS
-  // for the interval.
+  // taken from and returned to LDS.  With room for 20 q bytes in the staging
+  // region, the column index, beta and 1/||x||^2 of the active positions are
+  // staged in LDS for the interval.
+  template <bool CA = false>
   static __device__ __forceinline__ void cd_epochs(const Ctx& x, int q, bool full, double lambda,
                                    int ne, int k0) {
     double r[RPL];
     load_rows(x, x.rho_l, r);
-    const bool posl = q > 0 && (size_t)q * 2 * sizeof(double) <= (size_t)x.stg_cap * sizeof(float);
+    const bool posl = q > 0 && (size_t)q * (2 * sizeof(double) + sizeof(int)) <=
+                                   (size_t)x.stg_cap * sizeof(float);
     if (posl) {
       double* pb = reinterpret_cast<double*>(x.stg);
       double* pinv = pb + q;
+      int* pa = reinterpret_cast<int*>(pinv + q);
       for (int k = x.lane; k < q; k += 64) {
         const int j = full ? k : x.act[k];
+        pa[k] = j;
         pb[k] = x.beta[j];
         pinv[k] = x.inv[j];
       }
       wave_lds_order();
-      for (int e = 0; e < ne; ++e) cd_epoch<true>(x, q, full, lambda, pb, pinv, r, e == 0 ? k0 : 0);
-      for (int k = x.lane; k < q; k += 64) x.beta[full ? k : x.act[k]] = pb[k];
+      for (int e = 0; e < ne; ++e)
+        cd_epoch<true, CA>(x, q, full, lambda, pb, pinv, pa, r, e == 0 ? k0 : 0);
+      for (int k = x.lane; k < q; k += 64) x.beta[pa[k]] = pb[k];
     } else {
       for (int e = 0; e < ne; ++e)
-        cd_epoch<false>(x, q, full, lambda, nullptr, nullptr, r, e == 0 ? k0 : 0);
+        cd_epoch<false, CA>(x, q, full, lambda, nullptr, nullptr, nullptr, r, e == 0 ? k0 : 0);
     }
     __threadfence_block();
 #pragma unroll
@@ -1441,6 +1467,7 @@ __global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathO
   x.beta = gptr(d.beta);
   x.c = gptr(d.c);
   x.act = gptr(d.act) + (int64_t)st->cur * d.p;
+  x.act_c = (const cst<int32_t>*)x.act;  // the compaction kernels wrote A; this one only reads it
   N::setup(x, gptr(d.rows));
   for (int i = lane; i < d.n; i += 64) x.rho_l[i] = gptr(d.rho)[i];
   wave_lds_order();
@@ -1449,7 +1476,7 @@ __global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathO
   const int k0 = st->k;
   const int ne = min(opts.f, opts.K - k0);
   const double lambda = gptr(d.lam)[st->t];
-  N::cd_epochs(x, q, full, lambda, ne, 0);
+  N::template cd_epochs<true>(x, q, full, lambda, ne, 0);
   if (lane == 0) {
     st->k = k0 + ne;
     st->phase = 0;

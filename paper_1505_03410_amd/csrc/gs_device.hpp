@@ -22,11 +22,6 @@ template <typename T>
 __device__ __forceinline__ gbl<T>* gptr(T* p) {
   return (gbl<T>*)p;
 }
-// The constant address space: a wave-uniform load through such a pointer is
-// a scalar load, whose completion is counted apart from the vector loads.
-// Only for data that no wave writes while the kernel runs.
-template <typename T>
-using cst = __attribute__((address_space(4))) T;
 
 // Higham's gamma_m = m u / (1 - m u): relative error bound of an m-term sum
 // or dot product in FP64.

@@ -50,6 +50,12 @@
 
 namespace gs {
 
+// The constant address space: a wave-uniform load through such a pointer is
+// a scalar load, whose completion is counted apart from the vector loads.
+// Only for data that no wave writes while the kernel runs.
+template <typename T>
+using cst = __attribute__((address_space(4))) T;
+
 __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -378,12 +384,13 @@ struct Narrow {
                                                  double* pb, double (&r)[RPL]) {
     // Rows >= n hold copies of row 0: they meet zeros of the residual in the
     // dot products, and are zeroed in the tile that updates the residual.
+    // With one column per chunk the lane's own registers are that tile.
     XT* mytile = x.tile + x.lane * RPL;
     double xd[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       xd[i] = (double)s.x[i];
-      mytile[i] = ((x.mk >> i) & 1ull) ? s.x[i] : XT(0);
+      if constexpr (C > 1) mytile[i] = ((x.mk >> i) & 1ull) ? s.x[i] : XT(0);
     }
     double b = s.b;
     const double inv = s.inv;
@@ -409,9 +416,16 @@ struct Narrow {
         b = bn;
         changed = true;
       }
-      const XT* tx = x.tile + (cs * S + x.seg) * RPL;
+      if constexpr (C == 1) {
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) r[i] = fma(-delta, (double)tx[i], r[i]);
+        for (int i = 0; i < RPL; ++i)
+          r[i] = fma(-delta, ((x.mk >> i) & 1ull) ? xd[i] : 0.0, r[i]);
+        break;
+      } else {
+        const XT* tx = x.tile + (cs * S + x.seg) * RPL;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) r[i] = fma(-delta, (double)tx[i], r[i]);
+      }
       if (cs + 1 >= C) break;
       d = dotd(xd, r);
       start = cs + 1;

@@ -385,3 +385,21 @@ def test_trained_network_against_plain_start(torch, orc):
     assert np.array_equal(ep_p[:first], ep_l[:first])
     print(f"trained network: started {int(flags.sum())} of {len(flags) - 1} lambdas, "
           f"epochs {int(ep_l.sum())} learned vs {int(ep_p.sum())} plain")
+
+
+def test_zero_response_paths(torch):
+    """y = 0: lambda_max = 0, the solution is beta = 0 at once (gap 0); the
+    plain path and the learned driver (which then defers to the plain path)
+    both return zeros, certified, with zero epochs."""
+    d = synth.gaussian(31, 40, 300)
+    X = d["X"].astype(np.float32)
+    y = np.zeros(40, dtype=np.float32)
+    Xd, yd = _dev(torch, X, y)
+    P = gs.mlp_params_to_flat(_random_params(np.random.default_rng(32)))
+    for got in (gs.lasso_path(Xd, yd, T=5, lambda_min_ratio=0.1),
+                gs.lasso_path_learned(Xd, yd, P, T=5, lambda_min_ratio=0.1)):
+        torch.cuda.synchronize()
+        assert np.all(_np(got["beta"]) == 0)
+        assert np.all(_np(got["status"]) == 0)
+        assert np.all(_np(got["gap"]) == 0)
+        assert np.all(_np(got["epochs"]) == 0)

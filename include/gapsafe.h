@@ -21,11 +21,11 @@
  *   ldx*sizeof(dtype) is a multiple of 16 and n is a multiple of
  *   16/sizeof(dtype); otherwise scalar loads.  No entry beyond row n-1 of a
  *   column is read.
- * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  The
- *   per-problem ("narrow") schedule is stream-ordered and asynchronous:
- *   outputs are valid once the caller synchronizes the stream.  The wide
- *   schedule (one problem spread over the whole GPU) drives its passes from
- *   the host and returns when the path is finished.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   lasso_path returns when the path is finished on `stream` (it reads the
+ *   per-lambda status back); lasso_solve_batch, lasso_batch_run and screen
+ *   are stream-ordered and asynchronous: their outputs are valid once the
+ *   caller synchronizes the stream.
  * - The library never allocates device memory: every scratch array lives in
  *   the caller's workspace (size from the *_workspace_size queries, any
  *   256-byte-aligned device buffer).  Workspace contents need no
@@ -34,9 +34,11 @@
  *   launched.  Return codes:
  *     GS_OK             0   every lambda certified (gap <= eps)
  *     GS_NOT_CONVERGED  1   soft: at least one lambda hit max_epochs; its
- *                           outputs hold the last iterate and its gap.  Only
- *                           reported by the synchronous wide schedule; the
- *                           asynchronous schedule reports it in status_out.
+ *                           outputs hold the last iterate and its gap.
+ *                           Returned by the calls that wait for their result
+ *                           (lasso_path, lasso_path_learned); the
+ *                           asynchronous batch calls report it per lambda in
+ *                           status_out only.
  *     GS_EINVAL        -1   bad size, pointer, lambda, eps, f or dtype
  *     GS_EHIP          -2   HIP runtime error (text: lasso_strerror)
  *     GS_EWORKSPACE    -3   workspace NULL or smaller than required
@@ -175,7 +177,8 @@ size_t lasso_workspace_size(const gs_problem* probs, int32_t B,
  * from beta^{lambda_{t-1}}, screen every f epochs with the GAP SAFE sphere
  * (Sec. 3.2: theta = alpha rho from the residual rescaling of Sec. 2.3,
  * radius sqrt(2 gap)/lambda inflated by a rounding bound) and run cyclic CD
- * on the surviving coordinates until the gap is <= eps. */
+ * on the surviving coordinates until the gap is <= eps.  Returns when the
+ * path is finished (GS_NOT_CONVERGED if a lambda reached max_epochs). */
 int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace,
                size_t ws_bytes, void* stream);
 

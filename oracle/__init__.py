@@ -9,9 +9,8 @@ Two parts:
   Fercoq, Gramfort & Salmon (ICML 2015) in plain FP64 loops, one screening pass,
   the plain primal/dual gap.  Loaded through ctypes.
 * numpy FP64 code for the learned warm start: the 4-64-64-2 MLP forward and
-  backward pass with Adam, per-feature inputs and block-maximum correlation,
-  and the stability-selection counts.  These follow textbook definitions; the
-  paper does not cover them.
+  backward pass with Adam, per-feature inputs and block-maximum correlation.
+  These follow textbook definitions; the paper does not cover them.
 """
 from __future__ import annotations
 
@@ -129,7 +128,7 @@ class Oracle:
         c = np.empty(max(q, 1))
         ke = np.zeros(max(q, 1), dtype=np.uint8)
         ks = np.zeros(max(q, 1), dtype=np.uint8)
-        sc = np.empty(8)
+        sc = np.empty(10)
         rc = self.lib.orc_screen(n, p, n, _ptr(Xf), _ptr(y), _ptr(beta), lam,
                                  _ptr(act, _ip), q, _ptr(c), _ptr(ke, _bp),
                                  _ptr(ks, _bp), _ptr(sc))
@@ -139,7 +138,7 @@ class Oracle:
         return dict(c=c[:q], active=idx, keep_exact=ke[:q].astype(bool),
                     keep_safe=ks[:q].astype(bool), gap=sc[0], alpha=sc[1],
                     radius=sc[2], radius_inflated=sc[3], M=sc[4], rho_norm2=sc[5],
-                    y_rho=sc[6], l1=sc[7])
+                    y_rho=sc[6], l1=sc[7], alpha_safe=sc[8], err_gap=sc[9])
 
     def lasso_path(self, X, y, T=100, lambdas=None, relative=False, delta=3.0,
                    eps_rel=1e-8, f=10, K=100000, beta_init=None,
@@ -300,7 +299,3 @@ def warm_features(c, lam, lam_max, beta_prev, nrm, ynorm, bmc):
                      beta_prev * nrm / ynorm,
                      bmc], axis=1)
 
-
-def selection_counts(betas):
-    """Stability selection: betas (B, T, p) -> counts (T, p) of nonzeros."""
-    return (np.asarray(betas) != 0).sum(axis=0).astype(np.int32)

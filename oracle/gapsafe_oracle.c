@@ -144,6 +144,8 @@ typedef struct {
   double rho_norm2;  /* ||rho||^2                                           */
   double y_rho;      /* y^T rho                                             */
   double l1;         /* ||beta||_1                                          */
+  double alpha_s;    /* alpha of the rounding-safe dual point (R11)         */
+  double err_gap;    /* the rounding bound added to the gap (R11)           */
 } orc_pass_info;
 
 /* Residual rho = y - X beta, recomputed from scratch (Sec. 2.3). */
@@ -225,11 +227,15 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
              0.5 * lambda * lambda * alpha * alpha * R2;
   double Gs = 0.5 * R2 + lambda * l1 - lambda * alpha_s * Ry +
               0.5 * lambda * lambda * alpha_s * alpha_s * R2;
-  double yn = sqrt(col_dot(n, y, y));
+  double yn = sqrt(col_dot(n, y, y)) * (1.0 + gamma_m(n + 2));
   double d_rho = gamma_m(nnz + 1) * (yn + sum_bx * (1.0 + gamma_m(n + 2)));
+  /* The computed y^T rho carries an error of up to gamma_n ||y|| ||rho|| (a
+   * dot product whose terms have both signs: its error is not relative to
+   * its value); it enters G through lambda alpha y^T rho. */
   double errG = gamma_m(n + 6) * (0.5 * R2 + lambda * l1 +
                                   lambda * fabs(alpha_s * Ry) +
                                   0.5 * lambda * lambda * alpha_s * alpha_s * R2) +
+                lambda * fabs(alpha_s) * gamma_m(n) * yn * rnorm +
                 rnorm * d_rho + 0.5 * d_rho * d_rho;
   double Gp = (Gs > 0.0 ? Gs : 0.0) + errG;
   double radius = sqrt(2.0 * (G > 0.0 ? G : 0.0)) / lambda;
@@ -253,6 +259,8 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
   info->rho_norm2 = R2;
   info->y_rho = Ry;
   info->l1 = l1;
+  info->alpha_s = alpha_s;
+  info->err_gap = errG;
 }
 
 /* Public single pass: the boundary's screen() call done plainly.
@@ -261,7 +269,7 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
 int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
                const double* beta, double lambda, const int32_t* active_in,
                int q_in, double* c_out, uint8_t* keep_exact,
-               uint8_t* keep_safe, double* scalars /* 8: see orc_pass_info */) {
+               uint8_t* keep_safe, double* scalars /* 10: see orc_pass_info */) {
   if (n <= 0 || p <= 0 || ldx < n || !(lambda > 0.0)) return ORC_EINVAL;
   int q = active_in ? q_in : p;
   int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)(q > 0 ? q : 1));
@@ -290,6 +298,8 @@ int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
   scalars[5] = info.rho_norm2;
   scalars[6] = info.y_rho;
   scalars[7] = info.l1;
+  scalars[8] = info.alpha_s;
+  scalars[9] = info.err_gap;
   free(A); free(rho); free(nrm2);
   return q;
 }

@@ -671,7 +671,17 @@ int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace, siz
   std::vector<Group> groups;
   rc = prepare_batch(prob, 1, opts, workspace, ws_bytes, s, &sh, &groups);
   if (rc) return rc;
-  return launch_groups(sh, groups, path_opts(opts, false), s);
+  rc = launch_groups(sh, groups, path_opts(opts, false), s);
+  if (rc) return rc;
+  // the path is done when its status words are on the host: a lambda that
+  // reached max_epochs makes the call report GS_NOT_CONVERGED
+  std::vector<int32_t> st(prob->T);
+  HIPCHK(hipMemcpyAsync(st.data(), prob->status_out, sizeof(int32_t) * prob->T,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int32_t v : st)
+    if (v == GS_STATUS_NOT_CONVERGED) return GS_NOT_CONVERGED;
+  return GS_OK;
 }
 
 int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, void* workspace,

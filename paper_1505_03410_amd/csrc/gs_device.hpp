@@ -244,7 +244,10 @@ struct ColLayout {
 //   alpha = clip(Ry / (lambda R2), -1/M+, 1/M+)           (Sec. 2.3)
 //   G     = 1/2 R2 + lambda l1 - lambda alpha Ry + 1/2 lambda^2 alpha^2 R2
 //         = P(beta) - D(theta) with the 1/2||y||^2 terms cancelled analytically
-//   errG  bounds the rounding in G plus the gap between rho~ and y - X beta
+//   errG  bounds the rounding in G plus the gap between rho~ and y - X beta;
+//         the computed Ry may be off by gamma_n ||y|| ||rho~|| whatever its
+//         own size (its terms have both signs), which enters G through
+//         lambda |alpha| Ry
 //   r+    = sqrt(2 (max(G,0) + errG)) / lambda (1 + 4u)   (Proposition 1)
 // The sphere test then keeps j iff
 //   |alpha c^_j| + |alpha| e_c ||x_j||+ + r+ ||x_j||+ >= 1 - 4u    (Sec. 2.1)
@@ -270,7 +273,9 @@ __device__ __forceinline__ GapInfo gap_safe(double R2, double Ry, double l1, dou
                t4 = 0.5 * lambda * lambda * a * a * R2;
   g.gap = t1 + t2 - t3 + t4;
   const double drho = gam(nnz + 1) * (ynorm + sbx * up);
-  const double errG = gam(n + 6) * (t1 + t2 + fabs(t3) + t4) + rnorm * drho + 0.5 * drho * drho;
+  const double errG = gam(n + 6) * (t1 + t2 + fabs(t3) + t4) +
+                      lambda * fabs(a) * gam(n) * (ynorm * up) * rnorm + rnorm * drho +
+                      0.5 * drho * drho;
   g.radius = sqrt(2.0 * (fmax(g.gap, 0.0) + errG)) / lambda * (1.0 + 4.0 * kU);
   return g;
 }

@@ -55,6 +55,10 @@ def _screen_case(torch, orc, X, y, beta, lam, active=None, ld_multiple=4):
     scale = 0.5 * o["rho_norm2"] + lam * o["l1"] + 1e-300
     assert abs(float(_np(g["gap"])[0]) - o["gap"]) <= 1e-10 * scale
     assert abs(float(_np(g["alpha"])[0]) - o["alpha"]) <= 1e-12 * abs(o["alpha"]) + 1e-300
+    # the inflated radius the test uses: same rounding bound, computed apart
+    r_dev = float(_np(g["radius"])[0])
+    assert abs(r_dev - o["radius_inflated"]) <= 1e-9 * o["radius_inflated"] + 1e-300, \
+        (r_dev, o["radius_inflated"])
     # c_j = x_j^T rho in FP64
     xn = np.linalg.norm(_f64(X)[:, o["active"]], axis=0)
     err = np.abs(_np(g["c"]) - o["c"])
@@ -109,6 +113,25 @@ def test_screen_ragged_and_small(torch, orc):
     assert int(_np(g["q"])[0]) == 0
 
 
+def test_screen_radius_covers_cancelling_y_rho(torch, orc):
+    """The device's inflated radius contains the exact gap sphere of the dual
+    point it returns (theta = alpha (y - X beta)) on a design where y^T rho
+    cancels catastrophically, so the computed y^T rho is far from the exact
+    one (Proposition 1 with the rounding bound)."""
+    from fractions import Fraction as F
+    import test_oracle_pins as pins
+    x, y, rho = pins.cancelling_y_rho_case()
+    X = x[:, None]
+    lam = 1e-6
+    Xd, yd = _dev(torch, X, y, 2)
+    g = gs.screen(Xd, yd, torch.ones(1, dtype=torch.float64, device="cuda"), lam)
+    torch.cuda.synchronize()
+    alpha = float(_np(g["alpha"])[0])
+    r = float(_np(g["radius"])[0])
+    Gex = pins.exact_gap(y, rho, 1.0, lam, alpha)
+    assert Gex <= F(0.5 * (lam * r) ** 2), (float(Gex), 0.5 * (lam * r) ** 2)
+
+
 @pytest.mark.parametrize("full", [True])
 def test_screen_c4_full_size_sampled(torch, orc, full):
     """The 1000 x 100000 (400 MB) sweep in the launch configuration the
@@ -147,11 +170,22 @@ def _primal(Xf, yf, b, lam):
     return 0.5 * r @ r + lam * np.abs(b).sum()
 
 
-def _check_path(X, y, got, orc, lambdas, eps_rel=1e-8, tight=None, beta_tol=None):
-    """Check each returned beta against a tight oracle solution beta*:
-    the reported gap bounds the suboptimality, P(beta) - P(beta*) <= G + G*,
-    and ||X(beta - beta*)|| <= sqrt(2G) + sqrt(2G*) (Sec. 3.2 weak duality and
-    the strong convexity of the quadratic in X beta)."""
+BETA_TOL = 1e-5  # relative l2 distance to the tight oracle solution
+
+
+def _check_path(X, y, got, orc, lambdas, eps_rel=1e-8, tight=None, beta_tol=BETA_TOL,
+                label="path"):
+    """Check each returned beta against a tight oracle solution beta*
+    (gap <= 1e-13 ||y||^2):
+      * the reported gap bounds the suboptimality, P(beta) - P(beta*) <= G + G*,
+        and ||X(beta - beta*)|| <= sqrt(2G) + sqrt(2G*) (Sec. 3.2 weak duality
+        and the strong convexity of the quadratic in X beta);
+      * ||beta - beta*|| / ||beta*|| <= beta_tol, or, where the design does not
+        determine beta that closely from a gap of eps, within the bound those
+        two facts give: beta - beta* lives on U = supp(beta) u supp(beta*), so
+        ||beta - beta*|| <= (sqrt(2G) + sqrt(2G*)) / sigma_min(X_U).
+    Returns the worst relative error and the lambdas that needed the bound
+    (t, relative error, bound, sigma_min)."""
     Xf, yf = _f64(X), _f64(y)
     yy = float(yf @ yf)
     eps = eps_rel * yy
@@ -162,21 +196,31 @@ def _check_path(X, y, got, orc, lambdas, eps_rel=1e-8, tight=None, beta_tol=None
     assert np.all(gap <= eps)
     if tight is None:
         tight = orc.lasso_path(Xf, yf, lambdas=lambdas, eps_rel=1e-13)
-    worst = 0.0
+    worst, h4 = 0.0, []
     for t, lam in enumerate(lambdas):
         Gs = max(tight["gap"][t], 0.0)
         sub = _primal(Xf, yf, B[t], lam) - _primal(Xf, yf, tight["beta"][t], lam)
         assert sub <= gap[t] + Gs + 1e-12 * yy, (t, sub, gap[t])
         d = Xf @ (B[t] - tight["beta"][t])
-        assert np.linalg.norm(d) <= np.sqrt(2 * max(gap[t], 0)) + np.sqrt(2 * Gs) + 1e-9 * np.sqrt(yy)
+        xbound = np.sqrt(2 * max(gap[t], 0)) + np.sqrt(2 * Gs)
+        assert np.linalg.norm(d) <= xbound + 1e-9 * np.sqrt(yy)
         nb = np.linalg.norm(tight["beta"][t])
-        if nb > 0:
-            worst = max(worst, np.linalg.norm(B[t] - tight["beta"][t]) / nb)
-        else:
+        if nb == 0:
             assert np.all(B[t] == 0)
-    if beta_tol is not None:
-        assert worst <= beta_tol, worst
-    return worst
+            continue
+        rel = np.linalg.norm(B[t] - tight["beta"][t]) / nb
+        worst = max(worst, rel)
+        if beta_tol is not None and rel > beta_tol:
+            U = np.flatnonzero((B[t] != 0) | (tight["beta"][t] != 0))
+            smin = np.linalg.svd(Xf[:, U], compute_uv=False).min() if len(U) <= Xf.shape[0] else 0.0
+            bound = (xbound + 1e-9 * np.sqrt(yy)) / smin / nb if smin > 0 else np.inf
+            assert rel <= bound, (label, t, rel, bound, smin)
+            h4.append((t, rel, bound, smin))
+    if h4:
+        print(f"{label}: {len(h4)} of {len(lambdas)} lambdas beyond {beta_tol:g} relative, each "
+              f"within its sigma_min bound: " +
+              ", ".join(f"t={t} rel={r:.1e} bound={b:.1e} smin={s:.1e}" for t, r, b, s in h4[:8]))
+    return worst, h4
 
 
 @pytest.mark.parametrize("cd_mode", ["auto", "residual"])
@@ -201,11 +245,26 @@ def test_path_c1_full(torch, orc, cd_mode):
     Xd, yd = _dev(torch, X, y)
     got = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3, cd_mode=cd_mode)
     torch.cuda.synchronize()
+    assert got["rc"] == gs.GS_OK
     lams = _np(got["lambdas"])
     ref = orc.grid(orc.precompute(X, y)["lambda_max"], 100, 3.0)
     np.testing.assert_allclose(lams, ref, rtol=1e-13)
-    worst = _check_path(X, y, got, orc, lams)
-    print(f"c1 path: worst relative beta error vs tight oracle {worst:.2e}, "
+    worst, h4 = _check_path(X, y, got, orc, lams, label=f"c1[{cd_mode}]")
+    # the integer trace of Algorithm 1: epochs run and the final safe active
+    # set size at every lambda equal the oracle's (same readings, same eps)
+    o = orc.lasso_path(X, y, T=100, delta=3.0)
+    np.testing.assert_array_equal(_np(got["epochs"]), o["epochs"])
+    np.testing.assert_array_equal(_np(got["nactive"]), o["nactive"])
+    # and the same iterates: beta within 1e-5 relative l2 of the oracle's at
+    # the same certified gap (gap <= 1e-8 ||y||^2), at every lambda
+    B = _np(got["beta"])
+    same = [np.linalg.norm(B[t] - o["beta"][t]) / max(np.linalg.norm(o["beta"][t]), 1e-300)
+            for t in range(1, 100)]
+    assert max(same) <= BETA_TOL, max(same)
+    print(f"c1 path [{cd_mode}]: worst relative beta difference to the oracle at the same "
+          f"gap target {max(same):.2e}")
+    print(f"c1 path [{cd_mode}]: worst relative beta error vs tight oracle {worst:.2e} "
+          f"({len(h4)} lambdas within the sigma_min bound instead of 1e-5), "
           f"epochs {int(_np(got['epochs']).sum())}")
 
 
@@ -230,6 +289,89 @@ def test_path_large_n_configs(torch, orc, cd_mode):
         got = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.01, cd_mode=cd_mode)
         torch.cuda.synchronize()
         _check_path(X, y, got, orc, _np(got["lambdas"]))
+
+
+@pytest.mark.parametrize("cd_mode", ["auto", "residual"])
+def test_path_n_above_1024(torch, orc, cd_mode):
+    """The layouts for 1024 < n <= 2048: 16-byte loads (n = 1500, 2000) and
+    scalar loads (n = 1203, 1999), p about 3000."""
+    for n, p in [(1500, 3000), (2000, 2800), (1203, 3100), (1999, 2900)]:
+        d = synth.gaussian(n * 3 + p, n, p, k=40, sigma=0.5)
+        X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+        Xd, yd = _dev(torch, X, y)
+        got = gs.lasso_path(Xd, yd, T=6, lambda_min_ratio=0.05, cd_mode=cd_mode,
+                            schedule="narrow")
+        torch.cuda.synchronize()
+        _check_path(X, y, got, orc, _np(got["lambdas"]), label=f"n={n} p={p}")
+
+
+def _c3_class(n):
+    """The narrow layout class the library picks for an FP32 problem of n rows
+    stored with ldx a multiple of 4: (16-byte loads?, smallest row capacity)."""
+    vec = n % 4 == 0
+    caps = ([32, 48, 64, 80, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048] if vec
+            else [32, 48, 64, 96, 128, 256, 512, 1024, 2048])
+    return vec, next(c for c in caps if c >= n)
+
+
+def test_batch_c3_every_layout_class(torch, orc):
+    """Problems drawn from the 512-problem uneven batch, two per layout class
+    present in it (19 classes: every row capacity from 64 to 2048 rows, with
+    16-byte and with scalar loads), solved together in one batch (groups of
+    different layouts side by side) and each checked against the oracle at
+    its full size."""
+    params = synth.c3_params()
+    classes = {}
+    for b, pr in enumerate(params):
+        classes.setdefault(_c3_class(pr["n"]), []).append(b)
+    assert len(classes) == 19
+    picks = []
+    for key in sorted(classes):
+        mem = sorted(classes[key], key=lambda b: params[b]["n"] * params[b]["p"] /
+                     params[b]["lambda_ratio"] ** 0.5)
+        picks += sorted({mem[0], mem[len(mem) // 3]})
+    probs, host = [], []
+    for b in picks:
+        d = synth.c3_problem(params[b])
+        Xd, yd = _dev(torch, d["X"], d["y"])
+        probs.append(dict(X=Xd, y=yd, lambdas=[d["lambda_ratio"]], relative=True))
+        host.append((b, d))
+    outs = gs.lasso_solve_batch(probs)
+    torch.cuda.synchronize()
+    for (b, d), o in zip(host, outs):
+        n, p = d["X"].shape
+        _check_path(d["X"], d["y"], o, orc, _np(o["lambdas"]), label=f"c3[{b}] {n}x{p}")
+
+
+def test_batch_c2_full(torch, orc):
+    """The whole stability-selection workload: 256 row subsamples (36 rows) of
+    the 72 x 7129 design, 100 lambdas each down to lambda_max / 100, replayed
+    from the captured graph.  Every path is certified; 8 of them are checked
+    against the tight oracle; the selection counts equal the nonzero counts
+    of the returned paths."""
+    d = synth.c2()
+    X, y, rows = d["X"], d["y"], d["rows"]
+    Xd, yd = _dev(torch, X, y)
+    T = 100
+    probs = [dict(X=Xd, y=yd, rows=torch.from_numpy(rows[b]).cuda(), T=T, lambda_min_ratio=1e-2)
+             for b in range(rows.shape[0])]
+    counts = torch.zeros((T, X.shape[1]), dtype=torch.int32, device="cuda")
+    plan = gs.BatchPlan(probs, select_counts=counts)
+    try:
+        outs = plan.run()
+        torch.cuda.synchronize()
+        yy = (y.astype(np.float64)[rows] ** 2).sum(axis=1)
+        sel = np.zeros((T, X.shape[1]), np.int64)
+        for b, o in enumerate(outs):
+            assert np.all(_np(o["status"]) == 0), b
+            assert np.all(_np(o["gap"]) <= 1e-8 * yy[b]), b
+            sel += (_np(o["beta"]) != 0)
+        np.testing.assert_array_equal(_np(counts), sel)
+        for b in np.random.default_rng(2).choice(rows.shape[0], 8, replace=False):
+            _check_path(X[rows[b]], y[rows[b]], outs[b], orc, _np(outs[b]["lambdas"]),
+                        label=f"c2[{b}]")
+    finally:
+        plan.close()
 
 
 def test_batch_row_subsamples(torch, orc):
@@ -286,8 +428,9 @@ def test_epoch_budget(torch, orc):
     Xd, yd = _dev(torch, X, y)
     lmax = orc.precompute(X, y)["lambda_max"]
     lam = 0.01 * lmax
-    got = gs.lasso_path(Xd, yd, lambdas=[lam], max_epochs=7)
+    got = gs.lasso_path(Xd, yd, lambdas=[lam], max_epochs=7, schedule="narrow")
     torch.cuda.synchronize()
+    assert got["rc"] == gs.GS_NOT_CONVERGED
     assert int(_np(got["status"])[0]) == 1 and int(_np(got["epochs"])[0]) == 7
     # the gap of the returned beta, recomputed by the oracle on the same
     # (full) active set: the first pass after the budget has not screened

@@ -38,6 +38,7 @@ MUTANTS = {
                         "double D = 0.5 * yy + 0.5 * lambda * lambda * d2;"),
     "lambda_max_not_abs": ("if (fabs(xty[j]) > lmax) lmax = fabs(xty[j]);",
                            "if (xty[j] > lmax) lmax = xty[j];"),
+    "gap_bound_drops_y_rho_error": ("                lambda * fabs(alpha_s) * gamma_m(n) * yn * rnorm +\n", ""),
     "screen_drops_zero_test": ("keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.0 - 4.0 * ORC_U) ? 1 : 0;",
                                "keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.5) ? 1 : 0;"),
 }
@@ -60,6 +61,7 @@ checks = [
   lambda: T.test_brute_force_tiny(orc, 20, 6, 2),
   lambda: T.test_kkt_at_tight_solution(orc, "c0"),
   lambda: T.test_safety_invariant(orc),
+  lambda: T.test_rounding_bound_covers_cancelling_y_rho(orc),
 ]
 failed = 0
 for c in checks:          # one failing pin is enough

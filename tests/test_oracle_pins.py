@@ -297,6 +297,63 @@ def test_inflated_test_is_superset(orc):
         assert s["radius"] <= s["radius_inflated"] <= s["radius"] * (1 + 1e-6) + 1e-9
 
 
+def cancelling_y_rho_case(n=1000):
+    """A one-column design whose residual rho = y - x (beta = 1, computed
+    exactly) makes y^T rho cancel catastrophically in ascending-row order:
+    a product of 2^20, n - 3 products of -2^-34 (each below half an ulp of
+    the running sum, so all are lost), -2^20, then v = 2^-19.  The computed
+    y^T rho is v; the exact value is v - (n - 3) 2^-34.  Returns (x, y, rho)
+    with every entry exactly representable and y - x == rho exactly."""
+    v = 2.0 ** -19
+    rho = np.full(n, -2.0 ** -34)
+    y = np.ones(n)
+    rho[0], y[0] = 2.0 ** -10, 2.0 ** 30
+    rho[n - 2], y[n - 2] = -2.0 ** -10, 2.0 ** 30
+    rho[n - 1], y[n - 1] = v, 1.0
+    x = y - rho
+    assert np.all(y - x == rho) and np.all(x + rho == y)
+    return x, y, rho
+
+
+def exact_gap(y, rho, beta_l1, lam, alpha):
+    """P(beta) - D(alpha rho) in exact rational arithmetic for a beta whose
+    exact residual is rho (Sec. 1.1: primal and dual objectives)."""
+    from fractions import Fraction as F
+    L, a = F(lam), F(alpha)
+    yF = [F(t) for t in y]
+    rF = [F(t) for t in rho]
+    P = sum(t * t for t in rF) / 2 + L * F(beta_l1)
+    D = sum(t * t for t in yF) / 2 - L * L / 2 * sum((a * r - t / L) ** 2 for r, t in zip(rF, yF))
+    return P - D
+
+
+def test_rounding_bound_covers_cancelling_y_rho(orc):
+    """The inflated radius must contain the true gap sphere at the dual point
+    the pass actually uses, theta = alpha_s rho~ (Proposition 1 applied to
+    the exact gap of that point).  y^T rho is a dot product whose terms have
+    both signs, so its rounding error is bounded by gamma_n ||y|| ||rho||,
+    not by a multiple of its own value: in this constructed case the exact
+    gap exceeds the computed one by lambda alpha (n - 3) 2^-34, which only
+    that term of the bound covers."""
+    from fractions import Fraction as F
+    x, y, rho = cancelling_y_rho_case()
+    n = len(y)
+    lam = 1e-6
+    s = orc.screen(x[:, None], y, np.array([1.0]), lam)
+    assert s["y_rho"] == 2.0 ** -19                      # the lost terms are gone
+    Gex = exact_gap(y, rho, 1.0, lam, s["alpha_safe"])
+    R2, Ry, al = s["rho_norm2"], s["y_rho"], s["alpha_safe"]
+    Gs = 0.5 * R2 + lam * 1.0 - lam * al * Ry + 0.5 * lam * lam * al * al * R2
+    # the computed gap misses lambda alpha times the lost part of y^T rho
+    miss = Gex - F(Gs)
+    assert abs(miss - F(lam) * F(al) * (n - 3) * F(2.0 ** -34)) <= F(1e-3) * miss
+    assert Gex <= F(max(Gs, 0.0) + s["err_gap"])          # covered by the bound
+    assert Gex <= F(0.5 * (lam * s["radius_inflated"]) ** 2)
+    # a bound charging only a relative error of the computed y^T rho (its
+    # other terms are below 1e-9 here) would not cover it
+    assert miss > F(1e-9)
+
+
 # ----------------------------------------------------------------- the grid
 
 def test_grid(orc):

@@ -43,6 +43,8 @@
  *     GS_EHIP          -2   HIP runtime error (text: lasso_strerror)
  *     GS_EWORKSPACE    -3   workspace NULL or smaller than required
  *     GS_EUNSUPPORTED  -4   n larger than this build handles (2048)
+ *     GS_ETOOLARGE     -5   (screen_noalloc) the pass needs more scratch
+ *                           than GS_NOALLOC_SCRATCH_BYTES
  */
 #ifndef GAPSAFE_H
 #define GAPSAFE_H
@@ -62,7 +64,8 @@ enum {
   GS_EINVAL = -1,
   GS_EHIP = -2,
   GS_EWORKSPACE = -3,
-  GS_EUNSUPPORTED = -4
+  GS_EUNSUPPORTED = -4,
+  GS_ETOOLARGE = -5
 };
 
 /* Per-lambda status written to status_out[t]. */
@@ -249,6 +252,26 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
            int32_t* q_out, double* gap_out, double* alpha_out,
            double* radius_out, double* c_out, void* workspace,
            size_t ws_bytes, void* stream);
+
+/* screen() without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and semantics as screen(); its
+ * scratch arrays live in a static device array of GS_NOALLOC_SCRATCH_BYTES
+ * (16 MiB) that the library holds on each GPU it runs on until the process
+ * ends, so the call allocates nothing.  The pass fits when
+ * screen_workspace_size(n, p) <= GS_NOALLOC_SCRATCH_BYTES (about 40 bytes
+ * per column: p up to roughly 400,000 at n = 2048); larger inputs return
+ * GS_ETOOLARGE before anything is launched.  Every call on one GPU uses that
+ * GPU's array: calls that overlap on one GPU (on different streams or host
+ * threads) race and must be serialized by the caller; calls ordered on one
+ * stream are fine.  The array keeps the last call's contents; the pass
+ * initialises everything it reads. */
+#define GS_NOALLOC_SCRATCH_BYTES (16u << 20)
+int screen_noalloc(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
+                   const void* y, const double* beta, double lambda,
+                   const int32_t* active_in, int32_t q_in, int32_t* active_out,
+                   int32_t* q_out, double* gap_out, double* alpha_out, double* radius_out,
+                   double* c_out, void* stream);
 
 /* ---------------------------------------------------------------------
  * Learned warm start.  A small network proposes, at each lambda_t of a path,

@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(_HERE, "libgapsafe.so")
 
 GS_F32, GS_F64 = 0, 1
 GS_OK, GS_NOT_CONVERGED = 0, 1
-GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED = -1, -2, -3, -4
+GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED, GS_ETOOLARGE = -1, -2, -3, -4, -5
+NOALLOC_SCRATCH_BYTES = 16 << 20  # GS_NOALLOC_SCRATCH_BYTES
 SCHEDULES = {"auto": 0, "narrow": 1, "wide": 2}
 CD_MODES = {"auto": 0, "residual": 1}
 
@@ -67,7 +68,7 @@ STAT_NAMES = ["pattern_epochs", "residual_epochs", "rejected", "builds", "setups
 EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
            "lasso_solve_batch", "lasso_batch_plan", "lasso_batch_run", "lasso_batch_plan_free",
            "gs_autotune", "gs_tune_save", "gs_tune_load", "gs_tune_reset",
-           "screen_workspace_size", "screen", "gs_timing_enable",
+           "screen_workspace_size", "screen", "screen_noalloc", "gs_timing_enable",
            "gs_timing_reset", "gs_timing_query", "lasso_strerror",
            "gs_block_corr", "gs_mlp_forward", "gs_mlp_train_workspace_size", "gs_mlp_grad",
            "gs_mlp_adam", "gs_mlp_train_step", "gs_warm_features",
@@ -124,6 +125,10 @@ def load_library(path: str = LIB_PATH):
                            vp, vp, vp, ctypes.c_double, vp, ctypes.c_int32, vp, vp, vp, vp,
                            vp, vp, vp, ctypes.c_size_t, vp]
     lib.screen.restype = ctypes.c_int
+    lib.screen_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp,
+                                   ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    lib.screen_noalloc.restype = ctypes.c_int
     lib.gs_timing_enable.argtypes = [ctypes.c_int]
     lib.gs_timing_enable.restype = None
     lib.gs_timing_reset.argtypes = []
@@ -451,6 +456,44 @@ def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=N
     _check(rc, allow_not_converged=False)
     return dict(active=act_out, q=q_out, gap=gap, alpha=alpha, radius=radius,
                 c=c if c is None else c[:q], workspace=ws)
+
+
+def screen_noalloc(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=None,
+                   out=None):
+    """screen() through the allocation-free entry point: the library uses its
+    static device scratch instead of a workspace.  ``out`` (optional) is a
+    dict of preallocated output tensors as returned by a previous call, so a
+    loop of calls allocates nothing at all."""
+    torch = _torch()
+    lib = load_library()
+    n, p, ld = _design(X)
+    dev = X.device
+    if beta.dtype != torch.float64 or beta.numel() != p or not beta.is_contiguous():
+        raise ValueError("beta must be p contiguous float64 values")
+    if active is not None:
+        if active.dtype != torch.int32 or not active.is_contiguous():
+            raise ValueError("active must be a contiguous int32 tensor")
+        q = active.numel()
+    else:
+        q = p
+    if out is None:
+        out = dict(active=torch.empty(max(q, 1), dtype=torch.int32, device=dev),
+                   q=torch.empty(1, dtype=torch.int32, device=dev),
+                   gap=torch.empty(1, dtype=torch.float64, device=dev),
+                   alpha=torch.empty(1, dtype=torch.float64, device=dev),
+                   radius=torch.empty(1, dtype=torch.float64, device=dev),
+                   c=torch.empty(max(q, 1), dtype=torch.float64, device=dev) if want_c else None)
+    elif out["active"].numel() < q or (out.get("c") is not None and out["c"].numel() < q):
+        raise ValueError("preallocated outputs are smaller than the active set")
+    rc = lib.screen_noalloc(n, p, ld, _dtype_code(X), _ptr(X), _ptr(y), _ptr(beta), float(lam),
+                            _ptr(active), q, _ptr(out["active"]), _ptr(out["q"]),
+                            _ptr(out["gap"]), _ptr(out["alpha"]), _ptr(out["radius"]),
+                            _ptr(out.get("c")), _stream_ptr(stream))
+    _check(rc, allow_not_converged=False)
+    res = dict(out)
+    if res.get("c") is not None:
+        res["c"] = res["c"][:q]
+    return res
 
 
 def timing_enable(on: bool = True):

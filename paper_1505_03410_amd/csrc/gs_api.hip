@@ -16,6 +16,12 @@
 
 using namespace gs;
 
+// ---- static scratch of screen_noalloc (for callers that cannot allocate).
+// In host code `scratch` only names the symbol: its device address comes from
+// hipGetSymbolAddress, and only that address is handed to kernels.
+static_assert(GS_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -609,6 +615,129 @@ int launch_groups(const Shared& sh, const std::vector<Group>& groups, PathOpts p
   return enqueue_groups(sh, launches, s, true);
 }
 
+// Arrays of one screen() pass: the state, the sweep partials, the test
+// counts, the refresh's nonzero list, and per column ||x_j||^2, the FP64
+// coefficients, c and the active list; rho per row.  The path arrays (Gram
+// cache and the like) are not needed here.
+void carve_screen(Carver& cv, int n, int p, Shared* s, ProbDesc* d) {
+  s->descs = nullptr;
+  s->queues = nullptr;
+  s->st = cv.take<WideState>(1);
+  s->wb.part = cv.take<double>(4 * (size_t)std::max(kWideSweepBlocks, kWidePreBlocks));
+  s->wb.cnt = cv.take<int32_t>((p + kTestTile - 1) / kTestTile + 1);
+  s->wb.nzidx = cv.take<int32_t>(p);
+  s->wb.nzval = cv.take<double>(p);
+  d->nrm2 = cv.take<double>(p);
+  d->beta = cv.take<double>(p);
+  d->c = cv.take<double>(p);
+  d->act = cv.take<int32_t>(p);
+  d->lam = cv.take<double>(1);
+  d->rho = cv.take<double>(n);
+}
+
+int check_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, const void* y,
+                 const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
+                 int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
+                 double* radius_out) {
+  if (n < 1 || p < 1 || ldx < n) return GS_EINVAL;
+  if (dtype != GS_F32 && dtype != GS_F64) return GS_EINVAL;
+  if (!X || !y || !beta || !active_out || !q_out || !gap_out || !alpha_out || !radius_out)
+    return GS_EINVAL;
+  if (!finite_pos(lambda)) return GS_EINVAL;
+  if (active_in && (q_in < 0 || q_in > p)) return GS_EINVAL;
+  if (n > kMaxN) return GS_EUNSUPPORTED;
+  return GS_OK;
+}
+
+// The pass itself on the arrays carved from `base` (a workspace, or the
+// static scratch of screen_noalloc).
+int run_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, const void* y,
+               const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
+               int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
+               double* radius_out, double* c_out, char* base, hipStream_t s) {
+  const int q = active_in ? q_in : p;
+  gs_problem pr{};
+  pr.n = n;
+  pr.p = p;
+  pr.ldx = ldx;
+  pr.dtype = dtype;
+  pr.X = X;
+  pr.y = y;
+  pr.T = 1;
+  const WideEntry* w = pick_wide(&pr);
+  if (!w) return GS_EUNSUPPORTED;
+  Carver cv{base};
+  Shared sh;
+  ProbDesc d{};
+  fill_desc(&pr, 0, &d);
+  carve_screen(cv, n, p, &sh, &d);
+  if (c_out) d.c = c_out;
+  WideState* st = sh.st;
+  WideBufs wb = sh.wb;
+  PathOpts po{};
+  po.eps_rel = 1.0;
+  po.f = 1;
+  po.K = 0;
+  {
+    int qi = q_in;
+    void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda};
+    HIPCHK(launch(kScreenPrep[dtype], dim3(1), dim3(256), a, 0, s));
+  }
+  int zero = 0, one = 1;
+  {
+    void* a[] = {&d, &st, &wb, &zero};
+    HIPCHK(launch(kWideRefresh[dtype], dim3(1), dim3(kRefreshThreads), a, 0, s));
+  }
+  int nsweep = std::max(1, std::min(kWideSweepBlocks, (q + kSweepWaves * kSweepU - 1) /
+                                                          (kSweepWaves * kSweepU)));
+  {
+    void* a[] = {&d, &st, &wb};
+    HIPCHK(timed_launch(kTimeSweep, w->sweep_nrm_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0,
+                        s));
+  }
+  {
+    void* a[] = {&d, &st, &wb, &nsweep, &one, &gap_out, &alpha_out, &radius_out, &po};
+    HIPCHK(launch(kWideGap[dtype], dim3(1), dim3(256), a, 0, s));
+  }
+  int ntest = std::max(1, (q + kTestTile - 1) / kTestTile);
+  {
+    void* a[] = {&d, &st, &wb};
+    HIPCHK(launch(kWideTest, dim3(ntest), dim3(256), a, 0, s));
+  }
+  {
+    void* a[] = {&d, &st, &wb, &active_out};
+    HIPCHK(launch(kWideCompact, dim3(ntest), dim3(256), a, 0, s));
+  }
+  {
+    void* a[] = {&d, &st, &wb, &ntest, &q_out};
+    HIPCHK(launch(kWideFin, dim3(1), dim3(64), a, 0, s));
+  }
+  return GS_OK;
+}
+
+// Device address of the static scratch on the current device (looked up
+// once per device: each GPU holds its own copy of the array).
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;
+
+int scratch_base(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      g_err = "hipGetSymbolAddress(scratch) returned a null address";
+      return GS_EHIP;
+    }
+    it = g_scratch_ptr.emplace(dev, static_cast<char*>(ptr)).first;
+  }
+  *out = it->second;
+  return GS_OK;
+}
+
 }  // namespace
 
 int gs::set_hip_error(hipError_t e, const char* where) { return fail_hip(e, where); }
@@ -701,13 +830,8 @@ size_t screen_workspace_size(int32_t n, int32_t p) {
   if (n < 1 || p < 1) return 0;
   Carver cv{nullptr};
   Shared sh;
-  carve_shared(cv, 1, p, &sh);
-  gs_problem pr{};
-  pr.n = n;
-  pr.p = p;
-  pr.T = 1;
-  ProbDesc d;
-  carve_problem(cv, &pr, &d);
+  ProbDesc d{};
+  carve_screen(cv, n, p, &sh, &d);
   return align_up(cv.off, 256);
 }
 
@@ -715,75 +839,31 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, cons
            const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
            int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
            double* radius_out, double* c_out, void* workspace, size_t ws_bytes, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (n < 1 || p < 1 || ldx < n) return GS_EINVAL;
-  if (dtype != GS_F32 && dtype != GS_F64) return GS_EINVAL;
-  if (!X || !y || !beta || !active_out || !q_out || !gap_out || !alpha_out || !radius_out)
-    return GS_EINVAL;
-  if (!finite_pos(lambda)) return GS_EINVAL;
-  if (active_in && (q_in < 0 || q_in > p)) return GS_EINVAL;
-  if (n > kMaxN) return GS_EUNSUPPORTED;
+  const int rc = check_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out,
+                              q_out, gap_out, alpha_out, radius_out);
+  if (rc) return rc;
   if (!workspace) return GS_EWORKSPACE;
   if (ws_bytes < screen_workspace_size(n, p)) return GS_EWORKSPACE;
-  const int q = active_in ? q_in : p;
-  gs_problem pr{};
-  pr.n = n;
-  pr.p = p;
-  pr.ldx = ldx;
-  pr.dtype = dtype;
-  pr.X = X;
-  pr.y = y;
-  pr.T = 1;
-  const WideEntry* w = pick_wide(&pr);
-  if (!w) return GS_EUNSUPPORTED;
-  Carver cv{static_cast<char*>(workspace)};
-  Shared sh;
-  carve_shared(cv, 1, p, &sh);
-  ProbDesc d{};
-  fill_desc(&pr, 0, &d);
-  carve_problem(cv, &pr, &d);
-  if (c_out) d.c = c_out;
-  WideState* st = sh.st;
-  WideBufs wb = sh.wb;
-  PathOpts po{};
-  po.eps_rel = 1.0;
-  po.f = 1;
-  po.K = 0;
-  {
-    int qi = q_in;
-    void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda};
-    HIPCHK(launch(kScreenPrep[dtype], dim3(1), dim3(256), a, 0, s));
-  }
-  int zero = 0, one = 1;
-  {
-    void* a[] = {&d, &st, &wb, &zero};
-    HIPCHK(launch(kWideRefresh[dtype], dim3(1), dim3(kRefreshThreads), a, 0, s));
-  }
-  int nsweep = std::max(1, std::min(kWideSweepBlocks, (q + kSweepWaves * kSweepU - 1) /
-                                                          (kSweepWaves * kSweepU)));
-  {
-    void* a[] = {&d, &st, &wb};
-    HIPCHK(timed_launch(kTimeSweep, w->sweep_nrm_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0,
-                        s));
-  }
-  {
-    void* a[] = {&d, &st, &wb, &nsweep, &one, &gap_out, &alpha_out, &radius_out, &po};
-    HIPCHK(launch(kWideGap[dtype], dim3(1), dim3(256), a, 0, s));
-  }
-  int ntest = std::max(1, (q + kTestTile - 1) / kTestTile);
-  {
-    void* a[] = {&d, &st, &wb};
-    HIPCHK(launch(kWideTest, dim3(ntest), dim3(256), a, 0, s));
-  }
-  {
-    void* a[] = {&d, &st, &wb, &active_out};
-    HIPCHK(launch(kWideCompact, dim3(ntest), dim3(256), a, 0, s));
-  }
-  {
-    void* a[] = {&d, &st, &wb, &ntest, &q_out};
-    HIPCHK(launch(kWideFin, dim3(1), dim3(64), a, 0, s));
-  }
-  return GS_OK;
+  return run_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out, q_out,
+                    gap_out, alpha_out, radius_out, c_out, static_cast<char*>(workspace),
+                    static_cast<hipStream_t>(stream));
+}
+
+int screen_noalloc(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
+                   const void* y, const double* beta, double lambda,
+                   const int32_t* active_in, int32_t q_in, int32_t* active_out,
+                   int32_t* q_out, double* gap_out, double* alpha_out, double* radius_out,
+                   double* c_out, void* stream) {
+  const int rc = check_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out,
+                              q_out, gap_out, alpha_out, radius_out);
+  if (rc) return rc;
+  if (screen_workspace_size(n, p) > (size_t)GS_NOALLOC_SCRATCH_BYTES) return GS_ETOOLARGE;
+  char* base = nullptr;
+  const int r2 = scratch_base(&base);
+  if (r2) return r2;
+  return run_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out, q_out,
+                    gap_out, alpha_out, radius_out, c_out, base,
+                    static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------ batch plans
@@ -1042,6 +1122,9 @@ const char* lasso_strerror(int code) {
     case GS_EHIP: return g_err.empty() ? "HIP runtime error" : g_err.c_str();
     case GS_EWORKSPACE: return "workspace missing or too small";
     case GS_EUNSUPPORTED: return "unsupported: n larger than 2048";
+    case GS_ETOOLARGE:
+      return "input larger than the static scratch of the allocation-free entry point "
+             "(GS_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown error code";
   }
 }

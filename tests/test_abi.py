@@ -129,8 +129,29 @@ def test_screen_invalid(lib):
         assert lib.screen(*a) == gs.GS_EINVAL, (idx, val)
 
 
+def test_screen_noalloc_rejects_before_launch(lib):
+    """The allocation-free screen() checks its arguments and the size of its
+    static scratch on the host, before touching the device: bad arguments
+    give GS_EINVAL, a pass larger than GS_NOALLOC_SCRATCH_BYTES gives
+    GS_ETOOLARGE (fake device pointers are never dereferenced)."""
+    vp = ctypes.c_void_p(4096)
+    args = [8, 20, 8, gs.GS_F32, vp, vp, vp, 0.5, None, 0, vp, vp, vp, vp, vp, None, None]
+    for idx, val in [(0, 0), (2, 4), (3, 5), (7, 0.0), (7, float("nan")), (4, None)]:
+        a = list(args)
+        a[idx] = val
+        assert lib.screen_noalloc(*a) == gs.GS_EINVAL, (idx, val)
+    big = list(args)
+    big[1] = 1_000_000
+    assert lib.screen_workspace_size(8, 1_000_000) > gs.NOALLOC_SCRATCH_BYTES
+    assert lib.screen_noalloc(*big) == gs.GS_ETOOLARGE
+    assert "static scratch" in gs.strerror(gs.GS_ETOOLARGE)
+    # the largest p that fits at n = 2048 is about 400,000
+    assert lib.screen_workspace_size(2048, 400_000) <= gs.NOALLOC_SCRATCH_BYTES
+    assert lib.screen_workspace_size(2048, 420_000) > gs.NOALLOC_SCRATCH_BYTES
+
+
 def test_strerror(lib):
-    for c in (0, 1, -1, -2, -3, -4, 99):
+    for c in (0, 1, -1, -2, -3, -4, -5, 99):
         assert isinstance(gs.strerror(c), str) and gs.strerror(c)
 
 

@@ -109,6 +109,11 @@ enum {
                                  the exact check over the whole active set   */
   GS_STAT_NEAR,               /* pattern epochs where the norm bound left at
                                  most 64 zero coordinates, checked exactly   */
+  GS_STAT_WIDE_VISITS,        /* wide schedule: coordinates the CD rounds
+                                 visited exactly (the others were proven to
+                                 stay at zero)                               */
+  GS_STAT_WIDE_ROUNDS,        /* wide schedule: CD rounds                     */
+  GS_STAT_WIDE_STOPS,         /* wide schedule: rounds that re-anchored       */
   GS_NSTATS
 };
 

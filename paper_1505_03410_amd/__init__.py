@@ -63,7 +63,8 @@ class gs_opts(ctypes.Structure):
 
 # Names of the GS_NSTATS counters of gs_opts.stats, in index order.
 STAT_NAMES = ["pattern_epochs", "residual_epochs", "rejected", "builds", "setups",
-              "support_changes", "passes", "skipped", "exact_checks", "near_checks"]
+              "support_changes", "passes", "skipped", "exact_checks", "near_checks",
+              "wide_visits", "wide_rounds", "wide_stops"]
 
 EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_path",
            "lasso_solve_batch", "lasso_batch_plan", "lasso_batch_run", "lasso_batch_plan_free",

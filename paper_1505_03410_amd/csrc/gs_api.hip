@@ -187,6 +187,8 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   d->pslot = cv.take<int32_t>(ldg);
   d->pmem = cv.take<int32_t>(ldg);
   d->c2 = cv.take<double>(ldg);
+  d->lst = cv.take<int32_t>(2 * (size_t)pr->p);
+  d->lval = cv.take<double>(4 * (size_t)pr->p);
   d->ldg = ldg;
   d->ns = ns;
 }
@@ -260,9 +262,9 @@ struct Timed {
 };
 bool g_timing = false;
 std::vector<Timed> g_pending;
-double g_total_ms[2] = {0.0, 0.0};
-int64_t g_launches[2] = {0, 0};
-enum { kTimeSweep = 0, kTimePath = 1 };
+double g_total_ms[3] = {0.0, 0.0, 0.0};
+int64_t g_launches[3] = {0, 0, 0};
+enum { kTimeSweep = 0, kTimePath = 1, kTimeCD = 2 };
 
 hipError_t timed_launch(int slot, const void* k, dim3 g, dim3 b, void** args, size_t smem,
                         hipStream_t s) {
@@ -362,14 +364,8 @@ int upload_lambdas(const gs_problem* pr, const ProbDesc* d, hipStream_t s) {
 int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc d,
              hipStream_t s) {
   const WideEntry* w = pick_wide(pr);
-  const NarrowEntry* ne = pick_narrow(pr);
-  if (!w || !ne) return GS_EUNSUPPORTED;
+  if (!w) return GS_EUNSUPPORTED;
   PathOpts po = path_opts(o, false);
-  // the CD kernel stages the active positions' coefficients in LDS
-  po.lds_cap = lds_cap_for(ne, 1, 0);
-  const size_t cd_lds = ne->lds_bytes + sizeof(float) * (size_t)po.lds_cap;
-  HIPCHK(hipFuncSetAttribute(ne->cd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)cd_lds));
   WideState* st = sh.st;
   WideBufs wb = sh.wb;
   const int dt = pr->dtype;
@@ -387,10 +383,15 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
   int32_t* nullq = nullptr;
   int32_t* nullo = nullptr;
   double* nd = nullptr;
-  const long long max_passes =
-      (long long)pr->T * ((long long)o->max_epochs / o->screen_every + 3) + 16;
+  int nt = ntest;
+  // One iteration enqueues a screening pass and f CD rounds; every kernel
+  // checks the state machine, so a pass runs only when the previous f epochs
+  // are done and a round only while an epoch is pending (a round that
+  // re-anchors part of an epoch leaves the rest to the next iteration).
+  const long long max_iter =
+      4 * ((long long)pr->T * ((long long)o->max_epochs / o->screen_every + 3) + 16);
   long long enq = 0;
-  int chunk = 8;
+  int chunk = 4;
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
       void* ar[] = {&d, &st, &wb, &zero};
@@ -404,24 +405,36 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
       HIPCHK(launch(kWideTest, dim3(ntest), dim3(256), at, 0, s));
       void* ac[] = {&d, &st, &wb, &nullo};
       HIPCHK(launch(kWideCompact, dim3(ntest), dim3(256), ac, 0, s));
-      int nt = ntest;
       void* af[] = {&d, &st, &wb, &nt, &nullq};
       HIPCHK(launch(kWideFin, dim3(1), dim3(64), af, 0, s));
       void* ar2[] = {&d, &st, &wb, &one};
       HIPCHK(launch(kWideRefresh[dt], dim3(1), dim3(kRefreshThreads), ar2, 0, s));
-      void* acd[] = {&d, &st, &po};
-      HIPCHK(launch(ne->cd_kernel, dim3(1), dim3(64), acd, cd_lds, s));
+      for (int r = 0; r < o->screen_every; ++r) {
+        void* a1[] = {&d, &st};
+        HIPCHK(launch(w->csweep_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a1, 0, s));
+        void* a2[] = {&d, &st, &wb};
+        HIPCHK(launch(kWideLCount, dim3(ntest), dim3(256), a2, 0, s));
+        HIPCHK(launch(kWideLCompact, dim3(ntest), dim3(256), a2, 0, s));
+        void* a3[] = {&d, &st, &wb, &nt, &po};
+        HIPCHK(timed_launch(kTimeCD, w->walk_kernel, dim3(1), dim3(64), a3, 0, s));
+      }
     }
     enq += chunk;
     WideState hs;
     HIPCHK(hipMemcpyAsync(&hs, st, sizeof(WideState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hs.done) return hs.status_acc ? GS_NOT_CONVERGED : GS_OK;
-    if (enq > max_passes) {
+    if (hs.done) {
+      if (po.stats) {
+        void* a[] = {&st, &po.stats};
+        HIPCHK(launch(kWideStats, dim3(1), dim3(64), a, 0, s));
+      }
+      return hs.status_acc ? GS_NOT_CONVERGED : GS_OK;
+    }
+    if (enq > max_iter) {
       g_err = "wide schedule: pass budget exceeded";
       return GS_EHIP;
     }
-    chunk = std::min(chunk * 2, 256);
+    chunk = std::min(chunk * 2, 32);
   }
 }
 
@@ -1098,8 +1111,10 @@ void gs_timing_enable(int on) { g_timing = on != 0; }
 
 void gs_timing_reset(void) {
   resolve_timing();
-  g_total_ms[0] = g_total_ms[1] = 0.0;
-  g_launches[0] = g_launches[1] = 0;
+  for (int i = 0; i < 3; ++i) {
+    g_total_ms[i] = 0.0;
+    g_launches[i] = 0;
+  }
 }
 
 int gs_timing_query(const char* kernel, double* total_ms, int64_t* launches) {
@@ -1107,6 +1122,7 @@ int gs_timing_query(const char* kernel, double* total_ms, int64_t* launches) {
   int slot = -1;
   if (std::strcmp(kernel, "sweep") == 0) slot = kTimeSweep;
   if (std::strcmp(kernel, "path") == 0) slot = kTimePath;
+  if (std::strcmp(kernel, "cd") == 0) slot = kTimeCD;
   if (slot < 0) return -1;
   resolve_timing();
   if (total_ms) *total_ms = g_total_ms[slot];

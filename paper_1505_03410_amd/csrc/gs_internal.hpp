@@ -40,6 +40,9 @@ struct ProbDesc {
   int32_t* pslot;   // ldg: slot holding the Gram column of feature j, or -1
   int32_t* pmem;    // ldg: 1 when position k is in the support list, else 0
   double* c2;       // ldg: second buffer of the correlations c
+  int32_t* lst;     // 2p: positions of A the wide CD visits exactly, then their
+                    // features (wide schedule)
+  double* lval;     // 4p: per listed entry c_k, beta_j, 1/||x_j||^2, ||x_j||^2
   int64_t ldg;      // p rounded up to a multiple of 256
   int32_t ns;       // Gram slots of this problem (<= kSlotsMax)
   int32_t orig;     // index of the problem in the caller's array
@@ -60,6 +63,10 @@ enum {
   kStatSkipped,            // epochs skipped at an exact fixed point
   kStatExact,              // pattern epochs that needed the exact zero-coordinate check
   kStatNear,               // pattern epochs that checked at most 64 coordinates exactly
+  kStatWideVisits,         // wide schedule: coordinates visited exactly by the CD rounds
+  kStatWideRounds,         // wide schedule: CD rounds (an epoch or the part of one after
+                           // a re-anchor)
+  kStatWideStops,          // wide schedule: rounds that stopped to re-anchor
   kNumStats
 };
 
@@ -96,6 +103,13 @@ struct WideState {
   double gap, alpha_s, radius_s, e_c, M;
   double R2, Ry, l1, sbx, xmax;
   int32_t nnz, nblk_sweep, q_new, pad_;
+  // CD rounds of the wide schedule: an epoch is walked from position
+  // `resume`; zero coordinates whose anchored correlation keeps them at zero
+  // while the residual moves by at most tau are skipped
+  int32_t resume, first_epoch;
+  double tau, tau_first, dmax2;
+  double pb2;  // 2 P(beta) at the last pass: bounds ||rho||^2 of the CD iterates
+  long long n_visits, n_rounds, n_stops, n_epochs;
 };
 
 // Kernel configuration: rows per lane layout.  S lanes share one column

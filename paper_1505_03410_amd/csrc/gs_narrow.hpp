@@ -1458,43 +1458,4 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
   }
 }
 
-// The CD part of the wide schedule: one wavefront runs min(f, K - k) epochs
-// over the active set the wide kernels left in the workspace (residual mode).
-template <typename XT, int VEC, int S, int NG, bool GATHER>
-__global__ __launch_bounds__(64) void k_wide_cd(ProbDesc d, WideState* st, PathOpts opts) {
-  using N = Narrow<XT, VEC, S, NG, GATHER>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (st->done || st->phase != 2) return;
-  const int lane = threadIdx.x;
-  typename N::Ctx x;
-  typename N::Pat pt;
-  x.X = gptr((const XT*)d.X);
-  x.ldx = d.ldx;
-  x.n = d.n;
-  x.p = d.p;
-  x.lane = lane;
-  x.slot = lane / S;
-  x.seg = lane % S;
-  bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, pt, smem, opts);
-  x.nrm2 = gptr(d.nrm2);
-  x.inv = gptr(d.inv);
-  x.beta = gptr(d.beta);
-  x.c = gptr(d.c);
-  x.act = gptr(d.act) + (int64_t)st->cur * d.p;
-  x.act_c = (const cst<int32_t>*)x.act;  // the compaction kernels wrote A; this one only reads it
-  N::setup(x, gptr(d.rows));
-  for (int i = lane; i < d.n; i += 64) x.rho_l[i] = gptr(d.rho)[i];
-  wave_lds_order();
-  const int q = st->q;
-  const bool full = st->full != 0;
-  const int k0 = st->k;
-  const int ne = min(opts.f, opts.K - k0);
-  const double lambda = gptr(d.lam)[st->t];
-  N::template cd_epochs<true>(x, q, full, lambda, ne, 0);
-  if (lane == 0) {
-    st->k = k0 + ne;
-    st->phase = 0;
-  }
-}
-
 }  // namespace gs

@@ -8,7 +8,6 @@ namespace gs {
 struct NarrowEntry {
   Cfg cfg;
   const void* path_kernel;  // k_path_narrow<...>
-  const void* cd_kernel;    // k_wide_cd<...>
   size_t lds_bytes;
 };
 
@@ -17,6 +16,8 @@ struct WideEntry {
   const void* pre_kernel;   // k_wide_pre<...>
   const void* sweep_kernel; // k_wide_sweep<..., false>
   const void* sweep_nrm_kernel;  // k_wide_sweep<..., true>: also ||x_j||^2
+  const void* csweep_kernel;     // k_wide_csweep<...>: c from the resume position
+  const void* walk_kernel;       // k_wide_walk<...>: the CD epoch on one wave
   int nmax() const { return 64 * NG * vec; }
 };
 
@@ -43,6 +44,9 @@ extern const void* const kScreenPrep[2];   // k_screen_prep<...>
 extern const void* const kWideTest;
 extern const void* const kWideCompact;
 extern const void* const kWideFin;
+extern const void* const kWideLCount;
+extern const void* const kWideLCompact;
+extern const void* const kWideStats;
 extern const void* const kFillI32;
 
 }  // namespace gs
@@ -51,6 +55,5 @@ extern const void* const kFillI32;
   {                                                                                         \
     {0, sizeof(XT) == 8 ? 1 : 0, VEC, S, NG, G},                                            \
         reinterpret_cast<const void*>(&gs::k_path_narrow<XT, VEC, S, NG, G>),               \
-        reinterpret_cast<const void*>(&gs::k_wide_cd<XT, VEC, S, NG, G>),                   \
         gs::narrow_lds_bytes<XT, VEC, S, NG, G>()                                           \
   }

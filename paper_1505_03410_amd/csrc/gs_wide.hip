@@ -88,6 +88,74 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
     if (keep & (1u << e)) dst[pos++] = js[e];
 }
 
+__global__ __launch_bounds__(256) void k_wide_lcount(ProbDesc d, WideState* st, WideBufs wb) {
+  __shared__ double sh[256];
+  if (st->done || st->phase != 2) return;
+  const int q = st->q;
+  const int tile0 = st->resume + blockIdx.x * kTestTile;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const double lambda = d.lam[st->t];
+  const double tau = st->tau;
+  const double rn = sqrt(st->R2) * (1.0 + gam(d.n + 2));
+  int cnt = 0;
+  for (int e = threadIdx.x; e < kTestTile; e += 256) {
+    const int k = tile0 + e;
+    if (k >= q) break;
+    if (wide_listed(d, st, act[k], d.c[k], lambda, tau, rn)) ++cnt;
+  }
+  const double tot = block_sum<256>((double)cnt, sh);
+  if (threadIdx.x == 0) wb.cnt[blockIdx.x] = (int)tot;
+}
+
+__global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st, WideBufs wb) {
+  constexpr int PER = kTestTile / 256;
+  __shared__ int scan[256];
+  if (st->done || st->phase != 2) return;
+  const int q = st->q;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const double lambda = d.lam[st->t];
+  const double tau = st->tau;
+  const double rn = sqrt(st->R2) * (1.0 + gam(d.n + 2));
+  int off = 0;
+  for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];
+  const int k0 = st->resume + blockIdx.x * kTestTile + threadIdx.x * PER;
+  unsigned keep = 0;
+  int c = 0;
+  int js[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int k = k0 + e;
+    js[e] = k < q ? act[k] : 0;
+    if (k < q && wide_listed(d, st, js[e], d.c[k], lambda, tau, rn)) {
+      keep |= 1u << e;
+      ++c;
+    }
+  }
+  scan[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int v = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = off + scan[threadIdx.x] - c;
+  // entry: position, feature, then (c_k, beta_j, 1/||x_j||^2, ||x_j||^2)
+#pragma unroll
+  for (int e = 0; e < PER; ++e)
+    if (keep & (1u << e)) {
+      const int j = js[e];
+      d.lst[pos] = k0 + e;
+      d.lst[d.p + pos] = j;
+      double* v = d.lval + 4 * (int64_t)pos;
+      v[0] = d.c[k0 + e];
+      v[1] = d.beta[j];
+      v[2] = d.inv[j];
+      v[3] = d.nrm2[j];
+      ++pos;
+    }
+}
+
 __global__ __launch_bounds__(64) void k_wide_fin(ProbDesc d, WideState* st, WideBufs wb,
                                                  int ntest, int32_t* q_out) {
   if (st->done || st->phase != 1) return;
@@ -103,8 +171,22 @@ __global__ __launch_bounds__(64) void k_wide_fin(ProbDesc d, WideState* st, Wide
       st->cur ^= 1;
       st->full = 0;
       st->phase = 2;
+      st->resume = 0;
+      st->dmax2 = 0.0;
+      if (st->first_epoch) st->tau = st->tau_first;
     }
   }
+}
+
+// Adds the wide path's counters to the caller's gs_opts.stats.
+__global__ void k_wide_stats(const WideState* st, long long* stats) {
+  if (threadIdx.x != 0 || !stats) return;
+  unsigned long long* s = reinterpret_cast<unsigned long long*>(stats);
+  atomicAdd(&s[kStatPasses], (unsigned long long)st->passes);
+  atomicAdd(&s[kStatResidualEpochs], (unsigned long long)st->n_epochs);
+  atomicAdd(&s[kStatWideVisits], (unsigned long long)st->n_visits);
+  atomicAdd(&s[kStatWideRounds], (unsigned long long)st->n_rounds);
+  atomicAdd(&s[kStatWideStops], (unsigned long long)st->n_stops);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
@@ -157,13 +239,18 @@ const void* const kWideTest = reinterpret_cast<const void*>(&k_wide_test);
 const void* const kWideCompact = reinterpret_cast<const void*>(&k_wide_compact);
 const void* const kWideFin = reinterpret_cast<const void*>(&k_wide_fin);
 const void* const kFillI32 = reinterpret_cast<const void*>(&k_fill_i32);
+const void* const kWideLCount = reinterpret_cast<const void*>(&k_wide_lcount);
+const void* const kWideLCompact = reinterpret_cast<const void*>(&k_wide_lcompact);
+const void* const kWideStats = reinterpret_cast<const void*>(&k_wide_stats);
 
 #define GS_WIDE_ENTRY(XT, VEC, NG)                                              \
   {                                                                             \
     sizeof(XT) == 8 ? 1 : 0, VEC, NG,                                           \
         reinterpret_cast<const void*>(&k_wide_pre<XT, VEC, NG>),                \
         reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, false>),       \
-        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, true>)         \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, true>),        \
+        reinterpret_cast<const void*>(&k_wide_csweep<XT, VEC, NG>),             \
+        reinterpret_cast<const void*>(&k_wide_walk<XT, VEC, NG>)                \
   }
 
 // Ordered by dtype, vector width, then capacity (64 * NG * VEC rows).

@@ -9,7 +9,8 @@
 //   compact (grid)     ordered compaction of A into the other buffer
 //   fin     (1 block)  |A'|, swap buffers
 //   refresh (1 block)  again only if a nonzero coefficient was screened
-//   cd      (1 wave)   f CD epochs over A (k_wide_cd in gs_narrow.hpp)
+//   f CD rounds        csweep (grid), lcount + lcompact (grid), walk (1 wave):
+//                      one epoch each, see the CD rounds below
 //
 // Every reduction goes through per-block partials reduced in a fixed order,
 // so results are bitwise reproducible.
@@ -168,6 +169,15 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
     st->passes = 0;
     st->status_acc = 0;
     st->nonfinite = (bad != 0.0) ? 1 : 0;
+    st->resume = 0;
+    st->first_epoch = 1;
+    st->tau = INFINITY;
+    st->tau_first = INFINITY;
+    st->dmax2 = 0.0;
+    st->n_visits = 0;
+    st->n_rounds = 0;
+    st->n_stops = 0;
+    st->n_epochs = 0;
   }
 }
 
@@ -181,6 +191,7 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
   __shared__ int wcnt[NW];
   __shared__ double sh[kRefreshThreads];
   if (st->done) return;
+  if (mode == 0 && st->phase != 0) return;
   if (mode == 1 && (st->phase != 2 || !st->need_refresh)) return;
   const int q = st->q;
   const bool full = st->full != 0;
@@ -240,7 +251,11 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
     st->R2 = s2;
     st->Ry = sy;
     st->nnz = nnz;
-    if (mode == 1) st->need_refresh = 0;
+    if (mode == 1) {
+      // screened coefficients were zeroed: ||beta||_1 only fell
+      st->pb2 = fmax(st->pb2, s2 + 2.0 * d.lam[st->t] * st->l1);
+      st->need_refresh = 0;
+    }
   }
 }
 
@@ -254,7 +269,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
   using L = ColLayout<XT, VEC, 64, NG, false>;
   constexpr int RPL = L::RPL;
   __shared__ double sh[64 * kSweepWaves];
-  if (st->done) return;
+  if (st->done || st->phase != 0) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = st->q;
   const bool full = st->full != 0;
@@ -337,7 +352,7 @@ __global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, Wid
                                                   double* alpha_o, double* radius_o,
                                                   PathOpts opts) {
   __shared__ double sh[256];
-  if (st->done) return;
+  if (st->done || st->phase != 0) return;
   double M = 0.0, l1 = 0.0, sb = 0.0, xm = 0.0;
   for (int b = threadIdx.x; b < nsweep; b += 256) {
     M = fmax(M, wb.part[4 * b]);
@@ -385,6 +400,7 @@ __global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, Wid
       st->cur = 0;
       st->phase = 0;
       st->need_refresh = 0;
+      st->first_epoch = 1;
       if (t + 1 >= d.T) st->done = 1;
     }
   } else if (threadIdx.x == 0) {
@@ -394,6 +410,247 @@ __global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, Wid
     st->gap = g.gap;
     st->phase = 1;
     st->passes += 1;
+    // 2 P(beta) at this pass bounds ||rho||^2 for every later CD iterate of
+    // the interval (CD never increases P)
+    st->l1 = l1;
+    st->pb2 = st->R2 + 2.0 * lambda * l1;
+  }
+}
+
+// ---- CD rounds of the wide schedule.
+//
+// An epoch of cyclic CD over A (Algorithm 1) visits every position in
+// order.  A coordinate at zero stays at zero at its visit iff
+// |x_k^T rho_visit| <= lambda.  With c_k = x_k^T rho_a at an anchor rho_a
+// and D = rho_visit - rho_a, |x_k^T rho_visit| <= |c_k| + ||x_k|| ||D||, so
+// while ||D|| <= tau every zero coordinate with |c_k| + ||x_k|| tau <= lambda
+// (less the rounding of c_k) is left unchanged by its visit and need not be
+// visited.  A round therefore
+//   1. sweeps c_k for the positions from `resume` on (grid-wide, the anchor),
+//   2. lists, in order, the positions that are nonzero or fail that test
+//      (k_wide_lcount / k_wide_lcompact),
+//   3. visits the listed positions exactly on one wavefront, tracking ||D||
+//      from the scalars of each update:
+//         ||D - delta x_m||^2 = ||D||^2 - 2 delta (d_m - c_m) + delta^2 ||x_m||^2
+//      with d_m = x_m^T rho_visit, and stops right after an update that takes
+//      ||D|| above tau: the next round re-anchors at the following position.
+// The result is the cyclic epoch itself (up to the order of rounding).
+
+// c_k = x_{A[k]}^T rho for the positions k >= resume (the anchor of a round).
+template <typename XT, int VEC, int NG>
+__global__ __launch_bounds__(64 * kSweepWaves) void k_wide_csweep(ProbDesc d, WideState* st) {
+  using L = ColLayout<XT, VEC, 64, NG, false>;
+  constexpr int RPL = L::RPL;
+  if (st->done || st->phase != 2) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = st->q;
+  const int k0 = st->resume;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const XT* X = (const XT*)d.X;
+  double r[RPL];
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      int i = L::row(lane, m, e);
+      r[m * VEC + e] = (i < d.n) ? d.rho[i] : 0.0;
+    }
+  const int W = gridDim.x * kSweepWaves;
+  const int wid = blockIdx.x * kSweepWaves + w;
+  for (int base = k0 + wid * kSweepU; base < q; base += W * kSweepU) {
+    XT xv[kSweepU][RPL];
+    int jj[kSweepU];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) jj[u] = act[base + u < q ? base + u : q - 1];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) L::load_raw(X + (int64_t)jj[u] * d.ldx, d.n, lane, nullptr, xv[u]);
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) a = fma((double)xv[u][i], r[i], a);  // r is zero at rows >= n
+      a = wave_sum(a);
+      if (base + u < q && lane == 0) d.c[base + u] = a;
+    }
+  }
+}
+
+// Whether position k (>= resume) must be visited exactly in this round.
+__device__ __forceinline__ bool wide_listed(const ProbDesc& d, const WideState* st, int j,
+                                            double ck, double lambda, double tau, double rnorm) {
+  const double nr = d.nrm2[j];
+  if (!(nr > 0.0)) return false;  // a zero column never moves
+  if (d.beta[j] != 0.0) return true;
+  const double xn = sqrt(nr) * (1.0 + gam(d.n + 2));
+  // |c^_k - x_k^T rho_a| <= gamma_{n+1} ||x_k|| ||rho_a||
+  const double thr = lambda * (1.0 - 4.0 * kU) - gam(d.n + 1) * xn * rnorm;
+  return fabs(ck) + xn * tau > thr;
+}
+
+// The CD walk of one round on one wavefront (layout of the sweep: all 64
+// lanes split one column).  ntile: number of list tiles of the round.
+template <typename XT, int VEC, int NG>
+__global__ __launch_bounds__(64) void k_wide_walk(ProbDesc d, WideState* st, WideBufs wb,
+                                                  int ntile, PathOpts opts) {
+  using L = ColLayout<XT, VEC, 64, NG, false>;
+  constexpr int RPL = L::RPL;
+  constexpr int SEG = 1024;  // list entries staged in LDS at a time
+  constexpr int RING = (RPL * sizeof(XT) <= 64) ? 6 : 3;
+  __shared__ int s_j[SEG];
+  __shared__ double s_c[SEG], s_b[SEG], s_inv[SEG], s_nr[SEG], s_xn[SEG];
+  if (st->done || st->phase != 2) return;
+  const int lane = threadIdx.x;
+  const int q = st->q;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const double lambda = d.lam[st->t];
+  const double tau = st->tau;
+  const double tau2 = tau * tau;
+  const gbl<XT>* X = gptr((const XT*)d.X);
+  int nl = 0;
+  for (int b = lane; b < ntile; b += 64) nl += wb.cnt[b];
+  nl = wave_sum_i(nl);
+  const uint64_t mk = L::rowmask(lane, d.n);
+  double r[RPL];
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      int i = L::row(lane, m, e);
+      r[m * VEC + e] = (i < d.n) ? d.rho[i] : 0.0;
+    }
+  // ||rho|| of every iterate of the round is at most sqrt(2 P) of the pass
+  const double rb = sqrt(st->pb2) * (1.0 + 1e-9);
+  const double erc = 4.0 * gam(d.n + 1) * rb;
+  double D2 = 0.0, De = 0.0, dmax2 = 0.0;
+  int stop_k = -1;
+  long long visits = 0;
+  const gbl<int32_t>* lj = gptr(d.lst) + d.p;
+  const gbl<double>* lv = gptr(d.lval);
+  for (int s0 = 0; s0 < nl && stop_k < 0; s0 += SEG) {
+    const int cnt = min(SEG, nl - s0);
+    // the list holds each entry's feature and scalars contiguously, so the
+    // staging loads are coalesced and independent (four entries per lane in
+    // flight)
+    for (int e0 = 0; e0 < cnt; e0 += 256) {
+      int jv[4];
+      double cv[4], bv[4], iv[4], nv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 64 * u + lane;
+        const int ee = s0 + (e < cnt ? e : cnt - 1);
+        jv[u] = lj[ee];
+        cv[u] = lv[4 * (int64_t)ee + 0];
+        bv[u] = lv[4 * (int64_t)ee + 1];
+        iv[u] = lv[4 * (int64_t)ee + 2];
+        nv[u] = lv[4 * (int64_t)ee + 3];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 64 * u + lane;
+        if (e < cnt) {
+          s_j[e] = jv[u];
+          s_c[e] = cv[u];
+          s_b[e] = bv[u];
+          s_inv[e] = iv[u];
+          s_nr[e] = nv[u];
+          s_xn[e] = sqrt(nv[u]) * (1.0 + gam(d.n + 2));
+        }
+      }
+    }
+    wave_lds_order();
+    XT xs[RING][RPL];
+    // the first RING-1 columns, issued in ring order: the scheduler must not
+    // reorder them, or the wait for stage 0 would also wait for the others
+#pragma unroll
+    for (int i = 0; i + 1 < RING; ++i) {
+      L::load_raw(X + (int64_t)s_j[i < cnt ? i : cnt - 1] * d.ldx, d.n, lane, nullptr, xs[i]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    int e_stop = -1;
+    for (int e0 = 0; e0 < cnt; e0 += RING) {
+#pragma unroll
+      for (int i = 0; i < RING; ++i) {
+        const int e = e0 + i;
+        {
+          const int en = e + RING - 1;
+          L::load_raw(X + (int64_t)s_j[en < cnt ? en : cnt - 1] * d.ldx, d.n, lane, nullptr,
+                      xs[(i + RING - 1) % RING]);
+        }
+        if (e < cnt && e_stop < 0) {
+          const double b = s_b[e], inv = s_inv[e];
+          // rows >= n hold copies of row 0: zero them once, in FP32
+          double xd[RPL];
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) xd[t] = (double)(((mk >> t) & 1ull) ? xs[i][t] : XT(0));
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; t += 4) {
+            a0 = fma(xd[t], r[t], a0);
+            if (t + 1 < RPL) a1 = fma(xd[t + 1], r[t + 1], a1);
+            if (t + 2 < RPL) a2 = fma(xd[t + 2], r[t + 2], a2);
+            if (t + 3 < RPL) a3 = fma(xd[t + 3], r[t + 3], a3);
+          }
+          const double dm = wave_sum((a0 + a1) + (a2 + a3));
+          const double bn = soft_thr(lambda * inv, b + dm * inv);
+          ++visits;
+          if (bn != b) {
+            const double delta = bn - b;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) r[t] = fma(-delta, xd[t], r[t]);
+            if (lane == 0) s_b[e] = bn;
+            const double nr = s_nr[e];
+            const double dd = dm - s_c[e];
+            const double t1 = -2.0 * delta * dd, t2 = delta * delta * nr;
+            D2 = D2 + t1 + t2;
+            // rounding of this update and of d_m - c_m taken as x_m^T D
+            De += 4.0 * kU * (fabs(D2) + fabs(t1) + t2) + fabs(delta) * s_xn[e] * erc;
+            dmax2 = fmax(dmax2, D2 + De);
+            if (D2 + De > tau2) e_stop = e;
+          }
+        }
+      }
+      if (e_stop >= 0) break;
+    }
+    wave_lds_order();
+    for (int e = lane; e < cnt; e += 64) d.beta[s_j[e]] = s_b[e];
+    if (e_stop >= 0) stop_k = gptr(d.lst)[s0 + e_stop];
+    wave_lds_order();
+  }
+  double r2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int i = L::row(lane, m, e);
+      if (i < d.n) d.rho[i] = r[m * VEC + e];
+      r2 = fma(r[m * VEC + e], r[m * VEC + e], r2);
+    }
+  r2 = wave_sum(r2);
+  if (lane == 0) {
+    st->R2 = r2;
+    st->n_visits += visits;
+    st->n_rounds += 1;
+    st->dmax2 = fmax(st->dmax2, dmax2);
+    if (stop_k >= 0 && stop_k + 1 < q) {
+      // re-anchor after the listed position where ||D|| passed tau, with a
+      // larger threshold
+      st->resume = stop_k + 1;
+      st->tau = fmax(4.0 * tau, 4.0 * sqrt(dmax2));
+      st->n_stops += 1;
+    } else {
+      // the epoch is complete; the next one starts at position 0 with a
+      // threshold from this epoch's largest residual move
+      const int k = st->k + 1;
+      st->k = k;
+      st->n_epochs += 1;
+      st->resume = 0;
+      const double tn = 2.0 * sqrt(st->dmax2);
+      if (st->first_epoch) st->tau_first = tn;
+      st->first_epoch = 0;
+      st->tau = tn;
+      st->dmax2 = 0.0;
+      if (k % opts.f == 0 || k >= opts.K) st->phase = 0;
+    }
   }
 }
 
@@ -402,6 +659,11 @@ __global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, Wi
 // ---- ordered compaction of the kept indices into `out` (or the other buffer).
 __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st, WideBufs wb,
                                                       int32_t* out);
+// ---- the list of positions a CD round visits exactly: per-tile counts, then
+// the ordered compaction into d.lst (tiles of kTestTile positions from
+// `resume`; tiles past q count zero).
+__global__ __launch_bounds__(256) void k_wide_lcount(ProbDesc d, WideState* st, WideBufs wb);
+__global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st, WideBufs wb);
 // ---- |A'| and buffer swap (path) or q_out (screen()).
 __global__ __launch_bounds__(64) void k_wide_fin(ProbDesc d, WideState* st, WideBufs wb,
                                                  int ntest, int32_t* q_out);

@@ -268,14 +268,47 @@ def test_path_c1_full(torch, orc, cd_mode):
           f"epochs {int(_np(got['epochs']).sum())}")
 
 
+def _wide_case(torch, orc, X, y, T, ratio, label):
+    Xd, yd = _dev(torch, X, y)
+    stats = torch.zeros(len(gs.STAT_NAMES), dtype=torch.int64, device="cuda")
+    got = gs.lasso_path(Xd, yd, T=T, lambda_min_ratio=ratio, schedule="wide", stats=stats)
+    torch.cuda.synchronize()
+    assert got["rc"] == gs.GS_OK
+    lams = _np(got["lambdas"])
+    _check_path(X, y, got, orc, lams, label=label)
+    # the CD rounds are cyclic CD itself: the same epochs and final active
+    # set sizes as the oracle at every lambda
+    o = orc.lasso_path(X, y, lambdas=lams)
+    np.testing.assert_array_equal(_np(got["epochs"]), o["epochs"])
+    np.testing.assert_array_equal(_np(got["nactive"]), o["nactive"])
+    st = dict(zip(gs.STAT_NAMES, stats.cpu().tolist()))
+    assert st["residual_epochs"] == int(o["epochs"].sum())
+    assert st["passes"] == int(o["passes"].sum())
+    print(f"{label}: epochs {int(o['epochs'].sum())}, exact visits {st['wide_visits']}, "
+          f"rounds {st['wide_rounds']}, re-anchors {st['wide_stops']}")
+    return got, o, st
+
+
 def test_path_wide_matches(torch, orc):
-    """The wide schedule (sweeps over all CUs) on a C1-shaped problem."""
+    """The wide schedule (sweeps over all CUs, CD rounds on one wavefront) on
+    a C1-shaped problem."""
     d = synth.c1()
     X, y = d["X"][:, :3000], d["y"]
-    Xd, yd = _dev(torch, X, y)
-    got = gs.lasso_path(Xd, yd, T=30, lambda_min_ratio=1e-2, schedule="wide")
-    torch.cuda.synchronize()
-    _check_path(X, y, got, orc, _np(got["lambdas"]))
+    _wide_case(torch, orc, X, y, 30, 1e-2, "wide c1-shaped")
+
+
+def test_path_wide_c4_shaped(torch, orc):
+    """The wide schedule on the 1000-row block-correlated design of the
+    learned warm start workload at p = 4000, 20 lambdas down to
+    lambda_max / 333: supports of up to 800 coefficients, so the CD rounds
+    visit hundreds of coordinates exactly per epoch, skip the zero ones their
+    anchor bound clears, and re-anchor when the residual moves too far."""
+    d = synth.c4(seed=44, p=4000)
+    got, o, st = _wide_case(torch, orc, d["X"], d["y"], 20, 0.003, "wide c4-shaped")
+    # most of the design is never visited: at most a small multiple of the
+    # supports' visits
+    nnz = (o["beta"] != 0).sum(axis=1)
+    assert st["wide_visits"] < 2 * int((o["epochs"] * np.maximum(nnz, 1)).sum()) + 4000 * 20
 
 
 @pytest.mark.parametrize("cd_mode", ["auto", "residual"])

@@ -7,12 +7,17 @@ from lambda_max to lambda_max/1000, screening every 10 epochs, each lambda
 solved to gap <= 1e-8 ||y||^2, X already resident in device memory.  The
 value is seconds per path (lower is better).
 
-The same run also times the X^T rho sweep (the HBM-bound step of every
-screening pass) on the 1000 x 100000 FP32 design (400 MB, rotated between two
-copies so the 256 MB last-level cache cannot serve it) with HIP events
-recorded by the library on the launch stream, and reports it against the
-8 TB/s HBM peak.  The CPU oracle (plain FP64 C, one thread) is timed on the
-whole path of the same workload.
+The same run also reports, each with its own workload description:
+  * the X^T rho sweep (the HBM-bound step of every screening pass) on the
+    1000 x 100000 FP32 design (400 MB, rotated between two copies so the
+    256 MB last-level cache cannot serve it), timed with HIP events recorded
+    by the library on the launch stream, against the 8 TB/s HBM peak;
+  * the 256-path stability-selection batch (one captured graph) and the
+    512-problem uneven batch (autotuned tiles, p50/p99 latency), each beside
+    a pool of CPU threads running the oracle on a bounded sample;
+  * the whole 100-lambda path of the 1000 x 100000 design (plain warm
+    starts) and the learned warm start against it on the first lambdas;
+  * the oracle (plain FP64 C, one thread) on the whole 72 x 7129 path.
 
 Prints one JSON line.
 """
@@ -77,9 +82,8 @@ def bench_path(gs, torch, synth, steps, warmup):
                 path_launches=path_n, n=X.shape[0], p=X.shape[1], stats=st)
 
 
-def bench_sweep(gs, torch, synth, reps):
+def bench_sweep(gs, torch, d, reps):
     import numpy as np
-    d = synth.c4()
     X, y = d["X"], d["y"]
     n, p = X.shape
     copies = [gs.colmajor_to_device(X) for _ in range(2)]
@@ -116,7 +120,7 @@ def _latency(gs, ts):
                 max_ms=round(float(lat.max()), 3))
 
 
-def bench_c2(gs, torch, synth, reps):
+def bench_c2(gs, torch, synth, reps, cpu_threads=0):
     """256 row subsamples (36 rows) of the c1 design, 100 lambdas each, as one
     graph-captured batch; selection counts on the device."""
     d = synth.c2()
@@ -139,32 +143,96 @@ def bench_c2(gs, torch, synth, reps):
     ok = all(bool((o["status"] == 0).all()) for o in plan.outputs)
     lat = _latency(gs, ts)
     plan.close()
-    return dict(seconds=round(el, 4), paths_per_s=round(B / el, 1), certified=ok, **lat,
-                workload="c2: 256 row subsamples (36 rows) of 72x7129, T=100, ratio 1e-2, "
-                         "one graph-captured batch")
+    out = dict(seconds=round(el, 4), paths_per_s=round(B / el, 1), certified=ok, **lat,
+               workload="c2: 256 row subsamples (36 rows) of 72x7129, T=100, ratio 1e-2, "
+                        "one graph-captured batch")
+    if cpu_threads:
+        import numpy as np
+        import oracle
+        o = oracle.oracle()
+        sample = 32
+
+        def one(b):
+            r = o.lasso_path(X[rows[b]], y[rows[b]], T=T, delta=2.0)
+            return int(r["status"].max())
+
+        wall, res, _ = _pool(one, range(sample), cpu_threads, None)
+        out["cpu"] = dict(value=round(len(res) / wall, 2), unit="paths/s", cores=cpu_threads,
+                          kind="oracle", seconds=round(wall, 3), certified=max(res) == 0,
+                          sample=f"the first {sample} of the 256 paths on a pool of "
+                                 f"{cpu_threads} threads (one path per thread at a time), "
+                                 "FP64 C oracle")
+    return out
 
 
-def bench_c3(gs, torch, synth, tune, max_epochs=1000000):
+def _cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _pool(fn, items, threads, budget_s):
+    """Runs fn over items on a thread pool (the oracle's C calls release the
+    GIL).  With budget_s, no new item starts after that many seconds.
+    Returns (wall seconds, results, per-item completion times)."""
+    import concurrent.futures as cf
+    import threading
+    t0 = time.perf_counter()
+    lock = threading.Lock()
+    done = []
+    it = iter(items)
+
+    def worker():
+        out = []
+        while True:
+            with lock:
+                if budget_s is not None and time.perf_counter() - t0 > budget_s:
+                    return out
+                try:
+                    x = next(it)
+                except StopIteration:
+                    return out
+            r = fn(x)
+            out.append((r, time.perf_counter() - t0))
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        futs = [ex.submit(worker) for _ in range(threads)]
+        for f in futs:
+            done.extend(f.result())
+    wall = time.perf_counter() - t0
+    return wall, [r for r, _ in done], [t for _, t in done]
+
+
+def bench_c3(gs, torch, synth, tune, cpu_threads=0, cpu_budget=20.0, max_epochs=1000000):
     """512 independent problems of uneven n, p (one lambda each, cold start).
     The epoch budget is raised above the default 100000: one problem of the
     set (n = 88, p = 9918, lambda = 0.0103 lambda_max) needs 146,700 epochs
     from its cold start, in the oracle as on the device."""
+    import concurrent.futures as cf
+
     import numpy as np
     params = synth.c3_params()
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max(1, cpu_threads or 8)) as ex:
+        host = list(ex.map(lambda pr: synth.c3_problem(pr), params))
+    _log(f"c3: {len(host)} problems drawn in {time.perf_counter() - t0:.1f} s")
     probs, keep = [], []
-    for i, pr in enumerate(params):
-        d = synth.c3_problem(pr)
+    for d in host:
         Xd = gs.colmajor_to_device(d["X"])
         yd = torch.from_numpy(d["y"]).cuda()
         keep.append((Xd, yd))
         probs.append(dict(X=Xd, y=yd, T=1, lambdas=[d["lambda_ratio"]], relative=True))
-        if (i + 1) % 64 == 0:
-            _log(f"c3: {i + 1} problems drawn and uploaded")
     _log(f"c3: {len(probs)} problems uploaded")
     tiles = None
     if tune:
-        ch = gs.autotune(probs, max_lambdas=1, sample=2, max_epochs=max_epochs)
+        t0 = time.perf_counter()
+        # candidates are timed on at most 2000 epochs of each sampled problem:
+        # enough to rank the layouts, without solving the slowest problems
+        ch = gs.autotune(probs, max_lambdas=1, sample=2, max_epochs=2000)
         tiles = sorted(set(ch))
+        _log(f"c3: autotuned in {time.perf_counter() - t0:.1f} s: {len(tiles)} tile choices")
     B = len(probs)
     ts = torch.zeros(2 * B, dtype=torch.int64, device="cuda")
     t0 = time.perf_counter()
@@ -181,24 +249,49 @@ def bench_c3(gs, torch, synth, tune, max_epochs=1000000):
     bad = [dict(n=params[b]["n"], p=params[b]["p"], rho=round(params[b]["rho"], 3),
                 lambda_ratio=round(params[b]["lambda_ratio"], 4), status=int(st[b]),
                 epochs=int(ep[b])) for b in np.flatnonzero(st != 0)[:8]]
-    return dict(seconds=round(el, 4), certified=ok, tiles=tiles, **_latency(gs, ts),
-                status_counts={str(k): int((st == k).sum()) for k in np.unique(st)},
-                epochs_median=int(np.median(ep)), epochs_max=int(ep.max()), not_certified=bad,
-                max_epochs=max_epochs,
-                workload="c3: 512 problems, n log-U[50,2000], p log-U[1000,50000], "
-                         "lambda/lambda_max U[0.01,0.5]")
+    out = dict(seconds=round(el, 4), problems_per_s=round(B / el, 2), certified=ok, tiles=tiles,
+               **_latency(gs, ts),
+               status_counts={str(k): int((st == k).sum()) for k in np.unique(st)},
+               epochs_median=int(np.median(ep)), epochs_max=int(ep.max()), not_certified=bad,
+               max_epochs=max_epochs,
+               workload="c3: 512 problems, n log-U[50,2000], p log-U[1000,50000], "
+                        "lambda/lambda_max U[0.01,0.5], one lambda each from a cold start, "
+                        "autotuned tiles, one batched launch per tile class")
+    if cpu_threads:
+        import oracle
+        o = oracle.oracle()
+        order = np.random.default_rng(3).permutation(B)
+
+        def one(b):
+            d = host[b]
+            t = time.perf_counter()
+            r = o.lasso_path(d["X"], d["y"], lambdas=[d["lambda_ratio"]], relative=True,
+                             K=max_epochs)
+            return int(r["status"][0]), time.perf_counter() - t
+
+        wall, res, fin = _pool(one, order, cpu_threads, cpu_budget)
+        solve = np.array([t for _, t in res])
+        out["cpu"] = dict(value=round(len(res) / wall, 2), unit="problems/s", cores=cpu_threads,
+                          kind="oracle", problems=len(res), seconds=round(wall, 3),
+                          certified=all(s_ == 0 for s_, _ in res),
+                          solve_p50_ms=round(float(np.percentile(solve, 50)) * 1e3, 3),
+                          solve_p99_ms=round(float(np.percentile(solve, 99)) * 1e3, 3),
+                          sample=f"a pool of {cpu_threads} threads over the 512 problems in a "
+                                 f"seeded random order, no new problem started after "
+                                 f"{cpu_budget:g} s: {len(res)} problems solved, FP64 C oracle")
+    return out
 
 
-def bench_c4(gs, torch, synth, params_file, piece, nl, seed=4):
-    """Learned against plain warm starts on the C4 workload (1000 x 100000
-    FP32, blocks of 50 columns with correlation 0.7, the grid of 100 lambdas
-    down to lambda_max/1000, every lambda to gap <= 1e-8 ||y||^2), over the
-    first `nl` lambdas of the grid.  Both paths run in pieces of `piece`
-    lambdas (each piece warm-started from the previous one's last solution)
-    so that progress shows; the learned time includes the block correlations,
+def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
+    """The C4 workload (1000 x 100000 FP32, blocks of 50 columns with
+    correlation 0.7, the grid of 100 lambdas down to lambda_max/1000, every
+    lambda to gap <= 1e-8 ||y||^2): the plain path over the first `nl_plain`
+    lambdas (the whole grid by default) and the learned warm start over the
+    first `nl_learned`, compared on those.  Both run in pieces of `piece`
+    lambdas (each warm-started from the previous piece's last solution) so
+    that progress shows; the learned time includes the block correlations,
     features, inference and the extra gap checks."""
     import numpy as np
-    d = synth.c4(seed=seed)
     Xd = gs.colmajor_to_device(d["X"])
     yd = torch.from_numpy(d["y"]).cuda()
     yy = float((d["y"].astype(np.float64) ** 2).sum())
@@ -206,10 +299,13 @@ def bench_c4(gs, torch, synth, params_file, piece, nl, seed=4):
     P = None
     if params_file:
         P = torch.from_numpy(np.load(params_file).astype(np.float32)).cuda()
+    stats = torch.zeros(len(gs.STAT_NAMES), dtype=torch.int64, device="cuda")
 
-    def run(name, learned):
-        prev, ws, res = None, None, []
+    def run(name, learned, nl):
+        prev, ws, res, marks = None, None, [], []
         torch.cuda.synchronize()
+        stats.zero_()
+        gs.timing_reset()
         t0 = time.perf_counter()
         for k in range(0, nl, piece):
             sub = rel[k:min(k + piece, nl)]
@@ -218,35 +314,53 @@ def bench_c4(gs, torch, synth, params_file, piece, nl, seed=4):
                                           beta_init=prev, workspace=ws)
             else:
                 r = gs.lasso_path(Xd, yd, lambdas=sub, relative=True, beta_init=prev,
-                                  workspace=ws)
+                                  workspace=ws, stats=stats)
             ws = r["workspace"]
             prev = r["beta"][-1].contiguous()
             ep = r["epochs"].cpu().numpy()
             res.append(r)
+            marks.append(time.perf_counter() - t0)
             _log(f"c4 {name}: lambdas {k}..{k + len(sub) - 1} epochs {int(ep.sum())} "
-                 f"at {time.perf_counter() - t0:.1f} s")
+                 f"at {marks[-1]:.1f} s")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         cat = lambda key: np.concatenate([x[key].cpu().numpy() for x in res])
         st, gap, ep = cat("status"), cat("gap"), cat("epochs")
         out = dict(seconds=round(el, 3), epochs=int(ep.sum()),
                    certified=bool((st == 0).all() and (gap <= 1e-8 * yy).all()),
-                   epochs_per_lambda=[int(e) for e in ep])
+                   epochs_per_lambda=[int(e) for e in ep],
+                   seconds_at_piece_end=[round(m, 3) for m in marks])
         if learned:
             fl = cat("learned")
             out["network_start_fraction"] = round(float(fl[1:].mean()), 3)
             out["network_start_lambdas"] = int(fl.sum())
+        else:
+            sv = dict(zip(gs.STAT_NAMES, stats.cpu().tolist()))
+            cd_ms, cd_n = gs.timing_query("cd")
+            out["cd"] = dict(kernel="k_wide_walk", bound="latency", passes=sv["passes"],
+                             exact_visits=sv["wide_visits"], rounds=sv["wide_rounds"],
+                             reanchors=sv["wide_stops"], walk_ms=round(cd_ms, 1),
+                             us_per_visit=round(cd_ms * 1e3 / max(sv["wide_visits"], 1), 4))
         return out
 
-    plain = run("plain", False)
+    plain = run("plain", False, nl_plain)
     res = {"workload": "c4: n=1000 p=100000 FP32, 2000 blocks of 50 columns with "
-                       "correlation 0.7, 50-sparse truth, SNR 5, seed %d; lambdas 0..%d of "
-                       "the T=100 grid lambda_max..lambda_max/1000 (down to lambda_max/%.0f), "
-                       "eps=1e-8||y||^2" % (seed, nl - 1, 1.0 / rel[nl - 1]),
-           "piece": piece, "lambdas": nl, "plain": plain}
-    if P is not None:
-        res["learned"] = run("learned", True)
+                       "correlation 0.7, 50-sparse truth, SNR 5, seed %d; lambdas of the "
+                       "T=100 grid lambda_max..lambda_max/1000, eps=1e-8||y||^2; plain path "
+                       "over lambdas 0..%d, learned start over lambdas 0..%d" %
+                       (seed, nl_plain - 1, nl_learned - 1),
+           "piece": piece, "plain_lambdas": nl_plain, "learned_lambdas": nl_learned,
+           "plain": plain}
+    if P is not None and nl_learned > 0:
+        lr = run("learned", True, nl_learned)
+        res["learned"] = lr
         res["params"] = os.path.relpath(params_file, ROOT)
+        # the plain path's time and epochs over the same lambdas
+        npc = (nl_learned + piece - 1) // piece
+        if nl_learned % piece == 0 and npc <= len(plain["seconds_at_piece_end"]):
+            res["plain_same_lambdas"] = dict(
+                seconds=plain["seconds_at_piece_end"][npc - 1],
+                epochs=int(sum(plain["epochs_per_lambda"][:nl_learned])))
     return res
 
 
@@ -286,16 +400,19 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-path", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
-    ap.add_argument("--c3", action="store_true", help="also run the 512-problem uneven batch")
-    ap.add_argument("--tune", action="store_true", help="autotune tiles before the c3 batch")
-    ap.add_argument("--c4", action="store_true",
-                    help="also compare learned and plain warm starts on the c4 path")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 512-problem uneven batch")
+    ap.add_argument("--no-tune", action="store_true", help="no autotuning before the c3 batch")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the 1000 x 100000 path and the learned warm start")
     ap.add_argument("--c4-params", default=os.path.join(ROOT, "paper_1505_03410_amd",
                                                         "warm_mlp.npy"))
-    ap.add_argument("--c4-piece", type=int, default=5)
-    ap.add_argument("--c4-lambdas", type=int, default=60,
-                    help="lambdas of the 100-point c4 grid to solve (the tail beyond 60 "
-                         "takes tens of minutes per path)")
+    ap.add_argument("--c4-piece", type=int, default=10)
+    ap.add_argument("--c4-lambdas", type=int, default=100,
+                    help="lambdas of the 100-point c4 grid solved by the plain path")
+    ap.add_argument("--c4-learned-lambdas", type=int, default=70,
+                    help="lambdas solved by the learned warm start (0: none)")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of the c3 CPU pool sample")
     ap.add_argument("--copy-mb", type=float, default=0.0,
                     help="only run a plain device copy of this many MB (counter calibration)")
     a = ap.parse_args()
@@ -324,30 +441,34 @@ def main():
         _log(f"path: {path['seconds']:.4f} s/path, ok={path['ok']}")
     roof = None
     sweep = None
+    d4 = None
+    if not a.no_sweep or not a.no_c4:
+        d4 = synth.c4()
     if not a.no_sweep:
         _log("sweep: c4 1000x100000 FP32 (400 MB), two rotating copies")
-        sweep = bench_sweep(gs, torch, synth, a.sweep_reps)
+        sweep = bench_sweep(gs, torch, d4, a.sweep_reps)
         _log(f"sweep: {sweep['avg_us']:.1f} us, {sweep['gbs']:.0f} GB/s")
         roof = {"bound": "hbm", "kernel": "k_wide_sweep<float,4,4,true>",
                 "achieved": round(sweep["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(sweep["gbs"] / HBM_PEAK_GBS, 4), "traffic": sweep_traffic(),
                 "bytes_per_launch": sweep["bytes"], "avg_us": round(sweep["avg_us"], 2),
                 "launches": sweep["launches"], "workload": "1000x100000 FP32 full sweep"}
+    threads = 0 if a.no_cpu else _cpu_threads()
     c2 = None
-    if not a.no_c2 and path is not None:
+    if not a.no_c2:
         _log("c2: 256 row subsamples, graph-captured batch")
-        c2 = bench_c2(gs, torch, synth, 3)
+        c2 = bench_c2(gs, torch, synth, 3, threads)
         _log(f"c2: {c2['seconds']:.3f} s, {c2['paths_per_s']} paths/s, p99 {c2['p99_ms']} ms")
     c3 = None
-    if a.c3:
+    if not a.no_c3:
         _log("c3: 512 uneven problems")
-        c3 = bench_c3(gs, torch, synth, a.tune)
+        c3 = bench_c3(gs, torch, synth, not a.no_tune, threads, a.cpu_budget)
         _log(f"c3: {c3['seconds']:.3f} s, p50 {c3['p50_ms']} ms, p99 {c3['p99_ms']} ms")
     c4 = None
-    if a.c4:
-        _log("c4: learned vs plain warm starts, 1000x100000, 100 lambdas")
+    if not a.no_c4:
+        _log("c4: 1000x100000 path, plain and learned warm starts")
         pf = a.c4_params if a.c4_params and os.path.exists(a.c4_params) else None
-        c4 = bench_c4(gs, torch, synth, pf, a.c4_piece, a.c4_lambdas)
+        c4 = bench_c4(gs, torch, d4, pf, a.c4_piece, a.c4_lambdas, a.c4_learned_lambdas)
     cpu = None
     if not a.no_cpu:
         _log("cpu baseline: oracle, whole c1 path")
@@ -360,7 +481,8 @@ def main():
                           "learned_warm_start": c4}), flush=True)
         return
     line = {
-        "metric": "Lasso path seconds to gap<=1e-8||y||^2 (c1 72x7129); X^T theta HBM GB/s",
+        "metric": "Lasso path seconds to gap\u22641e-8\u2016y\u2016\u00b2; X\u1d40\u03b8 HBM GB/s; "
+                  "learned vs plain warm start",
         "value": round(path["seconds"], 5),
         "unit": "s",
         "n_gpus": 1,
@@ -370,12 +492,14 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "c1: lasso path, n=72 p=7129 FP32 X, AR(1) rho=0.5, "
                                "T=100 lambda_max..lambda_max/1000, f=10, eps=1e-8||y||^2",
                    "n": path["n"], "p": path["p"], "T": 100, "lambda_min_ratio": 1e-3,
-                   "screen_every": 10, "eps_rel": 1e-8, "parallelism": "single problem, one wavefront"},
+                   "screen_every": 10, "eps_rel": 1e-8, "parallelism": "single problem, one wavefront",
+                   "arithmetic": "FP32 X, Gram block and pattern-mode updates; FP64 residual, "
+                                 "coefficients, reductions, gap and radius"},
         "certified": path["ok"],
         "path_kernel": {"kernel": "k_path_narrow", "bound": "latency",
                         "avg_ms": round(path["path_ms"], 3), "launches": path["path_launches"],

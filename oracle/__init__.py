@@ -48,14 +48,16 @@ def _declare(lib):
                             _dp, _dp, ctypes.c_double, _dp, _dp]
     lib.orc_gap.restype = ctypes.c_double
     lib.orc_screen.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp,
-                               _dp, _dp, ctypes.c_double, _ip, ctypes.c_int, _dp,
-                               _bp, _bp, _dp]
+                               _dp, _dp, ctypes.c_double, _ip, ctypes.c_int,
+                               ctypes.c_int, _dp, _bp, _bp, _dp]
     lib.orc_screen.restype = ctypes.c_int
     lib.orc_lasso_path.argtypes = [
         ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _dp, ctypes.c_int, _dp,
         ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-        ctypes.c_int, _dp, _dp, _dp, _ip, _ip, _ip, _ip, _bp, _dp]
+        ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _ip, _ip, _ip, _ip, _bp, _dp]
     lib.orc_lasso_path.restype = ctypes.c_int
+    lib.orc_dome_mu.argtypes = [ctypes.c_double] * 7
+    lib.orc_dome_mu.restype = ctypes.c_double
     return lib
 
 
@@ -119,7 +121,9 @@ class Oracle:
                              lam, ctypes.byref(P), ctypes.byref(D))
         return g, P.value, D.value
 
-    def screen(self, X, y, beta, lam, active=None):
+    RULES = {"sphere": 0, "dome": 1}
+
+    def screen(self, X, y, beta, lam, active=None, rule="sphere"):
         Xf, n, p = _design(X)
         y = np.ascontiguousarray(y, dtype=np.float64)
         beta = np.ascontiguousarray(beta, dtype=np.float64)
@@ -130,8 +134,8 @@ class Oracle:
         ks = np.zeros(max(q, 1), dtype=np.uint8)
         sc = np.empty(10)
         rc = self.lib.orc_screen(n, p, n, _ptr(Xf), _ptr(y), _ptr(beta), lam,
-                                 _ptr(act, _ip), q, _ptr(c), _ptr(ke, _bp),
-                                 _ptr(ks, _bp), _ptr(sc))
+                                 _ptr(act, _ip), q, self.RULES[rule], _ptr(c),
+                                 _ptr(ke, _bp), _ptr(ks, _bp), _ptr(sc))
         if rc < 0:
             raise ValueError(f"orc_screen: {rc}")
         idx = np.arange(p, dtype=np.int32) if act is None else act
@@ -140,9 +144,14 @@ class Oracle:
                     radius=sc[2], radius_inflated=sc[3], M=sc[4], rho_norm2=sc[5],
                     y_rho=sc[6], l1=sc[7], alpha_safe=sc[8], err_gap=sc[9])
 
+    def dome_mu(self, xty, c, xn, alpha, lam, R_hat, r_check2):
+        """mu_D(x_j) of the GAP SAFE dome (exact formula) for one column."""
+        return self.lib.orc_dome_mu(float(xty), float(c), float(xn), float(alpha), float(lam),
+                                    float(R_hat), float(r_check2))
+
     def lasso_path(self, X, y, T=100, lambdas=None, relative=False, delta=3.0,
                    eps_rel=1e-8, f=10, K=100000, beta_init=None,
-                   want_screened=False):
+                   want_screened=False, rule="sphere"):
         Xf, n, p = _design(X)
         y = np.ascontiguousarray(y, dtype=np.float64)
         lam_in = None
@@ -160,7 +169,7 @@ class Oracle:
         lam_out = np.zeros(T)
         rc = self.lib.orc_lasso_path(
             n, p, n, _ptr(Xf), _ptr(y), T, _ptr(lam_in), int(bool(relative)),
-            float(delta), float(eps_rel), int(f), int(K), _ptr(b0), _ptr(beta),
+            float(delta), float(eps_rel), int(f), int(K), self.RULES[rule], _ptr(b0), _ptr(beta),
             _ptr(gap), _ptr(ep, _ip), _ptr(na, _ip), _ptr(st, _ip), _ptr(ps, _ip),
             _ptr(scr, _bp), _ptr(lam_out))
         if rc < 0:

@@ -41,6 +41,14 @@
  *   R13 after K epochs without certification one last gap is evaluated for the
  *       returned beta and status is set to "not converged".
  *   R14 coordinates are visited in ascending index order (cyclic CD).
+ *   R15 GAP SAFE dome (Sec. 3.2, appendix "Dome test"): the normal is
+ *       w = (y/lambda - theta) / R_hat and the ratio alpha_d =
+ *       2 (r_check[beta] / R_hat)^2 - 1 with r_check taken at the primal
+ *       point beta (the main text's normal has the opposite sign and the
+ *       appendix writes r_check[theta]; with those the dome would not contain
+ *       the dual optimum).  A coordinate is kept when either test keeps it
+ *       (the dome lies inside the sphere, so with exact arithmetic the dome
+ *       alone decides).
  */
 #include <math.h>
 #include <stddef.h>
@@ -159,6 +167,77 @@ static void residual(int n, int p, int64_t ldx, const double* X, const double* y
     }
 }
 
+/* Support function of the dome D(c, r, a, w) = B(c, r) n {t: w^T (t - c) <= -a r}
+ * (Sec. 3.2 dome tests; appendix "Dome test") at a vector x, given
+ * cx = c^T x, wx = w^T x and xn = ||x||:  the ball's maximizer c + r x/||x||
+ * lies in the half-space iff w^T x <= -a ||x||; otherwise the maximum is on
+ * the circle where the plane cuts the sphere. */
+static double dome_support(double cx, double wx, double xn, double r, double a) {
+  if (wx <= -a * xn) return cx + r * xn;
+  double s2 = (xn * xn - wx * wx) * (1.0 - a * a);
+  return cx - r * a * wx + r * sqrt(s2 > 0.0 ? s2 : 0.0);
+}
+
+/* Dome parameters of one pass (R15), in terms of the pass scalars:
+ *   R_hat^2   = ||alpha rho - y/lambda||^2 = alpha^2 R2 - 2 alpha Ry / lambda + yy / lambda^2
+ *   r_check^2 = (yy - ||rho||^2 - 2 lambda l1)_+ / lambda^2       (Theorem 2)
+ * center c = (y/lambda + theta)/2, radius R_hat/2, ratio 2 r_check^2/R_hat^2 - 1,
+ * normal (y/lambda - theta)/R_hat.  For x_j:  c^T x_j = (x_j^T y/lambda +
+ * alpha c_j)/2 and w^T x_j = (x_j^T y/lambda - alpha c_j)/R_hat, so the test
+ * needs X^T y (computed once) and c_j: no further pass over X. */
+double orc_dome_mu(double xty, double cj, double xn, double alpha, double lambda,
+                   double Rh, double rc2);
+static int dome_keep_exact(double xty, double cj, double xn, double alpha,
+                           double lambda, double Rh, double rc2) {
+  if (!(xn > 0.0)) return 0;
+  if (!(Rh > 0.0)) return 1; /* theta = y/lambda: the dome is a point; no decision here */
+  return orc_dome_mu(xty, cj, xn, alpha, lambda, Rh, rc2) >= 1.0;
+}
+
+/* mu_C(x_j) = max(sigma_C(x_j), sigma_C(-x_j)) of the GAP SAFE dome (exact
+ * formula; exported for the tests). */
+double orc_dome_mu(double xty, double cj, double xn, double alpha, double lambda,
+                   double Rh, double rc2) {
+  double r = 0.5 * Rh, a = 2.0 * rc2 / (Rh * Rh) - 1.0;
+  double cx = 0.5 * (xty / lambda + alpha * cj);
+  double wx = (xty / lambda - alpha * cj) / Rh;
+  double mu_p = dome_support(cx, wx, xn, r, a);
+  double mu_m = dome_support(-cx, -wx, xn, r, a);
+  return mu_p > mu_m ? mu_p : mu_m;
+}
+
+/* The same test made safe for the rounding of its inputs (R11, R15): every
+ * input is replaced by the bound that enlarges the dome (a larger ball, the
+ * cutting plane moved outwards: r_check down, R_hat up), w^T x by a lower
+ * bound (the support function does not increase with w^T x), c^T x by an
+ * upper bound and ||x|| by an upper bound; a final margin covers the
+ * evaluation itself.  e_cx, e_wn bound the errors of c^T x and of the
+ * numerator x^T y/lambda - alpha c_j; Rlo, Rhi bracket R_hat; rc2lo is a
+ * lower bound of r_check^2. */
+static int dome_keep_safe(double xty, double cj, double xn_up, double alpha,
+                          double lambda, double Rlo, double Rhi, double rc2lo,
+                          double e_cx, double e_wn) {
+  if (!(xn_up > 0.0)) return 0;
+  if (!(Rhi > 0.0)) return 1;
+  double r = 0.5 * Rhi;
+  double a = 2.0 * rc2lo / (Rhi * Rhi) - 1.0;
+  if (a < -1.0) a = -1.0;
+  double cx = 0.5 * (xty / lambda + alpha * cj);
+  double num = xty / lambda - alpha * cj;
+  double mu = -INFINITY;
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    double cs = sgn * cx + e_cx;               /* upper bound of c^T (sgn x) */
+    double ns = sgn * num - e_wn;              /* lower bound of the numerator */
+    double wlo;                                /* lower bound of w^T (sgn x)  */
+    if (ns >= 0.0) wlo = ns / Rhi;
+    else wlo = (Rlo > 0.0) ? ns / Rlo : -INFINITY;
+    double m = (wlo == -INFINITY) ? cs + r * xn_up : dome_support(cs, wlo, xn_up, r, a);
+    if (m > mu) mu = m;
+  }
+  double scale = fabs(cx) + r * xn_up * 3.0 + 1.0;
+  return mu >= 1.0 - 16.0 * ORC_U * scale;
+}
+
 /* One screening pass at (beta, lambda) over the active set A (q entries):
  *   c_j = x_j^T rho for j in A,  M = max |c_j|           (Sec. 4.1)
  *   alpha = min(max(y^T rho / (lambda ||rho||^2), -1/M), 1/M)   (Sec. 2.3)
@@ -170,6 +249,7 @@ static void residual(int n, int p, int64_t ldx, const double* X, const double* y
  * rho (n) must hold y - X beta on entry (caller refreshes it). */
 static void pass_on_residual(int n, int64_t ldx, const double* X, const double* y,
                              const double* beta, const double* nrm2,
+                             const double* xty, int rule,
                              const int32_t* A, int q, int nnz, double lambda,
                              const double* rho, double* c_out,
                              uint8_t* keep_exact, uint8_t* keep_safe,
@@ -241,6 +321,25 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
   double radius = sqrt(2.0 * (G > 0.0 ? G : 0.0)) / lambda;
   double radius_s = sqrt(2.0 * Gp) / lambda * (1.0 + 4.0 * ORC_U);
 
+  /* GAP SAFE dome (R15): exact parameters at (beta, alpha rho) and bounds
+   * for the safe test at (beta, alpha_s rho). */
+  double yy = col_dot(n, y, y);
+  double Rh2 = alpha * alpha * R2 - 2.0 * alpha * Ry / lambda + yy / (lambda * lambda);
+  double Rh = sqrt(Rh2 > 0.0 ? Rh2 : 0.0);
+  double rc2 = (yy - R2 - 2.0 * lambda * l1) / (lambda * lambda);
+  if (rc2 < 0.0) rc2 = 0.0;
+  double Rs2 = alpha_s * alpha_s * R2 - 2.0 * alpha_s * Ry / lambda + yy / (lambda * lambda);
+  double eR2 = gamma_m(n + 6) * (alpha_s * alpha_s * R2 + 2.0 * fabs(alpha_s * Ry) / lambda +
+                                 yy / (lambda * lambda)) +
+               2.0 * fabs(alpha_s) / lambda * gamma_m(n) * yn * rnorm;
+  double Rhi = sqrt(Rs2 + eR2 > 0.0 ? Rs2 + eR2 : 0.0) * (1.0 + 4.0 * ORC_U);
+  double Rlo = sqrt(Rs2 - eR2 > 0.0 ? Rs2 - eR2 : 0.0) * (1.0 - 4.0 * ORC_U);
+  double rt = rnorm + d_rho; /* bounds ||y - X beta|| */
+  double rc2lo = (yy * (1.0 - gamma_m(n + 2)) - rt * rt * (1.0 + 4.0 * ORC_U) -
+                  2.0 * lambda * l1 * (1.0 + gamma_m(q + 2))) /
+                 (lambda * lambda) * (1.0 - 4.0 * ORC_U);
+  if (rc2lo < 0.0) rc2lo = 0.0;
+
   for (int k = 0; k < q; ++k) {
     int j = A[k];
     double xn = sqrt(nrm2[j]);
@@ -250,6 +349,18 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
     double mu_s = fabs(alpha_s * c_out[k]) + fabs(alpha_s) * e_c * xn_up +
                   radius_s * xn_up;
     keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.0 - 4.0 * ORC_U) ? 1 : 0;
+    if (rule == 1) {
+      keep_exact[k] = keep_exact[k] && dome_keep_exact(xty[j], c_out[k], xn, alpha, lambda,
+                                                        Rh, rc2);
+      /* errors of x_j^T y / lambda and of alpha_s c_j */
+      double e_y = gamma_m(n + 1) * xn_up * yn / lambda;
+      double e_ac = fabs(alpha_s) * e_c * xn_up;
+      double t1 = fabs(xty[j] / lambda), t2 = fabs(alpha_s * c_out[k]);
+      double e_cx = 0.5 * (e_y + e_ac) + 4.0 * ORC_U * (t1 + t2);
+      double e_wn = e_y + e_ac + 4.0 * ORC_U * (t1 + t2);
+      keep_safe[k] = keep_safe[k] && dome_keep_safe(xty[j], c_out[k], xn_up, alpha_s, lambda,
+                                                      Rlo, Rhi, rc2lo, e_cx, e_wn);
+    }
   }
   info->gap = G;
   info->alpha = alpha;
@@ -268,27 +379,29 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
  *   c_out, keep_exact, keep_safe; plus scalars.  Returns q_in or <0. */
 int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
                const double* beta, double lambda, const int32_t* active_in,
-               int q_in, double* c_out, uint8_t* keep_exact,
+               int q_in, int rule, double* c_out, uint8_t* keep_exact,
                uint8_t* keep_safe, double* scalars /* 10: see orc_pass_info */) {
   if (n <= 0 || p <= 0 || ldx < n || !(lambda > 0.0)) return ORC_EINVAL;
   int q = active_in ? q_in : p;
   int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)(q > 0 ? q : 1));
   double* rho = (double*)malloc(sizeof(double) * (size_t)n);
   double* nrm2 = (double*)malloc(sizeof(double) * (size_t)p);
-  if (!A || !rho || !nrm2) {
-    free(A); free(rho); free(nrm2);
+  double* xty = (double*)malloc(sizeof(double) * (size_t)p);
+  if (!A || !rho || !nrm2 || !xty) {
+    free(A); free(rho); free(nrm2); free(xty);
     return ORC_ENOMEM;
   }
   for (int k = 0; k < q; ++k) A[k] = active_in ? active_in[k] : k;
   for (int j = 0; j < p; ++j) {
     const double* xj = X + (int64_t)j * ldx;
     nrm2[j] = col_dot(n, xj, xj);
+    xty[j] = col_dot(n, xj, y);
   }
   int nnz = 0;
   for (int j = 0; j < p; ++j) nnz += beta[j] != 0.0;
   residual(n, p, ldx, X, y, beta, rho);
   orc_pass_info info;
-  pass_on_residual(n, ldx, X, y, beta, nrm2, A, q, nnz, lambda, rho, c_out,
+  pass_on_residual(n, ldx, X, y, beta, nrm2, xty, rule, A, q, nnz, lambda, rho, c_out,
                    keep_exact, keep_safe, &info);
   scalars[0] = info.gap;
   scalars[1] = info.alpha;
@@ -300,7 +413,7 @@ int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
   scalars[7] = info.l1;
   scalars[8] = info.alpha_s;
   scalars[9] = info.err_gap;
-  free(A); free(rho); free(nrm2);
+  free(A); free(rho); free(nrm2); free(xty);
   return q;
 }
 
@@ -320,13 +433,13 @@ int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
  * Returns 0, ORC_NOT_CONVERGED if some lambda hit K epochs, or < 0. */
 int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
                    int T, const double* lambdas, int lambda_relative,
-                   double delta, double eps_rel, int f, int K,
+                   double delta, double eps_rel, int f, int K, int rule,
                    const double* beta_init, double* beta_out, double* gap_out,
                    int32_t* epochs_out, int32_t* nactive_out,
                    int32_t* status_out, int32_t* passes_out, uint8_t* screened,
                    double* lambdas_out) {
   if (n <= 0 || p <= 0 || ldx < n || T <= 0 || f < 1 || K < 0 ||
-      !(eps_rel > 0.0))
+      !(eps_rel > 0.0) || rule < 0 || rule > 1)
     return ORC_EINVAL;
   double *nrm2 = malloc(sizeof(double) * p), *xty = malloc(sizeof(double) * p);
   double *rho = malloc(sizeof(double) * n), *beta = malloc(sizeof(double) * p);
@@ -375,7 +488,7 @@ int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
         for (int j = 0; j < p; ++j) nnz += beta[j] != 0.0;
         residual(n, p, ldx, X, y, beta, rho);
         orc_pass_info info;
-        pass_on_residual(n, ldx, X, y, beta, nrm2, A, q, nnz, lambda, rho, c,
+        pass_on_residual(n, ldx, X, y, beta, nrm2, xty, rule, A, q, nnz, lambda, rho, c,
                          ke, ks, &info);
         ++passes;
         G = info.gap;

@@ -39,6 +39,10 @@ MUTANTS = {
     "lambda_max_not_abs": ("if (fabs(xty[j]) > lmax) lmax = fabs(xty[j]);",
                            "if (xty[j] > lmax) lmax = xty[j];"),
     "gap_bound_drops_y_rho_error": ("                lambda * fabs(alpha_s) * gamma_m(n) * yn * rnorm +\n", ""),
+    "dome_normal_flipped": ("  double wx = (xty / lambda - alpha * cj) / Rh;\n  double mu_p",
+                            "  double wx = (alpha * cj - xty / lambda) / Rh;\n  double mu_p"),
+    "dome_drops_ratio_factor": ("double s2 = (xn * xn - wx * wx) * (1.0 - a * a);",
+                                "double s2 = (xn * xn - wx * wx);"),
     "screen_drops_zero_test": ("keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.0 - 4.0 * ORC_U) ? 1 : 0;",
                                "keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.5) ? 1 : 0;"),
 }
@@ -62,6 +66,8 @@ checks = [
   lambda: T.test_kkt_at_tight_solution(orc, "c0"),
   lambda: T.test_safety_invariant(orc),
   lambda: T.test_rounding_bound_covers_cancelling_y_rho(orc),
+  lambda: T.test_dome_support_matches_brute_force(orc),
+  lambda: T.test_dome_contains_dual_optimum_and_lies_in_sphere(orc),
 ]
 failed = 0
 for c in checks:          # one failing pin is enough

@@ -418,3 +418,123 @@ def test_all_zero_design(orc):
     s = orc.screen(X, y, np.zeros(9), 0.1)
     assert not s["keep_safe"].any()
     assert abs(s["gap"]) <= 1e-12 * (y @ y)
+
+
+# ------------------------------------------------------------ GAP SAFE dome
+
+def _dome_geometry(X, y, beta, lam, alpha):
+    """Center, radius, ratio and normal of the GAP SAFE dome (Sec. 3.2,
+    appendix "Dome test") at (beta, theta = alpha rho), from the definitions
+    (numpy, not the oracle's formulas): c = (y/lambda + theta)/2,
+    r = R_hat/2, a = 2 (r_check[beta]/R_hat)^2 - 1, w = (y/lambda - theta)/R_hat."""
+    rho = y - X @ beta
+    theta = alpha * rho
+    R = np.linalg.norm(theta - y / lam)
+    rc2 = max(y @ y - rho @ rho - 2 * lam * np.abs(beta).sum(), 0.0) / lam ** 2
+    return (y / lam + theta) / 2, R / 2, 2 * rc2 / R ** 2 - 1, (y / lam - theta) / R, R, rc2
+
+
+def _dome_iterates(orc, seed):
+    X, y = _small_c1_like(seed=seed, n=12, p=30)
+    lmax = np.abs(X.T @ y).max()
+    lam = 0.2 * lmax
+    out = []
+    for K in (1, 3, 8, 20):
+        b = orc.lasso_path(X, y, lambdas=[lam], K=K, eps_rel=1e-30)["beta"][0]
+        out.append((X, y, b, lam))
+    return out
+
+
+def _dome_max_brute(x, c, r, a, w, m=400001):
+    """max of x^T t over the dome by brute force: t = c + u w + v e with e the
+    unit direction of x's part orthogonal to w (any component of t - c
+    outside span{w, x} leaves x^T t unchanged and only uses up radius, so the
+    maximum lies in that plane); the maximum of a linear function over the
+    cut disk lies on its boundary, which is sampled densely: the arc of the
+    circle of radius r with u <= -a r, and the chord u = -a r."""
+    xw = x @ w
+    xo = np.linalg.norm(x - xw * w)
+    ph = np.linspace(0.0, 2.0 * np.pi, m)
+    u, v = r * np.cos(ph), r * np.sin(ph)
+    arc = np.where(u <= -a * r, u * xw + v * xo, -np.inf).max()
+    half = r * np.sqrt(max(1.0 - a * a, 0.0))
+    vc = np.linspace(-half, half, m)
+    chord = (-a * r * xw + vc * xo).max()
+    return c @ x + max(arc, chord)
+
+
+def test_dome_support_matches_brute_force(orc):
+    """The closed-form support function of the dome (appendix, "Dome test")
+    equals a brute-force maximum of |x_j^T t| over the dome."""
+    checked = 0
+    for seed in (21, 22):
+        for X, y, b, lam in _dome_iterates(orc, seed):
+            s = orc.screen(X, y, b, lam)
+            c, r, a, w, R, rc2 = _dome_geometry(X, y, b, lam, s["alpha"])
+            for j in range(0, X.shape[1], 3):
+                x = X[:, j]
+                best = max(_dome_max_brute(x, c, r, a, w), _dome_max_brute(-x, c, r, a, w))
+                mu = orc.dome_mu(x @ y, s["c"][j], np.linalg.norm(x), s["alpha"], lam, R, rc2)
+                # boundary sampled every 2 pi / 400000 radians: error ~1e-10 r ||x||
+                tol = 1e-8 * (1.0 + r * np.linalg.norm(x))
+                assert abs(mu - best) <= tol, (j, mu, best)
+                checked += 1
+    assert checked >= 50
+
+
+def test_dome_contains_dual_optimum_and_lies_in_sphere(orc):
+    """The GAP SAFE dome holds theta_hat (Theorem 2's annulus intersected
+    with the ball of diameter [theta, y/lambda], since theta_hat is the
+    projection of y/lambda on the dual set), and it lies inside the GAP SAFE
+    sphere: its kept set is a subset of the sphere's."""
+    for seed in (23, 24, 25):
+        X, y = _small_c1_like(seed=seed, n=20, p=60)
+        lmax = np.abs(X.T @ y).max()
+        for ratio in (0.5, 0.1):
+            lam = ratio * lmax
+            tight = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-15, K=10_000_000)
+            th = (y - X @ tight["beta"][0]) / lam
+            for K in (0, 2, 10, 40):
+                b = orc.lasso_path(X, y, lambdas=[lam], K=K, eps_rel=1e-30)["beta"][0]
+                s = orc.screen(X, y, b, lam, rule="dome")
+                c, r, a, w, R, rc2 = _dome_geometry(X, y, b, lam, s["alpha"])
+                assert np.linalg.norm(th - c) <= r * (1 + 1e-9) + 1e-12
+                assert w @ (th - c) <= -a * r + 1e-9 * r + 1e-12
+                sph = orc.screen(X, y, b, lam, rule="sphere")
+                assert np.all(s["keep_exact"] <= sph["keep_exact"])
+                assert np.all(s["keep_safe"] >= s["keep_exact"])
+                assert np.all(s["keep_safe"] <= sph["keep_safe"])
+
+
+def test_dome_reduces_to_ball_when_r_check_vanishes(orc):
+    """With r_check = 0 the ratio is -1: the dome is the whole ball of
+    diameter [theta, y/lambda] and mu_D(x) = |c^T x| + r ||x||."""
+    rng = np.random.default_rng(26)
+    for _ in range(20):
+        n = 6
+        x, y, rho = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+        alpha, lam = rng.uniform(0.5, 2), rng.uniform(0.5, 2)
+        R = np.linalg.norm(alpha * rho - y / lam)
+        mu = orc.dome_mu(x @ y, x @ rho, np.linalg.norm(x), alpha, lam, R, 0.0)
+        cx = 0.5 * (x @ y / lam + alpha * (x @ rho))
+        assert abs(mu - (abs(cx) + 0.5 * R * np.linalg.norm(x))) <= 1e-13 * (1 + abs(mu))
+
+
+def test_dome_path_is_safe_and_matches_sphere_path(orc):
+    """Algorithm 1 with the dome test: every coordinate the dome screens is
+    zero at the tight solution, and the certified path agrees with the
+    sphere path within the gap bound."""
+    X, y = _small_c1_like(seed=27, n=40, p=300)
+    lmax = np.abs(X.T @ y).max()
+    lams = lmax * 10 ** (-np.arange(12) / 11 * 1.5)
+    dome = orc.lasso_path(X, y, lambdas=lams, rule="dome", want_screened=True)
+    sph = orc.lasso_path(X, y, lambdas=lams, rule="sphere")
+    tight = orc.lasso_path(X, y, lambdas=lams, eps_rel=1e-15, K=10_000_000)
+    assert np.all(dome["status"] == 0)
+    for t in range(len(lams)):
+        scr = dome["screened"][t].astype(bool)
+        assert np.all(tight["beta"][t][scr] == 0)
+        d = X @ (dome["beta"][t] - sph["beta"][t])
+        assert np.linalg.norm(d) <= np.sqrt(2 * dome["gap"][t]) + np.sqrt(2 * sph["gap"][t]) + 1e-12
+    # the dome never keeps more than the sphere at the first pass of a lambda
+    assert dome["nactive"].sum() <= sph["nactive"].sum()

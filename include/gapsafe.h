@@ -95,6 +95,22 @@ enum {
   GS_CD_RESIDUAL = 1  /* residual updates only (rho in registers and LDS)    */
 };
 
+/* Safe region of the screening test (gs_opts.rule, screen()'s rule). */
+enum {
+  GS_RULE_SPHERE = 0, /* GAP SAFE sphere B(theta, sqrt(2 gap)/lambda)
+                         (Sec. 3.2, Proposition 1)                        */
+  GS_RULE_DOME = 1    /* the sphere test and the GAP SAFE dome test (Sec. 3.2
+                         dome equation, appendix dome support function): the
+                         ball of diameter [theta, y/lambda] cut by the plane
+                         through its intersection with the sphere of radius
+                         r_check[beta] around y/lambda, normal (y/lambda -
+                         theta)/||theta - y/lambda||.  Uses x_j^T y, computed
+                         once per problem, so it adds no pass over X; every
+                         input is replaced by a bound that enlarges the dome
+                         under rounding.  A coordinate is dropped when either
+                         test drops it.                                    */
+};
+
 /* Counters of gs_opts.stats (indices). */
 enum {
   GS_STAT_PATTERN_EPOCHS = 0, /* epochs committed by the pattern mode         */
@@ -167,6 +183,7 @@ typedef struct gs_opts {
   int64_t* stats;        /* [device] optional: GS_NSTATS counters of the
                             narrow schedule, incremented (atomically) by the
                             call; the caller zeroes them                     */
+  int32_t rule;          /* GS_RULE_*: the safe region (default sphere)       */
 } gs_opts;
 
 /* Fill *o with the defaults above. */
@@ -243,7 +260,8 @@ size_t screen_workspace_size(int32_t n, int32_t p);
  * (lambda ||rho||^2), -1/M), 1/M) (Sec. 2.3); gap G = P(beta) - D(theta);
  * radius r = sqrt(2 G)/lambda (Proposition 1); keep j iff
  * |x_j^T theta| + r ||x_j|| >= 1 (Sec. 2.1 sphere test) with the rounding
- * inflation.  Asynchronous.
+ * inflation, and with rule GS_RULE_DOME also the GAP SAFE dome test (it
+ * computes x_j^T y in the same sweep).  Asynchronous.
  *   dtype/X/y/ldx as in gs_problem (no row subsample); beta [device] p FP64
  *   values; active_in [device] q_in ascending column indices or NULL (all p);
  *   active_out [device] capacity q_in (p when active_in is NULL), receives the
@@ -252,7 +270,7 @@ size_t screen_workspace_size(int32_t n, int32_t p);
  *   radius actually used by the test); c_out [device] optional q_in doubles:
  *   c_j for the j of active_in, in its order. */
 int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
-           const void* y, const double* beta, double lambda,
+           const void* y, const double* beta, double lambda, int32_t rule,
            const int32_t* active_in, int32_t q_in, int32_t* active_out,
            int32_t* q_out, double* gap_out, double* alpha_out,
            double* radius_out, double* c_out, void* workspace,
@@ -264,8 +282,8 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
  * scratch arrays live in a static device array of GS_NOALLOC_SCRATCH_BYTES
  * (16 MiB) that the library holds on each GPU it runs on until the process
  * ends, so the call allocates nothing.  The pass fits when
- * screen_workspace_size(n, p) <= GS_NOALLOC_SCRATCH_BYTES (about 40 bytes
- * per column: p up to roughly 400,000 at n = 2048); larger inputs return
+ * screen_workspace_size(n, p) <= GS_NOALLOC_SCRATCH_BYTES (about 48 bytes
+ * per column: p up to roughly 347,000 at n = 2048); larger inputs return
  * GS_ETOOLARGE before anything is launched.  Every call on one GPU uses that
  * GPU's array: calls that overlap on one GPU (on different streams or host
  * threads) race and must be serialized by the caller; calls ordered on one
@@ -273,7 +291,7 @@ int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
  * initialises everything it reads. */
 #define GS_NOALLOC_SCRATCH_BYTES (16u << 20)
 int screen_noalloc(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
-                   const void* y, const double* beta, double lambda,
+                   const void* y, const double* beta, double lambda, int32_t rule,
                    const int32_t* active_in, int32_t q_in, int32_t* active_out,
                    int32_t* q_out, double* gap_out, double* alpha_out, double* radius_out,
                    double* c_out, void* stream);

@@ -29,6 +29,7 @@ GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED, GS_ETOOLARGE = -1, -2, -3, -
 NOALLOC_SCRATCH_BYTES = 16 << 20  # GS_NOALLOC_SCRATCH_BYTES
 SCHEDULES = {"auto": 0, "narrow": 1, "wide": 2}
 CD_MODES = {"auto": 0, "residual": 1}
+RULES = {"sphere": 0, "dome": 1}
 
 
 class GsError(RuntimeError):
@@ -57,7 +58,7 @@ class gs_opts(ctypes.Structure):
         ("max_epochs", ctypes.c_int32), ("schedule", ctypes.c_int32),
         ("cd_mode", ctypes.c_int32),
         ("select_counts", ctypes.c_void_p), ("timestamps", ctypes.c_void_p),
-        ("stats", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p), ("rule", ctypes.c_int32),
     ]
 
 
@@ -123,12 +124,12 @@ def load_library(path: str = LIB_PATH):
     lib.screen_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.screen_workspace_size.restype = ctypes.c_size_t
     lib.screen.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
-                           vp, vp, vp, ctypes.c_double, vp, ctypes.c_int32, vp, vp, vp, vp,
-                           vp, vp, vp, ctypes.c_size_t, vp]
+                           vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int32,
+                           vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.screen.restype = ctypes.c_int
     lib.screen_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                   ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp,
-                                   ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+                                   ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_int32,
+                                   vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.screen_noalloc.restype = ctypes.c_int
     lib.gs_timing_enable.argtypes = [ctypes.c_int]
     lib.gs_timing_enable.restype = None
@@ -276,9 +277,10 @@ def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, o
 
 
 def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, timestamps=None,
-          cd_mode="auto", stats=None):
+          cd_mode="auto", stats=None, rule="sphere"):
     o = gs_opts()
     load_library().gs_opts_default(ctypes.byref(o))
+    o.rule = RULES[rule] if isinstance(rule, str) else int(rule)
     o.eps_rel = float(eps_rel)
     o.screen_every = int(screen_every)
     o.max_epochs = int(max_epochs)
@@ -307,7 +309,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
                relative: bool = False, lambda_min_ratio: float = 1e-3, beta_init=None,
                rows=None, eps_rel: float = 1e-8, screen_every: int = 10,
                max_epochs: int = 100000, schedule="auto", cd_mode="auto", stream=None,
-               out=None, workspace=None, stats=None):
+               out=None, workspace=None, stats=None, rule="sphere"):
     """Algorithm 1 on the device for one problem; see include/gapsafe.h.
     Returns a PathResult of device tensors (valid after the stream syncs) with
     an extra ``rc`` entry (GS_OK or GS_NOT_CONVERGED)."""
@@ -315,7 +317,8 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
     pr, out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
                               lambda_min_ratio=lambda_min_ratio, beta_init=beta_init,
                               rows=rows, out=out)
-    o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode, stats=stats)
+    o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode, stats=stats,
+              rule=rule)
     need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
     rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))
@@ -326,7 +329,7 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
 
 
 def _batch_args(problems, eps_rel, screen_every, max_epochs, select_counts, timestamps,
-                cd_mode, stats, workspace):
+                cd_mode, stats, workspace, rule="sphere"):
     lib = load_library()
     B = len(problems)
     arr = (gs_problem * B)()
@@ -341,7 +344,7 @@ def _batch_args(problems, eps_rel, screen_every, max_epochs, select_counts, time
         outs.append(out)
         keep.append(hl)
     o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps, cd_mode,
-              stats)
+              stats, rule)
     need = lib.lasso_workspace_size(arr, B, ctypes.byref(o))
     dev = problems[0]["X"].device
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
@@ -352,13 +355,13 @@ def _batch_args(problems, eps_rel, screen_every, max_epochs, select_counts, time
 
 def lasso_solve_batch(problems, *, eps_rel: float = 1e-8, screen_every: int = 10,
                       max_epochs: int = 100000, select_counts=None, timestamps=None,
-                      cd_mode="auto", stream=None, workspace=None, stats=None):
+                      cd_mode="auto", stream=None, workspace=None, stats=None, rule="sphere"):
     """Many paths in one persistent launch.  ``problems`` is a list of dicts
     with keys X, y and optionally T, lambdas, relative, lambda_min_ratio,
     beta_init, rows.  Returns the list of PathResults."""
     lib, arr, o, outs, _keep, ws = _batch_args(problems, eps_rel, screen_every, max_epochs,
                                                select_counts, timestamps, cd_mode, stats,
-                                               workspace)
+                                               workspace, rule)
     rc = lib.lasso_solve_batch(arr, len(problems), ctypes.byref(o), _ptr(ws), ws.numel(),
                                _stream_ptr(stream))
     _check(rc)
@@ -428,7 +431,7 @@ def tune_reset():
 
 
 def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=None,
-           workspace=None):
+           workspace=None, rule="sphere"):
     """One GAP SAFE screening pass at (beta, lam).  Returns device tensors:
     active (kept indices, ascending), q (1,), gap, alpha, radius (1,) and c."""
     torch = _torch()
@@ -452,7 +455,7 @@ def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=N
     need = lib.screen_workspace_size(n, p)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
     rc = lib.screen(n, p, ld, _dtype_code(X), _ptr(X), _ptr(y), _ptr(beta), float(lam),
-                    _ptr(active), q, _ptr(act_out), _ptr(q_out), _ptr(gap), _ptr(alpha),
+                    RULES[rule], _ptr(active), q, _ptr(act_out), _ptr(q_out), _ptr(gap), _ptr(alpha),
                     _ptr(radius), _ptr(c), _ptr(ws), ws.numel(), _stream_ptr(stream))
     _check(rc, allow_not_converged=False)
     return dict(active=act_out, q=q_out, gap=gap, alpha=alpha, radius=radius,
@@ -460,7 +463,7 @@ def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=N
 
 
 def screen_noalloc(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=None,
-                   out=None):
+                   out=None, rule="sphere"):
     """screen() through the allocation-free entry point: the library uses its
     static device scratch instead of a workspace.  ``out`` (optional) is a
     dict of preallocated output tensors as returned by a previous call, so a
@@ -487,7 +490,7 @@ def screen_noalloc(X, y, beta, lam: float, active=None, *, want_c: bool = True, 
     elif out["active"].numel() < q or (out.get("c") is not None and out["c"].numel() < q):
         raise ValueError("preallocated outputs are smaller than the active set")
     rc = lib.screen_noalloc(n, p, ld, _dtype_code(X), _ptr(X), _ptr(y), _ptr(beta), float(lam),
-                            _ptr(active), q, _ptr(out["active"]), _ptr(out["q"]),
+                            RULES[rule], _ptr(active), q, _ptr(out["active"]), _ptr(out["q"]),
                             _ptr(out["gap"]), _ptr(out["alpha"]), _ptr(out["radius"]),
                             _ptr(out.get("c")), _stream_ptr(stream))
     _check(rc, allow_not_converged=False)

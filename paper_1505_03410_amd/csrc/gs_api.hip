@@ -90,6 +90,7 @@ int check_opts(const gs_opts* o) {
   if (o->screen_every < 1 || o->max_epochs < 0) return GS_EINVAL;
   if (o->schedule < GS_SCHED_AUTO || o->schedule > GS_SCHED_WIDE) return GS_EINVAL;
   if (o->cd_mode < GS_CD_AUTO || o->cd_mode > GS_CD_RESIDUAL) return GS_EINVAL;
+  if (o->rule != GS_RULE_SPHERE && o->rule != GS_RULE_DOME) return GS_EINVAL;
   return GS_OK;
 }
 
@@ -175,6 +176,7 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   const int64_t ldg = (int64_t)align_up((size_t)pr->p, 256);
   const int ns = pattern_slots(pr);
   d->nrm2 = cv.take<double>(pr->p);
+  d->xty = cv.take<double>(pr->p);
   d->inv = cv.take<double>(pr->p);
   d->beta = cv.take<double>(pr->p);
   d->c = cv.take<double>(ldg);
@@ -244,7 +246,7 @@ PathOpts path_opts(const gs_opts* o, bool batch) {
   po.lds_cap = 0;
   po.pattern = o->cd_mode == GS_CD_RESIDUAL ? 0 : 1;
   po.gs_cap = 0;
-  po.pad_ = 0;
+  po.rule = o->rule;
   po.select_counts = batch ? o->select_counts : nullptr;
   po.timestamps = batch ? reinterpret_cast<long long*>(o->timestamps) : nullptr;
   po.stats = reinterpret_cast<long long*>(o->stats);
@@ -641,6 +643,7 @@ void carve_screen(Carver& cv, int n, int p, Shared* s, ProbDesc* d) {
   s->wb.nzidx = cv.take<int32_t>(p);
   s->wb.nzval = cv.take<double>(p);
   d->nrm2 = cv.take<double>(p);
+  d->xty = cv.take<double>(p);
   d->beta = cv.take<double>(p);
   d->c = cv.take<double>(p);
   d->act = cv.take<int32_t>(p);
@@ -649,7 +652,8 @@ void carve_screen(Carver& cv, int n, int p, Shared* s, ProbDesc* d) {
 }
 
 int check_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, const void* y,
-                 const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
+                 const double* beta, double lambda, int32_t rule, const int32_t* active_in,
+                 int32_t q_in,
                  int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
                  double* radius_out) {
   if (n < 1 || p < 1 || ldx < n) return GS_EINVAL;
@@ -657,6 +661,7 @@ int check_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X
   if (!X || !y || !beta || !active_out || !q_out || !gap_out || !alpha_out || !radius_out)
     return GS_EINVAL;
   if (!finite_pos(lambda)) return GS_EINVAL;
+  if (rule != GS_RULE_SPHERE && rule != GS_RULE_DOME) return GS_EINVAL;
   if (active_in && (q_in < 0 || q_in > p)) return GS_EINVAL;
   if (n > kMaxN) return GS_EUNSUPPORTED;
   return GS_OK;
@@ -665,7 +670,8 @@ int check_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X
 // The pass itself on the arrays carved from `base` (a workspace, or the
 // static scratch of screen_noalloc).
 int run_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, const void* y,
-               const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
+               const double* beta, double lambda, int32_t rule, const int32_t* active_in,
+               int32_t q_in,
                int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
                double* radius_out, double* c_out, char* base, hipStream_t s) {
   const int q = active_in ? q_in : p;
@@ -692,8 +698,8 @@ int run_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, 
   po.f = 1;
   po.K = 0;
   {
-    int qi = q_in;
-    void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda};
+    int qi = q_in, ru = rule;
+    void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda, &ru};
     HIPCHK(launch(kScreenPrep[dtype], dim3(1), dim3(256), a, 0, s));
   }
   int zero = 0, one = 1;
@@ -705,8 +711,8 @@ int run_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, 
                                                           (kSweepWaves * kSweepU)));
   {
     void* a[] = {&d, &st, &wb};
-    HIPCHK(timed_launch(kTimeSweep, w->sweep_nrm_kernel, dim3(nsweep), dim3(64 * kSweepWaves), a, 0,
-                        s));
+    HIPCHK(timed_launch(kTimeSweep, rule == GS_RULE_DOME ? w->sweep_nxy_kernel : w->sweep_nrm_kernel,
+                        dim3(nsweep), dim3(64 * kSweepWaves), a, 0, s));
   }
   {
     void* a[] = {&d, &st, &wb, &nsweep, &one, &gap_out, &alpha_out, &radius_out, &po};
@@ -849,32 +855,33 @@ size_t screen_workspace_size(int32_t n, int32_t p) {
 }
 
 int screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, const void* y,
-           const double* beta, double lambda, const int32_t* active_in, int32_t q_in,
-           int32_t* active_out, int32_t* q_out, double* gap_out, double* alpha_out,
-           double* radius_out, double* c_out, void* workspace, size_t ws_bytes, void* stream) {
-  const int rc = check_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out,
-                              q_out, gap_out, alpha_out, radius_out);
+           const double* beta, double lambda, int32_t rule, const int32_t* active_in,
+           int32_t q_in, int32_t* active_out, int32_t* q_out, double* gap_out,
+           double* alpha_out, double* radius_out, double* c_out, void* workspace,
+           size_t ws_bytes, void* stream) {
+  const int rc = check_screen(n, p, ldx, dtype, X, y, beta, lambda, rule, active_in, q_in,
+                              active_out, q_out, gap_out, alpha_out, radius_out);
   if (rc) return rc;
   if (!workspace) return GS_EWORKSPACE;
   if (ws_bytes < screen_workspace_size(n, p)) return GS_EWORKSPACE;
-  return run_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out, q_out,
+  return run_screen(n, p, ldx, dtype, X, y, beta, lambda, rule, active_in, q_in, active_out, q_out,
                     gap_out, alpha_out, radius_out, c_out, static_cast<char*>(workspace),
                     static_cast<hipStream_t>(stream));
 }
 
 int screen_noalloc(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
-                   const void* y, const double* beta, double lambda,
+                   const void* y, const double* beta, double lambda, int32_t rule,
                    const int32_t* active_in, int32_t q_in, int32_t* active_out,
                    int32_t* q_out, double* gap_out, double* alpha_out, double* radius_out,
                    double* c_out, void* stream) {
-  const int rc = check_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out,
-                              q_out, gap_out, alpha_out, radius_out);
+  const int rc = check_screen(n, p, ldx, dtype, X, y, beta, lambda, rule, active_in, q_in,
+                              active_out, q_out, gap_out, alpha_out, radius_out);
   if (rc) return rc;
   if (screen_workspace_size(n, p) > (size_t)GS_NOALLOC_SCRATCH_BYTES) return GS_ETOOLARGE;
   char* base = nullptr;
   const int r2 = scratch_base(&base);
   if (r2) return r2;
-  return run_screen(n, p, ldx, dtype, X, y, beta, lambda, active_in, q_in, active_out, q_out,
+  return run_screen(n, p, ldx, dtype, X, y, beta, lambda, rule, active_in, q_in, active_out, q_out,
                     gap_out, alpha_out, radius_out, c_out, base,
                     static_cast<hipStream_t>(stream));
 }

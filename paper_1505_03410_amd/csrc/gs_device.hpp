@@ -251,13 +251,26 @@ struct ColLayout {
 //   r+    = sqrt(2 (max(G,0) + errG)) / lambda (1 + 4u)   (Proposition 1)
 // The sphere test then keeps j iff
 //   |alpha c^_j| + |alpha| e_c ||x_j||+ + r+ ||x_j||+ >= 1 - 4u    (Sec. 2.1)
+//
+// GAP SAFE dome (Sec. 3.2; dome support function of the appendix), the ball
+// of diameter [theta, y/lambda] cut by the plane through its intersection
+// with the sphere of radius r_check[beta] around y/lambda, normal
+// w = (y/lambda - theta)/R_hat, R_hat = ||theta - y/lambda||.  Its safe
+// parameters enlarge the dome by the rounding of the inputs: R_hat between
+// Rlo and Rhi (R_hat^2 = alpha^2 R2 - 2 alpha Ry/lambda + ||y||^2/lambda^2),
+// rc2lo a lower bound of r_check^2 = (||y||^2 - ||y - X beta||^2 -
+// 2 lambda ||beta||_1)_+/lambda^2, e_y the error of x_j^T y/lambda per
+// unit ||x_j||.
 struct GapInfo {
   double alpha, gap, radius, e_c;
+  double lambda, Rlo, Rhi, rc2lo, e_y;
+  bool dome;
 };
 
 __device__ __forceinline__ GapInfo gap_safe(double R2, double Ry, double l1, double sbx,
                                             double xmax, double M, int nnz, int n,
-                                            double lambda, double ynorm) {
+                                            double lambda, double ynorm, int q = 0,
+                                            bool dome = false) {
   GapInfo g;
   const double up = 1.0 + gam(n + 2);
   const double rnorm = sqrt(R2) * up;
@@ -277,7 +290,68 @@ __device__ __forceinline__ GapInfo gap_safe(double R2, double Ry, double l1, dou
                       lambda * fabs(a) * gam(n) * (ynorm * up) * rnorm + rnorm * drho +
                       0.5 * drho * drho;
   g.radius = sqrt(2.0 * (fmax(g.gap, 0.0) + errG)) / lambda * (1.0 + 4.0 * kU);
+  g.lambda = lambda;
+  g.dome = dome;
+  g.Rlo = g.Rhi = g.rc2lo = g.e_y = 0.0;
+  if (dome) {
+    const double yy = ynorm * ynorm, il = 1.0 / lambda, il2 = il * il;
+    const double yn = ynorm * up;
+    const double Rs2 = a * a * R2 - 2.0 * a * Ry * il + yy * il2;
+    const double eR2 = gam(n + 6) * (a * a * R2 + 2.0 * fabs(a * Ry) * il + yy * il2) +
+                       2.0 * fabs(a) * il * gam(n) * yn * rnorm;
+    g.Rhi = sqrt(fmax(Rs2 + eR2, 0.0)) * (1.0 + 4.0 * kU);
+    g.Rlo = sqrt(fmax(Rs2 - eR2, 0.0)) * (1.0 - 4.0 * kU);
+    const double rt = rnorm + drho;  // bounds ||y - X beta||
+    g.rc2lo = fmax((yy * (1.0 - gam(n + 2)) - rt * rt * (1.0 + 4.0 * kU) -
+                    2.0 * lambda * l1 * (1.0 + gam(q + 2))) * il2 * (1.0 - 4.0 * kU),
+                   0.0);
+    g.e_y = gam(n + 1) * yn * il;
+  }
   return g;
+}
+
+// Support function of the dome at x given c^T x (cx), w^T x (wx) and ||x||:
+// the ball's maximizer c + r x/||x|| when it lies on the kept side of the
+// plane (w^T x <= -ra ||x||), else the best point of the circle where the
+// plane cuts the sphere.  Non-increasing in wx.
+__device__ __forceinline__ double dome_sigma(double cx, double wx, double xn, double r,
+                                             double ra) {
+  if (wx <= -ra * xn) return cx + r * xn;
+  return cx - r * ra * wx + r * sqrt(fmax((xn * xn - wx * wx) * (1.0 - ra * ra), 0.0));
+}
+
+// The dome test for column j (keep iff max(sigma(x_j), sigma(-x_j)) >= 1),
+// with every input replaced by the bound that enlarges the dome: Rhi for the
+// ball, rc2lo for the plane, an upper bound of c^T x, a lower bound of w^T x
+// and of ||x||'s upper bound, plus a margin for the evaluation.
+__device__ __forceinline__ bool dome_keep(const GapInfo& g, double xty, double c, double nrm2,
+                                          int n) {
+  if (!g.dome) return true;
+  if (!(nrm2 > 0.0)) return false;
+  if (!(g.Rhi > 0.0)) return true;
+  const double xn = sqrt(nrm2) * (1.0 + gam(n + 2));
+  const double r = 0.5 * g.Rhi;
+  const double ra = fmax(2.0 * g.rc2lo / (g.Rhi * g.Rhi) - 1.0, -1.0);
+  const double yl = xty / g.lambda, ac = g.alpha * c;
+  const double cx = 0.5 * (yl + ac), num = yl - ac;
+  const double ey = g.e_y * xn, eac = fabs(g.alpha) * g.e_c * xn;
+  const double ro = 4.0 * kU * (fabs(yl) + fabs(ac));
+  const double ecx = 0.5 * (ey + eac) + ro, ewn = ey + eac + ro;
+  double mu = -INFINITY;
+#pragma unroll
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    const double cs = sgn * cx + ecx;
+    const double ns = sgn * num - ewn;
+    double m;
+    if (ns >= 0.0)
+      m = dome_sigma(cs, ns / g.Rhi, xn, r, ra);
+    else if (g.Rlo > 0.0)
+      m = dome_sigma(cs, ns / g.Rlo, xn, r, ra);
+    else
+      m = cs + r * xn;
+    mu = fmax(mu, m);
+  }
+  return mu >= 1.0 - 16.0 * kU * (fabs(cx) + 3.0 * r * xn + 1.0);
 }
 
 __device__ __forceinline__ bool sphere_keep(const GapInfo& g, double c, double nrm2, int n) {

@@ -617,6 +617,7 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = prob->n, p = prob->p, T = prob->T;
   const int dt = prob->dtype;
+  const int rule = opts ? opts->rule : GS_RULE_SPHERE;
   int rc;
 
   // once per problem: ||x_j||^2, x_j^T y, lambda_max, ||y||, bmc
@@ -677,7 +678,7 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
     const double* startp = bprev;
     if (params && bprev) {
       // plain screening pass at the previous solution: A_plain and c
-      rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], nullptr, 0, w.act, w.q,
+      rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], rule, nullptr, 0, w.act, w.q,
                   w.scal + 2, w.scal + 4, w.scal + 5, w.c, w.inner, w.inner_bytes, s);
       if (rc) return rc;
       rc = launch_features(p, w.c, bprev, w.nrm2, w.bmc, lam[t], lam_max, ynorm, w.U, s);
@@ -697,11 +698,11 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
         rc = last_launch("k_warm_set");
         if (rc) return rc;
         // both candidates' gaps on the reduced problem over A_plain
-        rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], w.act, q, w.act2,
+        rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], rule, w.act, q, w.act2,
                     w.q + 1, w.scal + 2, w.scal + 4, w.scal + 5, nullptr, w.inner, w.inner_bytes,
                     s);
         if (rc) return rc;
-        rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, w.beta0, lam[t], w.act, q, w.act2,
+        rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, w.beta0, lam[t], rule, w.act, q, w.act2,
                     w.q + 1, w.scal + 3, w.scal + 4, w.scal + 5, nullptr, w.inner, w.inner_bytes,
                     s);
         if (rc) return rc;

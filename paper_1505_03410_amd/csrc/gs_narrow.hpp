@@ -94,6 +94,7 @@ struct Narrow {
     float* stg;                 // LDS staging region of the residual mode
     int stg_cap;                // its size in floats
     gbl<double>* nrm2;
+    gbl<double>* xty;           // x_j^T y (the dome test)
     gbl<double>* inv;           // 1/||x_j||^2 (0 for a zero column)
     gbl<double>* beta;
     gbl<double>* c;             // correlations by position (one of two buffers)
@@ -354,7 +355,8 @@ struct Narrow {
       for (int u = 0; u < 4; ++u) {
         const int k = base + 64 * u + x.lane;
         const bool v = k < q;
-        const bool keep = v && sphere_keep(g, cv[u], nv[u], x.n);
+        bool keep = v && sphere_keep(g, cv[u], nv[u], x.n);
+        if (g.dome && keep) keep = dome_keep(g, x.xty[jv[u]], cv[u], nv[u], x.n);
         if (v && !keep && bv[u] != 0.0) {
           x.beta[jv[u]] = 0.0;
           dn = true;
@@ -1246,6 +1248,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
     x.seg = lane % S;
     bind_lds<N, XT, narrow_lds_bytes<XT, VEC, S, NG, GATHER>()>(x, pt, smem, opts);
     x.nrm2 = gptr(d.nrm2);
+    x.xty = gptr(d.xty);
     x.inv = gptr(d.inv);
     x.beta = gptr(d.beta);
     x.c = gptr(d.c);
@@ -1306,6 +1309,7 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
           sy = seg_sum<S>(sy);
           if (st[u].v && x.seg == 0) {
             x.nrm2[st[u].j] = s2;
+            x.xty[st[u].j] = sy;
             x.inv[st[u].j] = s2 > 0.0 ? 1.0 / s2 : 0.0;
             lmax_l = fmax(lmax_l, fabs(sy));
             if (!isfinite(s2) || !isfinite(sy)) bad = true;
@@ -1362,7 +1366,8 @@ __global__ __launch_bounds__(64) void k_path_narrow(const ProbDesc* __restrict__
             int nnz = N::refresh(x, q, full, R2, Ry);
             N::sweep(x, q, full, M, l1, sbx, xmax);
             ++stc[kStatPasses];
-            GapInfo g = gap_safe(R2, Ry, l1, sbx, xmax, M, nnz, n, lambda, ynorm);
+            GapInfo g = gap_safe(R2, Ry, l1, sbx, xmax, M, nnz, n, lambda, ynorm, q,
+                                 opts.rule == 1);
             G = g.gap;
             if (G <= eps) {
               status = 0;

@@ -14,8 +14,9 @@ struct NarrowEntry {
 struct WideEntry {
   int dtype, vec, NG;       // sweep layout: 64 lanes over rows
   const void* pre_kernel;   // k_wide_pre<...>
-  const void* sweep_kernel; // k_wide_sweep<..., false>
-  const void* sweep_nrm_kernel;  // k_wide_sweep<..., true>: also ||x_j||^2
+  const void* sweep_kernel; // k_wide_sweep<..., 0>
+  const void* sweep_nrm_kernel;  // k_wide_sweep<..., 1>: also ||x_j||^2
+  const void* sweep_nxy_kernel;  // k_wide_sweep<..., 2>: also ||x_j||^2 and x_j^T y
   const void* csweep_kernel;     // k_wide_csweep<...>: c from the resume position
   const void* walk_kernel;       // k_wide_walk<...>: the CD epoch on one wave
   int nmax() const { return 64 * NG * vec; }

@@ -5,13 +5,25 @@
 
 namespace gs {
 
-__device__ __forceinline__ GapInfo state_gap(const WideState* st) {
+__device__ __forceinline__ GapInfo state_gap(const ProbDesc& d, const WideState* st) {
   GapInfo g;
   g.alpha = st->alpha_s;
   g.gap = st->gap;
   g.radius = st->radius_s;
   g.e_c = st->e_c;
+  g.lambda = d.lam[st->t];
+  g.Rlo = st->Rlo;
+  g.Rhi = st->Rhi;
+  g.rc2lo = st->rc2lo;
+  g.e_y = st->e_y;
+  g.dome = st->rule == 1;
   return g;
+}
+
+// The sphere test, and the dome test where it is on (each is safe alone).
+__device__ __forceinline__ bool wide_keep(const ProbDesc& d, const GapInfo& g, int j, double c) {
+  const double nr = d.nrm2[j];
+  return sphere_keep(g, c, nr, d.n) && (!g.dome || dome_keep(g, d.xty[j], c, nr, d.n));
 }
 
 // Sphere test over one tile of A: kept count per block; screened nonzero
@@ -22,7 +34,7 @@ __global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, Wi
   const int q = st->q;
   const bool full = st->full != 0;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
-  const GapInfo g = state_gap(st);
+  const GapInfo g = state_gap(d, st);
   const int tile0 = blockIdx.x * kTestTile;
   int cnt = 0;
   bool dn = false;
@@ -30,7 +42,7 @@ __global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, Wi
     const int k = tile0 + e;
     if (k >= q) break;
     const int j = full ? k : act[k];
-    if (sphere_keep(g, d.c[k], d.nrm2[j], d.n)) {
+    if (wide_keep(d, g, j, d.c[k])) {
       ++cnt;
     } else if (d.beta[j] != 0.0) {
       d.beta[j] = 0.0;
@@ -53,7 +65,7 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
   const bool full = st->full != 0;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   int32_t* dst = out ? out : d.act + (int64_t)(st->cur ^ 1) * d.p;
-  const GapInfo g = state_gap(st);
+  const GapInfo g = state_gap(d, st);
   int off = 0;
   for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];
   const int k0 = blockIdx.x * kTestTile + threadIdx.x * PER;
@@ -67,7 +79,7 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
     if (k < q) {
       const int j = full ? k : act[k];
       js[e] = j;
-      if (sphere_keep(g, d.c[k], d.nrm2[j], d.n)) {
+      if (wide_keep(d, g, j, d.c[k])) {
         keep |= 1u << e;
         ++c;
       }
@@ -200,7 +212,7 @@ template <typename XT>
 __global__ __launch_bounds__(256) void k_screen_prep(ProbDesc d, WideState* st,
                                                      const double* beta_in,
                                                      const int32_t* active_in, int q_in,
-                                                     double lambda) {
+                                                     double lambda, int rule) {
   __shared__ double sh[256];
   for (int j = threadIdx.x; j < d.p; j += 256) d.beta[j] = beta_in[j];
   if (active_in)
@@ -224,6 +236,7 @@ __global__ __launch_bounds__(256) void k_screen_prep(ProbDesc d, WideState* st,
     st->done = 0;
     st->phase = 0;
     st->need_refresh = 0;
+    st->rule = rule;
   }
 }
 
@@ -247,8 +260,9 @@ const void* const kWideStats = reinterpret_cast<const void*>(&k_wide_stats);
   {                                                                             \
     sizeof(XT) == 8 ? 1 : 0, VEC, NG,                                           \
         reinterpret_cast<const void*>(&k_wide_pre<XT, VEC, NG>),                \
-        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, false>),       \
-        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, true>),        \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, 0>),           \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, 1>),           \
+        reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, 2>),           \
         reinterpret_cast<const void*>(&k_wide_csweep<XT, VEC, NG>),             \
         reinterpret_cast<const void*>(&k_wide_walk<XT, VEC, NG>)                \
   }

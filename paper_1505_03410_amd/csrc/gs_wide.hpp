@@ -102,6 +102,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_pre(ProbDesc d, WideB
     if (lane == 0) {
       d.nrm2[j] = s2;
       d.inv[j] = s2 > 0.0 ? 1.0 / s2 : 0.0;
+      d.xty[j] = sy;
       mx = fmax(mx, fabs(sy));
       if (!isfinite(s2) || !isfinite(sy)) bad = 1.0;
     }
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
     st->status_acc = 0;
     st->nonfinite = (bad != 0.0) ? 1 : 0;
     st->resume = 0;
+    st->rule = opts.rule;
     st->first_epoch = 1;
     st->tau = INFINITY;
     st->tau_first = INFINITY;
@@ -260,12 +262,14 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
 }
 
 // ---- the sweep: c_k = x_{A[k]}^T rho for the k of A, per-block partials
-// (max |c|, ||beta||_1, sum |beta_j| ||x_j||, max ||x_j||).  With WN the
-// column norms are computed here too (screen()).
-template <typename XT, int VEC, int NG, bool WN>
+// (max |c|, ||beta||_1, sum |beta_j| ||x_j||, max ||x_j||).  WN = 1: the
+// column norms are computed here too (screen()); WN = 2: and x_j^T y (the
+// dome test of screen()).
+template <typename XT, int VEC, int NG, int WN>
 __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, WideState* st,
                                                                  WideBufs wb) {
-  constexpr bool with_nrm2 = WN;
+  constexpr bool with_nrm2 = WN >= 1;
+  constexpr bool with_xty = WN == 2;
   using L = ColLayout<XT, VEC, 64, NG, false>;
   constexpr int RPL = L::RPL;
   __shared__ double sh[64 * kSweepWaves];
@@ -276,12 +280,14 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   const XT* X = (const XT*)d.X;
   double r[RPL];
+  double yv[with_xty ? RPL : 1];
 #pragma unroll
   for (int m = 0; m < NG; ++m)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       int i = L::row(lane, m, e);
       r[m * VEC + e] = (i < d.n) ? d.rho[i] : 0.0;
+      if constexpr (with_xty) yv[m * VEC + e] = (i < d.n) ? (double)((const XT*)d.y)[i] : 0.0;
     }
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
       L::load_raw_nt(X + (int64_t)jj[u] * d.ldx, d.n, lane, xv[u]);
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
-      double a = 0.0, s2 = 0.0;
+      double a = 0.0, s2 = 0.0, sy = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         a = fma((double)xv[u][i], r[i], a);  // r is zero at rows >= n
@@ -316,13 +322,16 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
           const double xi = L::at(xv[u], mk, i);
           s2 = fma(xi, xi, s2);
         }
+        if constexpr (with_xty) sy = fma((double)xv[u][i], yv[i], sy);
       }
       a = wave_sum(a);
       if (with_nrm2) s2 = wave_sum(s2);
+      if constexpr (with_xty) sy = wave_sum(sy);
       if (base + u < q && lane == 0) {
         const int j = jj[u];
         d.c[base + u] = a;
         if (with_nrm2) d.nrm2[j] = s2;
+        if constexpr (with_xty) d.xty[j] = sy;
         const double nr = with_nrm2 ? s2 : nrv[u];
         const double b = bv[u];
         Ml = fmax(Ml, fabs(a));
@@ -366,7 +375,14 @@ __global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, Wid
   xm = block_max<256>(xm, sh);
   const int t = st->t;
   const double lambda = d.lam[t];
-  GapInfo g = gap_safe(st->R2, st->Ry, l1, sb, xm, M, st->nnz, d.n, lambda, sqrt(st->ynorm2));
+  GapInfo g = gap_safe(st->R2, st->Ry, l1, sb, xm, M, st->nnz, d.n, lambda, sqrt(st->ynorm2),
+                       st->q, st->rule == 1);
+  if (threadIdx.x == 0) {
+    st->Rlo = g.Rlo;
+    st->Rhi = g.Rhi;
+    st->rc2lo = g.rc2lo;
+    st->e_y = g.e_y;
+  }
   if (mode == 1) {
     if (threadIdx.x == 0) {
       *gap_o = g.gap;

@@ -163,6 +163,99 @@ def test_screen_c4_full_size_sampled(torch, orc, full):
     assert ex <= kept and len(kept) - len(ex) <= max(5, len(ex) // 1000)
 
 
+# ------------------------------------------------------------ GAP SAFE dome
+
+def _dome_mu_all(orc, X, y, beta, lam, o):
+    """mu_D(x_j) of the exact GAP SAFE dome for every column of o's active
+    set, from the oracle's pass scalars (no rounding inflation)."""
+    Xf, yf = _f64(X), _f64(y)
+    al = o["alpha"]
+    R = np.sqrt(max(al * al * o["rho_norm2"] - 2 * al * o["y_rho"] / lam + yf @ yf / lam ** 2, 0.0))
+    rc2 = max(yf @ yf - o["rho_norm2"] - 2 * lam * o["l1"], 0.0) / lam ** 2
+    act = o["active"]
+    xty = Xf[:, act].T @ yf
+    xn = np.linalg.norm(Xf[:, act], axis=0)
+    return np.array([orc.dome_mu(xty[k], o["c"][k], xn[k], al, lam, R, rc2)
+                     for k in range(len(act))])
+
+
+def _screen_dome_case(torch, orc, X, y, beta, lam, active=None, ld_multiple=4):
+    Xd, yd = _dev(torch, X, y, ld_multiple)
+    bd = torch.from_numpy(np.ascontiguousarray(beta, dtype=np.float64)).cuda()
+    ad = None if active is None else torch.from_numpy(active.astype(np.int32)).cuda()
+    g = gs.screen(Xd, yd, bd, lam, ad, rule="dome")
+    gsph = gs.screen(Xd, yd, bd, lam, ad, rule="sphere")
+    torch.cuda.synchronize()
+    o = orc.screen(_f64(X), _f64(y), _f64(beta), lam, active, rule="dome")
+    q = int(_np(g["q"])[0])
+    kept = set(_np(g["active"])[:q].tolist())
+    qs = int(_np(gsph["q"])[0])
+    kept_sph = set(_np(gsph["active"])[:qs].tolist())
+    # gap, alpha and radius are those of the sphere pass
+    assert abs(float(_np(g["gap"])[0]) - float(_np(gsph["gap"])[0])) == 0.0
+    ex = set(o["active"][o["keep_exact"]].tolist())          # exact dome and sphere
+    assert ex <= kept, sorted(ex - kept)[:10]
+    mu = _dome_mu_all(orc, X, y, beta, lam, o)
+    xn = np.linalg.norm(_f64(X)[:, o["active"]], axis=0)
+    mu_s = np.abs(o["alpha"] * o["c"]) + o["radius"] * xn
+    loose = set(o["active"][(mu >= 1 - 1e-6) & (mu_s >= 1 - 1e-6)].tolist())
+    assert kept <= loose, sorted(kept - loose)[:10]
+    assert kept <= kept_sph
+    assert list(_np(g["active"])[:q]) == sorted(kept)
+    return len(kept), len(kept_sph)
+
+
+def test_screen_dome_kept_sets(torch, orc):
+    """The device's GAP SAFE dome test (Sec. 3.2; appendix dome support
+    function) keeps every column the exact dome and sphere keep, nothing the
+    exact tests would drop with a margin of 1e-6, and a subset of the
+    sphere's kept set; on these iterates it drops more than the sphere."""
+    fewer = 0
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    lmax = np.abs(X.T @ y).max()
+    for ratio in (0.7, 0.3, 0.1):
+        lam = ratio * lmax
+        r = orc.lasso_path(X, y, lambdas=[lmax, lam], K=5)
+        kd, ks = _screen_dome_case(torch, orc, X, y, r["beta"][1], lam, ld_multiple=2)
+        fewer += kd < ks
+    d = synth.c1()
+    X, y = d["X"], d["y"]
+    lmax = np.abs(_f64(X).T @ _f64(y)).max()
+    for ratio, K in ((0.5, 10), (0.2, 30), (0.05, 60)):
+        lam = ratio * lmax
+        r = orc.lasso_path(X, y, lambdas=[lmax, lam], K=K)
+        kd, ks = _screen_dome_case(torch, orc, X, y, r["beta"][1], lam)
+        fewer += kd < ks
+        act = np.union1d(np.sort(np.random.default_rng(K).choice(7129, 2500, replace=False)),
+                         np.flatnonzero(r["beta"][1])).astype(np.int32)
+        _screen_dome_case(torch, orc, X, y, r["beta"][1], lam, active=act)
+    assert fewer >= 1
+
+
+@pytest.mark.parametrize("schedule", ["narrow", "wide"])
+def test_path_dome_c1(torch, orc, schedule):
+    """The 72 x 7129 path (40 lambdas down to lambda_max/100) with the dome
+    test on the narrow and the wide schedule: certified, beta against the
+    tight oracle, and the same epochs and final active sets as the oracle
+    running Algorithm 1 with the dome."""
+    d = synth.c1()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path(Xd, yd, T=40, lambda_min_ratio=1e-2, rule="dome", schedule=schedule)
+    torch.cuda.synchronize()
+    assert got["rc"] == gs.GS_OK
+    lams = _np(got["lambdas"])
+    _check_path(X, y, got, orc, lams, label=f"c1 dome {schedule}")
+    o = orc.lasso_path(X, y, lambdas=lams, rule="dome")
+    np.testing.assert_array_equal(_np(got["epochs"]), o["epochs"])
+    np.testing.assert_array_equal(_np(got["nactive"]), o["nactive"])
+    sph = orc.lasso_path(X, y, lambdas=lams, rule="sphere")
+    print(f"c1 dome [{schedule}]: epochs {int(o['epochs'].sum())} (sphere "
+          f"{int(sph['epochs'].sum())}), final active {int(o['nactive'].sum())} (sphere "
+          f"{int(sph['nactive'].sum())})")
+
+
 # -------------------------------------------------------------------- paths
 
 def _primal(Xf, yf, b, lam):

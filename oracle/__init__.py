@@ -121,7 +121,7 @@ class Oracle:
                              lam, ctypes.byref(P), ctypes.byref(D))
         return g, P.value, D.value
 
-    RULES = {"sphere": 0, "dome": 1}
+    RULES = {"sphere": 0, "dome": 1, "static": 2, "dynamic_safe": 3, "st3": 4}
 
     def screen(self, X, y, beta, lam, active=None, rule="sphere"):
         Xf, n, p = _design(X)

@@ -49,6 +49,20 @@
  *       the dual optimum).  A coordinate is kept when either test keeps it
  *       (the dome lies inside the sphere, so with exact arithmetic the dome
  *       alone decides).
+ *   R16 the comparison rules of Table 1 are sphere tests (Sec. 2.1) with:
+ *       static SAFE: center y/lambda, radius ||y|| |1/lambda - 1/lambda_max|
+ *       (Sec. 2.1 first example); Dynamic Safe: center y/lambda, radius
+ *       R_hat[theta_k] = ||theta_k - y/lambda|| (Sec. 2.3 example); Dynamic
+ *       ST3: the ball B(y/lambda, R_hat) cut by the half-space
+ *       s* x*^T theta <= 1 (x* = x_{j*}, j* the first index of the largest
+ *       |x_j^T y|, s* the sign of x*^T y), held in the ball around the
+ *       projection of y/lambda on that plane: center y/lambda - delta s* x*
+ *       with delta = (lambda_max/lambda - 1)/||x*||^2 (Table 1) and radius
+ *       (R_hat^2 - d^2)^(1/2) with d = (lambda_max/lambda - 1)/||x*||, the
+ *       distance to the plane (the remark after Proposition 1 writes this
+ *       d as delta; the two coincide for unit-norm columns).  For lambda >=
+ *       lambda_max ST3 falls back to the Dynamic Safe ball.  These rules
+ *       replace the GAP SAFE test; the gap still decides the stop.
  */
 #include <math.h>
 #include <stddef.h>
@@ -238,6 +252,29 @@ static int dome_keep_safe(double xty, double cj, double xn_up, double alpha,
   return mu >= 1.0 - 16.0 * ORC_U * scale;
 }
 
+/* Ingredients of the comparison rules (R16), computed once per problem. */
+typedef struct {
+  double lambda_max;   /* |x*^T y|                                         */
+  double sstar;        /* sign of x*^T y                                   */
+  double nstar;        /* ||x*||                                           */
+  const double* g;     /* p: x_j^T x*                                      */
+} orc_ref;
+
+/* j* = first index of max |x_j^T y|; g_j = x_j^T x*. */
+static void comparator_ingredients(int n, int p, int64_t ldx, const double* X,
+                                   const double* xty, const double* nrm2, double* g,
+                                   orc_ref* ref) {
+  int js = 0;
+  for (int j = 1; j < p; ++j)
+    if (fabs(xty[j]) > fabs(xty[js])) js = j;
+  const double* xs = X + (int64_t)js * ldx;
+  for (int j = 0; j < p; ++j) g[j] = col_dot(n, X + (int64_t)j * ldx, xs);
+  ref->lambda_max = fabs(xty[js]);
+  ref->sstar = xty[js] >= 0.0 ? 1.0 : -1.0;
+  ref->nstar = sqrt(nrm2[js]);
+  ref->g = g;
+}
+
 /* One screening pass at (beta, lambda) over the active set A (q entries):
  *   c_j = x_j^T rho for j in A,  M = max |c_j|           (Sec. 4.1)
  *   alpha = min(max(y^T rho / (lambda ||rho||^2), -1/M), 1/M)   (Sec. 2.3)
@@ -249,7 +286,7 @@ static int dome_keep_safe(double xty, double cj, double xn_up, double alpha,
  * rho (n) must hold y - X beta on entry (caller refreshes it). */
 static void pass_on_residual(int n, int64_t ldx, const double* X, const double* y,
                              const double* beta, const double* nrm2,
-                             const double* xty, int rule,
+                             const double* xty, int rule, const orc_ref* ref,
                              const int32_t* A, int q, int nnz, double lambda,
                              const double* rho, double* c_out,
                              uint8_t* keep_exact, uint8_t* keep_safe,
@@ -340,10 +377,49 @@ static void pass_on_residual(int n, int64_t ldx, const double* X, const double* 
                  (lambda * lambda) * (1.0 - 4.0 * ORC_U);
   if (rc2lo < 0.0) rc2lo = 0.0;
 
+  /* the comparison rules' spheres (R16): center term x_j^T c = xty_j/lambda
+   * - shift * g_j, radius r; with the bounds of their rounding */
+  double shift = 0.0, rad = 0.0, rad_s = 0.0, e_shift = 0.0;
+  if (rule >= 2) {
+    double lmx = ref->lambda_max;
+    double e_lm = gamma_m(n + 1) * ref->nstar * yn;
+    if (rule == 2) {
+      rad = sqrt(yy) * fabs(1.0 / lambda - 1.0 / lmx);
+      rad_s = yn * (fabs(1.0 / lambda - 1.0 / lmx) +
+                    (lmx > e_lm ? e_lm / (lmx * (lmx - e_lm)) : INFINITY)) *
+              (1.0 + 4.0 * ORC_U);
+    } else if (rule == 3 || !(lambda < lmx)) {
+      rad = Rh;
+      rad_s = Rhi;
+    } else {
+      double ratio = lmx / lambda - 1.0;
+      shift = ref->sstar * ratio / (ref->nstar * ref->nstar);
+      double dd = ratio / ref->nstar;
+      rad = sqrt(Rh * Rh - dd * dd > 0.0 ? Rh * Rh - dd * dd : 0.0);
+      double dlo = ((lmx - e_lm) / lambda - 1.0) / (ref->nstar * (1.0 + gamma_m(n + 2)));
+      if (dlo < 0.0) dlo = 0.0;
+      double r2s = Rhi * Rhi * (1.0 + 4.0 * ORC_U) - dlo * dlo * (1.0 - 4.0 * ORC_U);
+      rad_s = sqrt(r2s > 0.0 ? r2s : 0.0) * (1.0 + 4.0 * ORC_U);
+      /* |error of the computed shift| times |g_j| <= ||x_j|| ||x*|| */
+      e_shift = (e_lm / lambda / (ref->nstar * ref->nstar) + 8.0 * ORC_U * fabs(shift)) *
+                ref->nstar;
+    }
+  }
+
   for (int k = 0; k < q; ++k) {
     int j = A[k];
     double xn = sqrt(nrm2[j]);
     double xn_up = xn * (1.0 + gamma_m(n + 2));
+    if (rule >= 2) {
+      double cx = xty[j] / lambda - shift * ref->g[j];
+      keep_exact[k] = (nrm2[j] > 0.0 && fabs(cx) + rad * xn >= 1.0) ? 1 : 0;
+      double e_cx = gamma_m(n + 1) * xn_up * yn / lambda + e_shift * xn_up +
+                    fabs(shift) * gamma_m(n + 1) * xn_up * ref->nstar +
+                    4.0 * ORC_U * (fabs(xty[j] / lambda) + fabs(shift * ref->g[j]));
+      keep_safe[k] =
+          (nrm2[j] > 0.0 && fabs(cx) + e_cx + rad_s * xn_up >= 1.0 - 4.0 * ORC_U) ? 1 : 0;
+      continue;
+    }
     double mu = fabs(alpha * c_out[k]) + radius * xn;
     keep_exact[k] = (nrm2[j] > 0.0 && mu >= 1.0) ? 1 : 0;
     double mu_s = fabs(alpha_s * c_out[k]) + fabs(alpha_s) * e_c * xn_up +
@@ -381,7 +457,8 @@ int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
                const double* beta, double lambda, const int32_t* active_in,
                int q_in, int rule, double* c_out, uint8_t* keep_exact,
                uint8_t* keep_safe, double* scalars /* 10: see orc_pass_info */) {
-  if (n <= 0 || p <= 0 || ldx < n || !(lambda > 0.0)) return ORC_EINVAL;
+  if (n <= 0 || p <= 0 || ldx < n || !(lambda > 0.0) || rule < 0 || rule > 4)
+    return ORC_EINVAL;
   int q = active_in ? q_in : p;
   int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)(q > 0 ? q : 1));
   double* rho = (double*)malloc(sizeof(double) * (size_t)n);
@@ -397,11 +474,18 @@ int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
     nrm2[j] = col_dot(n, xj, xj);
     xty[j] = col_dot(n, xj, y);
   }
+  double* g = (double*)malloc(sizeof(double) * (size_t)p);
+  if (!g) {
+    free(A); free(rho); free(nrm2); free(xty);
+    return ORC_ENOMEM;
+  }
+  orc_ref ref;
+  comparator_ingredients(n, p, ldx, X, xty, nrm2, g, &ref);
   int nnz = 0;
   for (int j = 0; j < p; ++j) nnz += beta[j] != 0.0;
   residual(n, p, ldx, X, y, beta, rho);
   orc_pass_info info;
-  pass_on_residual(n, ldx, X, y, beta, nrm2, xty, rule, A, q, nnz, lambda, rho, c_out,
+  pass_on_residual(n, ldx, X, y, beta, nrm2, xty, rule, &ref, A, q, nnz, lambda, rho, c_out,
                    keep_exact, keep_safe, &info);
   scalars[0] = info.gap;
   scalars[1] = info.alpha;
@@ -413,7 +497,7 @@ int orc_screen(int n, int p, int64_t ldx, const double* X, const double* y,
   scalars[7] = info.l1;
   scalars[8] = info.alpha_s;
   scalars[9] = info.err_gap;
-  free(A); free(rho); free(nrm2); free(xty);
+  free(A); free(rho); free(nrm2); free(xty); free(g);
   return q;
 }
 
@@ -439,7 +523,7 @@ int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
                    int32_t* status_out, int32_t* passes_out, uint8_t* screened,
                    double* lambdas_out) {
   if (n <= 0 || p <= 0 || ldx < n || T <= 0 || f < 1 || K < 0 ||
-      !(eps_rel > 0.0) || rule < 0 || rule > 1)
+      !(eps_rel > 0.0) || rule < 0 || rule > 4)
     return ORC_EINVAL;
   double *nrm2 = malloc(sizeof(double) * p), *xty = malloc(sizeof(double) * p);
   double *rho = malloc(sizeof(double) * n), *beta = malloc(sizeof(double) * p);
@@ -453,6 +537,14 @@ int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
   }
   double lambda_max, ynorm2;
   orc_precompute(n, p, ldx, X, y, nrm2, xty, &lambda_max, &ynorm2);
+  double* gst = malloc(sizeof(double) * p);
+  if (!gst) {
+    free(nrm2); free(xty); free(rho); free(beta); free(c); free(lam);
+    free(A); free(ke); free(ks);
+    return ORC_ENOMEM;
+  }
+  orc_ref ref;
+  comparator_ingredients(n, p, ldx, X, xty, nrm2, gst, &ref);
   if (lambdas == NULL) {
     orc_grid(lambda_max, T, delta, lam);
   } else {
@@ -466,7 +558,7 @@ int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
   }
   if (bad) {
     free(nrm2); free(xty); free(rho); free(beta); free(c); free(lam);
-    free(A); free(ke); free(ks);
+    free(A); free(ke); free(ks); free(gst);
     return ORC_EINVAL;
   }
   if (lambdas_out) memcpy(lambdas_out, lam, sizeof(double) * T);
@@ -488,7 +580,7 @@ int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
         for (int j = 0; j < p; ++j) nnz += beta[j] != 0.0;
         residual(n, p, ldx, X, y, beta, rho);
         orc_pass_info info;
-        pass_on_residual(n, ldx, X, y, beta, nrm2, xty, rule, A, q, nnz, lambda, rho, c,
+        pass_on_residual(n, ldx, X, y, beta, nrm2, xty, rule, &ref, A, q, nnz, lambda, rho, c,
                          ke, ks, &info);
         ++passes;
         G = info.gap;
@@ -540,6 +632,6 @@ int orc_lasso_path(int n, int p, int64_t ldx, const double* X, const double* y,
     if (passes_out) passes_out[t] = passes;
   }
   free(nrm2); free(xty); free(rho); free(beta); free(c); free(lam);
-  free(A); free(ke); free(ks);
+  free(A); free(ke); free(ks); free(gst);
   return any_nc ? ORC_NOT_CONVERGED : ORC_OK;
 }

@@ -43,6 +43,10 @@ MUTANTS = {
                             "  double wx = (alpha * cj - xty / lambda) / Rh;\n  double mu_p"),
     "dome_drops_ratio_factor": ("double s2 = (xn * xn - wx * wx) * (1.0 - a * a);",
                                 "double s2 = (xn * xn - wx * wx);"),
+    "st3_center_on_wrong_side": ("      shift = ref->sstar * ratio / (ref->nstar * ref->nstar);",
+                                 "      shift = -ref->sstar * ratio / (ref->nstar * ref->nstar);"),
+    "static_radius_drops_lambda_max": ("      rad = sqrt(yy) * fabs(1.0 / lambda - 1.0 / lmx);",
+                                       "      rad = sqrt(yy) * fabs(1.0 / lambda - 1.0 / (2.0 * lmx));"),
     "screen_drops_zero_test": ("keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.0 - 4.0 * ORC_U) ? 1 : 0;",
                                "keep_safe[k] = (nrm2[j] > 0.0 && mu_s >= 1.5) ? 1 : 0;"),
 }
@@ -68,6 +72,9 @@ checks = [
   lambda: T.test_rounding_bound_covers_cancelling_y_rho(orc),
   lambda: T.test_dome_support_matches_brute_force(orc),
   lambda: T.test_dome_contains_dual_optimum_and_lies_in_sphere(orc),
+  lambda: T.test_comparison_rules_hold_dual_optimum(orc, "st3"),
+  lambda: T.test_comparison_rules_hold_dual_optimum(orc, "static"),
+  lambda: T.test_static_safe_critical_ratio(orc),
 ]
 failed = 0
 for c in checks:          # one failing pin is enough

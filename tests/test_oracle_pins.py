@@ -538,3 +538,90 @@ def test_dome_path_is_safe_and_matches_sphere_path(orc):
         assert np.linalg.norm(d) <= np.sqrt(2 * dome["gap"][t]) + np.sqrt(2 * sph["gap"][t]) + 1e-12
     # the dome never keeps more than the sphere at the first pass of a lambda
     assert dome["nactive"].sum() <= sph["nactive"].sum()
+
+
+# ------------------------------------------------ comparison rules (Table 1)
+
+def _rule_ball(X, y, beta, lam, alpha, rule):
+    """Center and radius of the comparison rules of Table 1 from their
+    definitions: static SAFE B(y/lambda, ||y|| |1/lambda - 1/lambda_max|)
+    (Sec. 2.1), Dynamic Safe B(y/lambda, ||theta - y/lambda||) (Sec. 2.3),
+    Dynamic ST3: B(y/lambda, R_hat) cut by s* x*^T t <= 1, held in the ball
+    around the projection of y/lambda on that plane."""
+    xty = X.T @ y
+    js = int(np.argmax(np.abs(xty)))
+    lmax, s = abs(xty[js]), np.sign(xty[js])
+    xs = X[:, js]
+    theta = alpha * (y - X @ beta)
+    R = np.linalg.norm(theta - y / lam)
+    if rule == "static":
+        return y / lam, np.linalg.norm(y) * abs(1 / lam - 1 / lmax)
+    if rule == "dynamic_safe" or lam >= lmax:
+        return y / lam, R
+    # projection of y/lambda on the plane s x*^T t = 1
+    h = (s * xs @ (y / lam) - 1.0) / (xs @ xs)
+    center = y / lam - h * s * xs
+    dist = np.linalg.norm(center - y / lam)
+    return center, np.sqrt(max(R * R - dist * dist, 0.0))
+
+
+@pytest.mark.parametrize("rule", ["static", "dynamic_safe", "st3"])
+def test_comparison_rules_hold_dual_optimum(orc, rule):
+    """Each comparison region of Table 1 holds theta_hat (from a tight
+    solve), and the oracle's exact kept set for the rule is the sphere test
+    of that region; the rounding-safe kept set contains it."""
+    for seed in (31, 32):
+        X, y = _small_c1_like(seed=seed, n=20, p=80)
+        lmax = np.abs(X.T @ y).max()
+        for ratio in (0.9, 0.5, 0.2):
+            lam = ratio * lmax
+            tight = orc.lasso_path(X, y, lambdas=[lam], eps_rel=1e-15, K=10_000_000)
+            th = (y - X @ tight["beta"][0]) / lam
+            for K in (0, 3, 20):
+                b = orc.lasso_path(X, y, lambdas=[lam], K=K, eps_rel=1e-30)["beta"][0]
+                o = orc.screen(X, y, b, lam, rule=rule)
+                c, r = _rule_ball(X, y, b, lam, o["alpha"], rule)
+                assert np.linalg.norm(th - c) <= r * (1 + 1e-9) + 1e-12, (rule, ratio, K)
+                mu = np.abs(X.T @ c) + r * np.linalg.norm(X, axis=0)
+                sure = (mu >= 1 + 1e-9) | (mu < 1 - 1e-9)
+                assert np.array_equal(o["keep_exact"][sure], (mu >= 1)[sure])
+                assert np.all(o["keep_safe"] >= o["keep_exact"])
+
+
+def test_static_safe_critical_ratio(orc):
+    """Sec. 2.1, first example: the static SAFE rule screens nothing once
+    lambda/lambda_max <= min_j (1 + |x_j^T y|/(||x_j|| ||y||)) /
+    (1 + lambda_max/(||x_j|| ||y||)), and at lambda = lambda_max it keeps
+    only the columns reaching the maximum."""
+    X, y = _small_c1_like(seed=33, n=30, p=200)
+    xty = X.T @ y
+    lmax = np.abs(xty).max()
+    xn = np.linalg.norm(X, axis=0)
+    yn = np.linalg.norm(y)
+    crit = np.min((1 + np.abs(xty) / (xn * yn)) / (1 + lmax / (xn * yn)))
+    below = orc.screen(X, y, np.zeros(200), crit * lmax * (1 - 1e-6), rule="static")
+    assert below["keep_exact"].all()
+    above = orc.screen(X, y, np.zeros(200), crit * lmax * (1 + 1e-3), rule="static")
+    assert not above["keep_exact"].all()
+    at = orc.screen(X, y, np.zeros(200), lmax, rule="static")
+    assert np.array_equal(np.flatnonzero(at["keep_exact"]),
+                          np.flatnonzero(np.abs(xty) >= lmax))
+
+
+@pytest.mark.parametrize("rule", ["static", "dynamic_safe", "st3"])
+def test_comparison_rule_paths_are_safe(orc, rule):
+    """Algorithm 1 with each comparison rule: certified, every screened
+    coordinate is zero at the tight solution, and the path agrees with the
+    GAP SAFE one within the gap bound."""
+    X, y = _small_c1_like(seed=34, n=40, p=300)
+    lmax = np.abs(X.T @ y).max()
+    lams = lmax * 10 ** (-np.arange(10) / 9 * 1.5)
+    got = orc.lasso_path(X, y, lambdas=lams, rule=rule, want_screened=True)
+    gap = orc.lasso_path(X, y, lambdas=lams, rule="sphere")
+    tight = orc.lasso_path(X, y, lambdas=lams, eps_rel=1e-15, K=10_000_000)
+    assert np.all(got["status"] == 0)
+    for t in range(len(lams)):
+        scr = got["screened"][t].astype(bool)
+        assert np.all(tight["beta"][t][scr] == 0)
+        d = X @ (got["beta"][t] - gap["beta"][t])
+        assert np.linalg.norm(d) <= np.sqrt(2 * got["gap"][t]) + np.sqrt(2 * gap["gap"][t]) + 1e-12

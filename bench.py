@@ -364,6 +364,40 @@ def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
     return res
 
 
+def bench_screening(gs, torch, synth, Ks=(10, 50, 200)):
+    """The proportion of active variables against lambda and the epoch budget
+    K (the paper's Fig. 3, on the 72 x 7129 workload): for every rule and K,
+    a 100-lambda path (down to lambda_max/1000, warm starts) whose lambdas
+    each stop after K epochs or at gap <= 1e-8 ||y||^2; reported is |A|/p at
+    the exit of every lambda (wide schedule, so every rule runs the same
+    kernels)."""
+    import numpy as np
+    d = synth.c1()
+    Xd = gs.colmajor_to_device(d["X"])
+    yd = torch.from_numpy(d["y"]).cuda()
+    p = d["X"].shape[1]
+    rules = ["sphere", "dome", "static", "dynamic_safe", "st3"]
+    out = {"workload": "c1 72x7129, T=100 grid lambda_max..lambda_max/1000, warm starts, "
+                       "at most K epochs per lambda; |A|/p at each lambda's exit",
+           "K": list(Ks), "lambda_ratio": [round(float(1e-3 ** (t / 99)), 6) for t in range(100)],
+           "proportion": {}}
+    t0 = time.perf_counter()
+    for rule in rules:
+        out["proportion"][rule] = {}
+        for K in Ks:
+            r = gs.lasso_path(Xd, yd, T=100, lambda_min_ratio=1e-3, max_epochs=K, rule=rule,
+                              schedule="wide")
+            na = r["nactive"].cpu().numpy()
+            out["proportion"][rule][str(K)] = [round(float(v) / p, 4) for v in na]
+    out["seconds"] = round(time.perf_counter() - t0, 2)
+    # lambdas (of 100) at which each rule keeps under half of the columns,
+    # at the largest K
+    kmax = str(Ks[-1])
+    out["lambdas_below_half"] = {r: int((np.array(out["proportion"][r][kmax]) < 0.5).sum())
+                                 for r in rules}
+    return out
+
+
 def copy_calibration(torch, mb, reps):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     nel = int(mb * 1e6) // 4
@@ -411,6 +445,8 @@ def main():
                     help="lambdas of the 100-point c4 grid solved by the plain path")
     ap.add_argument("--c4-learned-lambdas", type=int, default=70,
                     help="lambdas solved by the learned warm start (0: none)")
+    ap.add_argument("--no-screening", action="store_true",
+                    help="skip the screening-proportion comparison of the safe rules")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of the c3 CPU pool sample")
     ap.add_argument("--copy-mb", type=float, default=0.0,
@@ -469,6 +505,12 @@ def main():
         _log("c4: 1000x100000 path, plain and learned warm starts")
         pf = a.c4_params if a.c4_params and os.path.exists(a.c4_params) else None
         c4 = bench_c4(gs, torch, d4, pf, a.c4_piece, a.c4_lambdas, a.c4_learned_lambdas)
+    scr = None
+    if not a.no_screening:
+        _log("screening proportion: five safe rules on the c1 path")
+        scr = bench_screening(gs, torch, synth)
+        _log(f"screening: {scr['seconds']} s, lambdas under half active "
+             f"{scr['lambdas_below_half']}")
     cpu = None
     if not a.no_cpu:
         _log("cpu baseline: oracle, whole c1 path")
@@ -478,7 +520,7 @@ def main():
                          "FP64 C oracle, one thread"}
     if path is None:
         print(json.dumps({"roofline": roof, "batched": {"c2": c2, "c3": c3},
-                          "learned_warm_start": c4}), flush=True)
+                          "learned_warm_start": c4, "screening_proportion": scr}), flush=True)
         return
     line = {
         "metric": "Lasso path seconds to gap\u22641e-8\u2016y\u2016\u00b2; X\u1d40\u03b8 HBM GB/s; "
@@ -510,6 +552,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": {"c2": c2, "c3": c3},
         "learned_warm_start": c4,
+        "screening_proportion": scr,
     }
     print(json.dumps(line), flush=True)
 

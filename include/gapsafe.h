@@ -99,7 +99,7 @@ enum {
 enum {
   GS_RULE_SPHERE = 0, /* GAP SAFE sphere B(theta, sqrt(2 gap)/lambda)
                          (Sec. 3.2, Proposition 1)                        */
-  GS_RULE_DOME = 1    /* the sphere test and the GAP SAFE dome test (Sec. 3.2
+  GS_RULE_DOME = 1,   /* the sphere test and the GAP SAFE dome test (Sec. 3.2
                          dome equation, appendix dome support function): the
                          ball of diameter [theta, y/lambda] cut by the plane
                          through its intersection with the sphere of radius
@@ -109,6 +109,21 @@ enum {
                          input is replaced by a bound that enlarges the dome
                          under rounding.  A coordinate is dropped when either
                          test drops it.                                    */
+  /* The comparison rules of Table 1, sphere tests that replace the GAP SAFE
+   * test (the duality gap still decides the stop).  They run on the wide
+   * schedule only (lasso_path moves to it; lasso_solve_batch and screen()
+   * return GS_EUNSUPPORTED): */
+  GS_RULE_STATIC = 2,  /* static SAFE: B(y/lambda, ||y|| |1/lambda -
+                          1/lambda_max|) (Sec. 2.1)                         */
+  GS_RULE_DYNSAFE = 3, /* Dynamic Safe: B(y/lambda, ||theta_k - y/lambda||)
+                          (Sec. 2.3)                                        */
+  GS_RULE_ST3 = 4      /* Dynamic ST3: B(y/lambda, R_hat) cut by the plane
+                          s* x*^T theta = 1 (x* the column of largest
+                          |x_j^T y|, s* its sign), held in the ball around the
+                          projection of y/lambda on the plane: center
+                          y/lambda - s* (lambda_max/lambda - 1) x* / ||x*||^2,
+                          radius (R_hat^2 - d^2)^(1/2), d the distance to the
+                          plane (Table 1)                                   */
 };
 
 /* Counters of gs_opts.stats (indices). */

@@ -29,7 +29,7 @@ GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED, GS_ETOOLARGE = -1, -2, -3, -
 NOALLOC_SCRATCH_BYTES = 16 << 20  # GS_NOALLOC_SCRATCH_BYTES
 SCHEDULES = {"auto": 0, "narrow": 1, "wide": 2}
 CD_MODES = {"auto": 0, "residual": 1}
-RULES = {"sphere": 0, "dome": 1}
+RULES = {"sphere": 0, "dome": 1, "static": 2, "dynamic_safe": 3, "st3": 4}
 
 
 class GsError(RuntimeError):

@@ -90,7 +90,7 @@ int check_opts(const gs_opts* o) {
   if (o->screen_every < 1 || o->max_epochs < 0) return GS_EINVAL;
   if (o->schedule < GS_SCHED_AUTO || o->schedule > GS_SCHED_WIDE) return GS_EINVAL;
   if (o->cd_mode < GS_CD_AUTO || o->cd_mode > GS_CD_RESIDUAL) return GS_EINVAL;
-  if (o->rule != GS_RULE_SPHERE && o->rule != GS_RULE_DOME) return GS_EINVAL;
+  if (o->rule < GS_RULE_SPHERE || o->rule > GS_RULE_ST3) return GS_EINVAL;
   return GS_OK;
 }
 
@@ -158,6 +158,7 @@ const WideEntry* pick_wide(const gs_problem* pr) {
 bool use_wide(const gs_problem* pr, const gs_opts* o) {
   if (pr->rows) return false;  // the wide kernels read contiguous rows only
   if (o->schedule == GS_SCHED_WIDE) return true;
+  if (o->rule >= GS_RULE_STATIC) return true;  // comparison rules: wide schedule only
   if (o->schedule == GS_SCHED_NARROW) return false;
   return (double)pr->n * (double)pr->p > kWideThreshold;
 }
@@ -177,6 +178,7 @@ void carve_problem(Carver& cv, const gs_problem* pr, ProbDesc* d) {
   const int ns = pattern_slots(pr);
   d->nrm2 = cv.take<double>(pr->p);
   d->xty = cv.take<double>(pr->p);
+  d->gst = cv.take<double>(pr->p);
   d->inv = cv.take<double>(pr->p);
   d->beta = cv.take<double>(pr->p);
   d->c = cv.take<double>(ldg);
@@ -378,6 +380,10 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
     int npre = kWidePreBlocks;
     void* b[] = {&d, &st, &wb, &npre, &po};
     HIPCHK(launch(kWideInit[dt], dim3(1), dim3(256), b, 0, s));
+    if (o->rule == GS_RULE_ST3) {
+      void* g[] = {&d, &st};
+      HIPCHK(launch(w->gstar_kernel, dim3(kWidePreBlocks), dim3(64 * kSweepWaves), g, 0, s));
+    }
   }
   const int ntest = (pr->p + kTestTile - 1) / kTestTile;
   int nsweep = kWideSweepBlocks;
@@ -466,6 +472,7 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   if (!probs || B < 1 || !o) return GS_EINVAL;
   int rc = check_opts(o);
   if (rc) return rc;
+  if (o->rule >= GS_RULE_STATIC) return GS_EUNSUPPORTED;  // wide schedule only
   for (int b = 0; b < B; ++b) {
     rc = check_problem(&probs[b]);
     if (rc) return rc;
@@ -661,6 +668,7 @@ int check_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X
   if (!X || !y || !beta || !active_out || !q_out || !gap_out || !alpha_out || !radius_out)
     return GS_EINVAL;
   if (!finite_pos(lambda)) return GS_EINVAL;
+  if (rule >= GS_RULE_STATIC && rule <= GS_RULE_ST3) return GS_EUNSUPPORTED;
   if (rule != GS_RULE_SPHERE && rule != GS_RULE_DOME) return GS_EINVAL;
   if (active_in && (q_in < 0 || q_in > p)) return GS_EINVAL;
   if (n > kMaxN) return GS_EUNSUPPORTED;

@@ -265,12 +265,16 @@ struct GapInfo {
   double alpha, gap, radius, e_c;
   double lambda, Rlo, Rhi, rc2lo, e_y;
   bool dome;
+  // comparison rules (Table 1), rule 2-4: sphere test with center term
+  // x_j^T y/lambda - shift x_j^T x_{j*} and radius rad_s (rounding-safe)
+  int rule;
+  double shift, rad_s, e_shift, nstar;
 };
 
 __device__ __forceinline__ GapInfo gap_safe(double R2, double Ry, double l1, double sbx,
                                             double xmax, double M, int nnz, int n,
                                             double lambda, double ynorm, int q = 0,
-                                            bool dome = false) {
+                                            bool dome = false, bool rule_ball = false) {
   GapInfo g;
   const double up = 1.0 + gam(n + 2);
   const double rnorm = sqrt(R2) * up;
@@ -292,8 +296,10 @@ __device__ __forceinline__ GapInfo gap_safe(double R2, double Ry, double l1, dou
   g.radius = sqrt(2.0 * (fmax(g.gap, 0.0) + errG)) / lambda * (1.0 + 4.0 * kU);
   g.lambda = lambda;
   g.dome = dome;
+  g.rule = dome ? 1 : 0;
+  g.shift = g.rad_s = g.e_shift = g.nstar = 0.0;
   g.Rlo = g.Rhi = g.rc2lo = g.e_y = 0.0;
-  if (dome) {
+  if (dome || rule_ball) {
     const double yy = ynorm * ynorm, il = 1.0 / lambda, il2 = il * il;
     const double yn = ynorm * up;
     const double Rs2 = a * a * R2 - 2.0 * a * Ry * il + yy * il2;
@@ -308,6 +314,49 @@ __device__ __forceinline__ GapInfo gap_safe(double R2, double Ry, double l1, dou
     g.e_y = gam(n + 1) * yn * il;
   }
   return g;
+}
+
+// The comparison rules of Table 1 as sphere tests (rule 2 static SAFE:
+// B(y/lambda, ||y|| |1/lambda - 1/lambda_max|); rule 3 Dynamic Safe:
+// B(y/lambda, R_hat); rule 4 Dynamic ST3: B(y/lambda, R_hat) cut by the plane
+// s* x*^T t = 1, held in the ball around the projection of y/lambda on it:
+// center y/lambda - shift x*, shift = s* (lambda_max/lambda - 1)/||x*||^2,
+// radius (R_hat^2 - d^2)^(1/2), d = (lambda_max/lambda - 1)/||x*||).  The
+// radius is rounding-safe (R_hat by Rhi, lambda_max and d by lower bounds);
+// e_shift bounds the error of the computed shift per unit ||x_j||.
+__device__ __forceinline__ void rule_ball(GapInfo& g, int rule, double lmax, double sstar,
+                                          double nstar, double ynorm, int n) {
+  g.rule = rule;
+  g.nstar = nstar;
+  const double yn = ynorm * (1.0 + gam(n + 2));
+  const double e_lm = gam(n + 1) * nstar * yn;
+  const double lambda = g.lambda;
+  if (rule == 2) {
+    g.rad_s = yn *
+              (fabs(1.0 / lambda - 1.0 / lmax) +
+               (lmax > e_lm ? e_lm / (lmax * (lmax - e_lm)) : INFINITY)) *
+              (1.0 + 4.0 * kU);
+  } else if (rule == 3 || !(lambda < lmax)) {
+    g.rad_s = g.Rhi;
+  } else {
+    const double ratio = lmax / lambda - 1.0;
+    g.shift = sstar * ratio / (nstar * nstar);
+    const double dlo = fmax(((lmax - e_lm) / lambda - 1.0) / (nstar * (1.0 + gam(n + 2))), 0.0);
+    g.rad_s = sqrt(fmax(g.Rhi * g.Rhi * (1.0 + 4.0 * kU) - dlo * dlo * (1.0 - 4.0 * kU), 0.0)) *
+              (1.0 + 4.0 * kU);
+    g.e_shift = (e_lm / lambda / (nstar * nstar) + 8.0 * kU * fabs(g.shift)) * nstar;
+  }
+}
+
+__device__ __forceinline__ bool rule_keep(const GapInfo& g, double xty, double gj, double nrm2,
+                                          int n) {
+  if (!(nrm2 > 0.0)) return false;
+  const double xn = sqrt(nrm2) * (1.0 + gam(n + 2));
+  const double yl = xty / g.lambda, sg = g.shift * gj;
+  const double cx = yl - sg;
+  const double e = g.e_y * xn + g.e_shift * xn + fabs(g.shift) * gam(n + 1) * xn * g.nstar +
+                   4.0 * kU * (fabs(yl) + fabs(sg));
+  return fabs(cx) + e + g.rad_s * xn >= 1.0 - 4.0 * kU;
 }
 
 // Support function of the dome at x given c^T x (cx), w^T x (wx) and ||x||:

@@ -33,7 +33,8 @@ struct ProbDesc {
   double* lam;    // T: the absolute lambdas of the path (set by the kernels)
   double* lam_in; // T: caller lambdas (absolute or relative), read only
   double* rho;    // n: residual (wide schedule)
-  double* xty;    // p: x_j^T y (the dome test)
+  double* xty;    // p: x_j^T y (the dome test, the comparison rules)
+  double* gst;    // p: x_j^T x_{j*} (the Dynamic ST3 rule)
   // pattern mode of the narrow schedule; the arrays hold ldg entries, so
   // that 256-position tiles never leave them
   float* gc;        // ns x ldg: Gram columns by slot, row j = feature j
@@ -77,7 +78,8 @@ struct PathOpts {
   int32_t lds_cap;         // floats of LDS for staging the active coefficients
   int32_t pattern;         // 1: pattern mode allowed, 0: residual mode only
   int32_t gs_cap;          // floats of LDS for the support's Gram block
-  int32_t rule;            // 0: GAP SAFE sphere, 1: sphere and GAP SAFE dome
+  int32_t rule;            // 0: GAP SAFE sphere, 1: sphere and GAP SAFE dome,
+                           // 2-4: static SAFE, Dynamic Safe, Dynamic ST3
   int32_t* select_counts;  // T x p or null
   long long* timestamps;   // 2B or null
   long long* stats;        // kNumStats or null
@@ -112,7 +114,9 @@ struct WideState {
   double pb2;  // 2 P(beta) at the last pass: bounds ||rho||^2 of the CD iterates
   // dome parameters of the last pass (rule 1)
   double Rlo, Rhi, rc2lo, e_y;
-  int32_t rule, pad2_;
+  int32_t rule, jstar;
+  // comparison rules (rules 2-4): x_{j*} and the sphere of the last pass
+  double sstar, nstar, shift, rad_s, e_shift;
   long long n_visits, n_rounds, n_stops, n_epochs;
 };
 

@@ -18,6 +18,7 @@ struct WideEntry {
   const void* sweep_nrm_kernel;  // k_wide_sweep<..., 1>: also ||x_j||^2
   const void* sweep_nxy_kernel;  // k_wide_sweep<..., 2>: also ||x_j||^2 and x_j^T y
   const void* csweep_kernel;     // k_wide_csweep<...>: c from the resume position
+  const void* gstar_kernel;      // k_wide_gstar<...>: x_j^T x_{j*} (Dynamic ST3)
   const void* walk_kernel;       // k_wide_walk<...>: the CD epoch on one wave
   int nmax() const { return 64 * NG * vec; }
 };

@@ -17,12 +17,19 @@ __device__ __forceinline__ GapInfo state_gap(const ProbDesc& d, const WideState*
   g.rc2lo = st->rc2lo;
   g.e_y = st->e_y;
   g.dome = st->rule == 1;
+  g.rule = st->rule;
+  g.shift = st->shift;
+  g.rad_s = st->rad_s;
+  g.e_shift = st->e_shift;
+  g.nstar = st->nstar;
   return g;
 }
 
-// The sphere test, and the dome test where it is on (each is safe alone).
+// The GAP SAFE sphere test, and the dome test where it is on (each is safe
+// alone); or one of the comparison rules of Table 1 in their place.
 __device__ __forceinline__ bool wide_keep(const ProbDesc& d, const GapInfo& g, int j, double c) {
   const double nr = d.nrm2[j];
+  if (g.rule >= 2) return rule_keep(g, d.xty[j], g.rule == 4 ? d.gst[j] : 0.0, nr, d.n);
   return sphere_keep(g, c, nr, d.n) && (!g.dome || dome_keep(g, d.xty[j], c, nr, d.n));
 }
 
@@ -264,6 +271,7 @@ const void* const kWideStats = reinterpret_cast<const void*>(&k_wide_stats);
         reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, 1>),           \
         reinterpret_cast<const void*>(&k_wide_sweep<XT, VEC, NG, 2>),           \
         reinterpret_cast<const void*>(&k_wide_csweep<XT, VEC, NG>),             \
+        reinterpret_cast<const void*>(&k_wide_gstar<XT, VEC, NG>),              \
         reinterpret_cast<const void*>(&k_wide_walk<XT, VEC, NG>)                \
   }
 

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_pre(ProbDesc d, WideB
   const int wid = blockIdx.x * kSweepWaves + w;
   const uint64_t mk = L::rowmask(lane, d.n);
   double mx = 0.0, bad = 0.0;
+  int jm = 0x7fffffff;  // first column reaching mx
   for (int j = wid; j < d.p; j += W) {
     XT xv[RPL];
     L::load(X + (int64_t)j * d.ldx, d.n, lane, nullptr, mk, xv);
@@ -103,15 +104,46 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_pre(ProbDesc d, WideB
       d.nrm2[j] = s2;
       d.inv[j] = s2 > 0.0 ? 1.0 / s2 : 0.0;
       d.xty[j] = sy;
-      mx = fmax(mx, fabs(sy));
+      if (fabs(sy) > mx || (fabs(sy) == mx && j < jm)) {
+        mx = fabs(sy);
+        jm = j;
+      }
       if (!isfinite(s2) || !isfinite(sy)) bad = 1.0;
     }
   }
-  mx = block_max<64 * kSweepWaves>(mx, sh);
+  const double bmx = block_max<64 * kSweepWaves>(mx, sh);
   bad = block_max<64 * kSweepWaves>(bad, sh);
+  // first column of the block reaching its maximum
+  const double jb = block_max<64 * kSweepWaves>(
+      (lane == 0 && mx == bmx && jm != 0x7fffffff) ? -(double)jm : -INFINITY, sh);
   if (threadIdx.x == 0) {
-    wb.part[4 * blockIdx.x + 0] = mx;
+    wb.part[4 * blockIdx.x + 0] = bmx;
     wb.part[4 * blockIdx.x + 1] = bad;
+    wb.part[4 * blockIdx.x + 2] = -jb;
+  }
+}
+
+// ---- x_j^T x_{j*} for every column (the Dynamic ST3 rule only).
+template <typename XT, int VEC, int NG>
+__global__ __launch_bounds__(64 * kSweepWaves) void k_wide_gstar(ProbDesc d, WideState* st) {
+  using L = ColLayout<XT, VEC, 64, NG, false>;
+  constexpr int RPL = L::RPL;
+  if (st->rule != 4 || st->done) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const XT* X = (const XT*)d.X;
+  const uint64_t mk = L::rowmask(lane, d.n);
+  XT xs[RPL];
+  L::load(X + (int64_t)st->jstar * d.ldx, d.n, lane, nullptr, mk, xs);
+  const int W = gridDim.x * kSweepWaves;
+  const int wid = blockIdx.x * kSweepWaves + w;
+  for (int j = wid; j < d.p; j += W) {
+    XT xv[RPL];
+    L::load(X + (int64_t)j * d.ldx, d.n, lane, nullptr, mk, xv);
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) a = fma((double)xv[i], (double)xs[i], a);
+    a = wave_sum(a);
+    if (lane == 0) d.gst[j] = a;
   }
 }
 
@@ -126,6 +158,12 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
     mx = fmax(mx, wb.part[4 * b]);
     bad = fmax(bad, wb.part[4 * b + 1]);
   }
+  __shared__ double shj[256];
+  const double gmx = block_max<256>(mx, shj);
+  double jneg = -INFINITY;
+  for (int b = threadIdx.x; b < npre; b += 256)
+    if (wb.part[4 * b] == gmx) jneg = fmax(jneg, -wb.part[4 * b + 2]);
+  const int jstar = (int)(-block_max<256>(jneg, shj));
   for (int i = threadIdx.x; i < d.n; i += 256) {
     double v = (double)Y[i];
     yy = fma(v, v, yy);
@@ -172,6 +210,9 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
     st->nonfinite = (bad != 0.0) ? 1 : 0;
     st->resume = 0;
     st->rule = opts.rule;
+    st->jstar = (jstar >= 0 && jstar < d.p) ? jstar : 0;
+    st->sstar = d.xty[st->jstar] >= 0.0 ? 1.0 : -1.0;
+    st->nstar = sqrt(d.nrm2[st->jstar]);
     st->first_epoch = 1;
     st->tau = INFINITY;
     st->tau_first = INFINITY;
@@ -376,12 +417,17 @@ __global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, Wid
   const int t = st->t;
   const double lambda = d.lam[t];
   GapInfo g = gap_safe(st->R2, st->Ry, l1, sb, xm, M, st->nnz, d.n, lambda, sqrt(st->ynorm2),
-                       st->q, st->rule == 1);
+                       st->q, st->rule == 1, st->rule >= 2);
+  if (st->rule >= 2)
+    rule_ball(g, st->rule, st->lambda_max, st->sstar, st->nstar, sqrt(st->ynorm2), d.n);
   if (threadIdx.x == 0) {
     st->Rlo = g.Rlo;
     st->Rhi = g.Rhi;
     st->rc2lo = g.rc2lo;
     st->e_y = g.e_y;
+    st->shift = g.shift;
+    st->rad_s = g.rad_s;
+    st->e_shift = g.e_shift;
   }
   if (mode == 1) {
     if (threadIdx.x == 0) {

@@ -125,11 +125,16 @@ def test_screen_invalid(lib):
     vp = ctypes.c_void_p(4096)
     args = [8, 20, 8, gs.GS_F32, vp, vp, vp, 0.5, 0, None, 0, vp, vp, vp, vp, vp, None, vp, 1 << 30,
             None]
-    for idx, val in [(0, 0), (2, 4), (3, 5), (7, 0.0), (7, float("inf")), (4, None), (8, 2),
+    for idx, val in [(0, 0), (2, 4), (3, 5), (7, 0.0), (7, float("inf")), (4, None), (8, 5),
                      (8, -1)]:
         a = list(args)
         a[idx] = val
         assert lib.screen(*a) == gs.GS_EINVAL, (idx, val)
+    # the comparison rules run on the wide schedule of lasso_path only
+    for rule in (2, 3, 4):
+        a = list(args)
+        a[8] = rule
+        assert lib.screen(*a) == gs.GS_EUNSUPPORTED
 
 
 def test_screen_noalloc_rejects_before_launch(lib):
@@ -139,7 +144,7 @@ def test_screen_noalloc_rejects_before_launch(lib):
     GS_ETOOLARGE (fake device pointers are never dereferenced)."""
     vp = ctypes.c_void_p(4096)
     args = [8, 20, 8, gs.GS_F32, vp, vp, vp, 0.5, 0, None, 0, vp, vp, vp, vp, vp, None, None]
-    for idx, val in [(0, 0), (2, 4), (3, 5), (7, 0.0), (7, float("nan")), (4, None), (8, 3)]:
+    for idx, val in [(0, 0), (2, 4), (3, 5), (7, 0.0), (7, float("nan")), (4, None), (8, 7)]:
         a = list(args)
         a[idx] = val
         assert lib.screen_noalloc(*a) == gs.GS_EINVAL, (idx, val)

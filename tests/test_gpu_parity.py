@@ -256,6 +256,25 @@ def test_path_dome_c1(torch, orc, schedule):
           f"{int(sph['nactive'].sum())})")
 
 
+@pytest.mark.parametrize("rule", ["static", "dynamic_safe", "st3"])
+def test_path_comparison_rules(torch, orc, rule):
+    """The comparison rules of Table 1 (wide schedule) on the 72 x 7129 path
+    down to lambda_max/10: certified, beta against the tight oracle, and the
+    same epochs and final active set sizes as the oracle with that rule."""
+    d = synth.c1()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path(Xd, yd, T=12, lambda_min_ratio=0.1, rule=rule)
+    torch.cuda.synchronize()
+    assert got["rc"] == gs.GS_OK
+    lams = _np(got["lambdas"])
+    _check_path(X, y, got, orc, lams, label=f"c1 {rule}")
+    o = orc.lasso_path(X, y, lambdas=lams, rule=rule)
+    np.testing.assert_array_equal(_np(got["epochs"]), o["epochs"])
+    np.testing.assert_array_equal(_np(got["nactive"]), o["nactive"])
+    print(f"c1 {rule}: final active {_np(got['nactive']).tolist()}")
+
+
 # -------------------------------------------------------------------- paths
 
 def _primal(Xf, yf, b, lam):

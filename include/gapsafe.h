@@ -199,6 +199,18 @@ typedef struct gs_opts {
                             narrow schedule, incremented (atomically) by the
                             call; the caller zeroes them                     */
   int32_t rule;          /* GS_RULE_*: the safe region (default sphere)       */
+  double enet_alpha;     /* elastic net mixing a in (0, 1] (appendix,
+                            "Elastic-Net"): minimizes 1/2||X b - y||^2 +
+                            a lambda ||b||_1 + (1-a) lambda/2 ||b||^2, solved
+                            as the Lasso with parameter a lambda on the
+                            augmented design [X; sqrt((1-a) lambda) I] and
+                            response [y; 0], kept implicit; the grid starts
+                            at ||X^T y||_inf / a and the gap is that of the
+                            augmented problem.  1 (default; 0 also means 1)
+                            is the Lasso.  a < 1 runs on the wide schedule
+                            (lasso_path moves there; lasso_solve_batch and
+                            lasso_path_learned return GS_EUNSUPPORTED) and
+                            with the GAP SAFE sphere or dome only.         */
 } gs_opts;
 
 /* Fill *o with the defaults above. */

@@ -178,6 +178,40 @@ class Oracle:
                     passes=ps, lambdas=lam_out, screened=scr, rc=rc)
 
 
+    def enet_path(self, X, y, alpha, T=100, lambdas=None, relative=False, delta=3.0,
+                  eps_rel=1e-8, f=10, K=100000, beta_init=None, rule="sphere"):
+        """The elastic net min 1/2||X b - y||^2 + alpha lam ||b||_1 +
+        (1 - alpha) lam/2 ||b||^2 along a lambda grid (appendix,
+        "Elastic-Net"): at each lambda_t, Algorithm 1 on the Lasso with
+        parameter alpha lambda_t, design [X; sqrt((1 - alpha) lambda_t) I_p]
+        and response [y; 0], written out explicitly, warm-started from the
+        previous lambda.  The grid starts at ||X^T y||_inf / alpha, the
+        smallest lambda with a zero solution.  Returns the lasso_path fields
+        (gap and passes of the augmented problems)."""
+        X = np.asarray(X, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        n, p = X.shape
+        lmax = np.abs(X.T @ y).max() / alpha
+        if lambdas is None:
+            lams = lmax * 10.0 ** (-delta * np.arange(T) / max(T - 1, 1))
+        else:
+            lams = np.asarray(lambdas, dtype=np.float64) * (lmax if relative else 1.0)
+        yt = np.concatenate([y, np.zeros(p)])
+        keys = ("beta", "gap", "epochs", "nactive", "status", "passes")
+        out = {k: [] for k in keys}
+        b = None if beta_init is None else np.asarray(beta_init, dtype=np.float64)
+        for lam in lams:
+            Xt = np.vstack([X, np.sqrt((1.0 - alpha) * lam) * np.eye(p)])
+            r = self.lasso_path(Xt, yt, lambdas=[alpha * lam], eps_rel=eps_rel, f=f, K=K,
+                                beta_init=b, rule=rule)
+            b = r["beta"][0]
+            for k in keys:
+                out[k].append(r[k][0])
+        res = {k: np.array(v) for k, v in out.items()}
+        res["lambdas"] = lams
+        return res
+
+
 _default: Optional[Oracle] = None
 
 

@@ -59,6 +59,7 @@ class gs_opts(ctypes.Structure):
         ("cd_mode", ctypes.c_int32),
         ("select_counts", ctypes.c_void_p), ("timestamps", ctypes.c_void_p),
         ("stats", ctypes.c_void_p), ("rule", ctypes.c_int32),
+        ("enet_alpha", ctypes.c_double),
     ]
 
 
@@ -277,10 +278,11 @@ def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, o
 
 
 def _opts(eps_rel, screen_every, max_epochs, schedule, select_counts=None, timestamps=None,
-          cd_mode="auto", stats=None, rule="sphere"):
+          cd_mode="auto", stats=None, rule="sphere", enet_alpha=1.0):
     o = gs_opts()
     load_library().gs_opts_default(ctypes.byref(o))
     o.rule = RULES[rule] if isinstance(rule, str) else int(rule)
+    o.enet_alpha = float(enet_alpha)
     o.eps_rel = float(eps_rel)
     o.screen_every = int(screen_every)
     o.max_epochs = int(max_epochs)
@@ -309,16 +311,17 @@ def lasso_path(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
                relative: bool = False, lambda_min_ratio: float = 1e-3, beta_init=None,
                rows=None, eps_rel: float = 1e-8, screen_every: int = 10,
                max_epochs: int = 100000, schedule="auto", cd_mode="auto", stream=None,
-               out=None, workspace=None, stats=None, rule="sphere"):
+               out=None, workspace=None, stats=None, rule="sphere", enet_alpha=1.0):
     """Algorithm 1 on the device for one problem; see include/gapsafe.h.
     Returns a PathResult of device tensors (valid after the stream syncs) with
-    an extra ``rc`` entry (GS_OK or GS_NOT_CONVERGED)."""
+    an extra ``rc`` entry (GS_OK or GS_NOT_CONVERGED).  enet_alpha < 1 solves
+    the elastic net through its augmented Lasso."""
     lib = load_library()
     pr, out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
                               lambda_min_ratio=lambda_min_ratio, beta_init=beta_init,
                               rows=rows, out=out)
     o = _opts(eps_rel, screen_every, max_epochs, schedule, cd_mode=cd_mode, stats=stats,
-              rule=rule)
+              rule=rule, enet_alpha=enet_alpha)
     need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
     rc = lib.lasso_path(ctypes.byref(pr), ctypes.byref(o), _ptr(ws), ws.numel(), _stream_ptr(stream))

@@ -91,6 +91,9 @@ int check_opts(const gs_opts* o) {
   if (o->schedule < GS_SCHED_AUTO || o->schedule > GS_SCHED_WIDE) return GS_EINVAL;
   if (o->cd_mode < GS_CD_AUTO || o->cd_mode > GS_CD_RESIDUAL) return GS_EINVAL;
   if (o->rule < GS_RULE_SPHERE || o->rule > GS_RULE_ST3) return GS_EINVAL;
+  const double a = o->enet_alpha == 0.0 ? 1.0 : o->enet_alpha;
+  if (!(a > 0.0 && a <= 1.0)) return GS_EINVAL;
+  if (a < 1.0 && o->rule >= GS_RULE_STATIC) return GS_EINVAL;  // Lasso-only rules
   return GS_OK;
 }
 
@@ -159,6 +162,7 @@ bool use_wide(const gs_problem* pr, const gs_opts* o) {
   if (pr->rows) return false;  // the wide kernels read contiguous rows only
   if (o->schedule == GS_SCHED_WIDE) return true;
   if (o->rule >= GS_RULE_STATIC) return true;  // comparison rules: wide schedule only
+  if (o->enet_alpha != 0.0 && o->enet_alpha < 1.0) return true;  // elastic net: likewise
   if (o->schedule == GS_SCHED_NARROW) return false;
   return (double)pr->n * (double)pr->p > kWideThreshold;
 }
@@ -249,6 +253,7 @@ PathOpts path_opts(const gs_opts* o, bool batch) {
   po.pattern = o->cd_mode == GS_CD_RESIDUAL ? 0 : 1;
   po.gs_cap = 0;
   po.rule = o->rule;
+  po.enet = o->enet_alpha == 0.0 ? 1.0 : o->enet_alpha;
   po.select_counts = batch ? o->select_counts : nullptr;
   po.timestamps = batch ? reinterpret_cast<long long*>(o->timestamps) : nullptr;
   po.stats = reinterpret_cast<long long*>(o->stats);
@@ -473,6 +478,7 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   int rc = check_opts(o);
   if (rc) return rc;
   if (o->rule >= GS_RULE_STATIC) return GS_EUNSUPPORTED;  // wide schedule only
+  if (o->enet_alpha != 0.0 && o->enet_alpha < 1.0) return GS_EUNSUPPORTED;
   for (int b = 0; b < B; ++b) {
     rc = check_problem(&probs[b]);
     if (rc) return rc;
@@ -780,6 +786,7 @@ void gs_opts_default(gs_opts* o) {
   o->screen_every = 10;
   o->max_epochs = 100000;
   o->schedule = GS_SCHED_AUTO;
+  o->enet_alpha = 1.0;
 }
 
 double gs_wallclock_hz(void) {

@@ -83,6 +83,7 @@ struct PathOpts {
   int32_t* select_counts;  // T x p or null
   long long* timestamps;   // 2B or null
   long long* stats;        // kNumStats or null
+  double enet;             // elastic net mixing alpha in (0, 1]; 1 = the Lasso
 };
 
 // Parameters of the warm-start network (4 -> 64 -> 64 -> 2), one FP32 array:
@@ -117,6 +118,7 @@ struct WideState {
   int32_t rule, jstar;
   // comparison rules (rules 2-4): x_{j*} and the sphere of the last pass
   double sstar, nstar, shift, rad_s, e_shift;
+  double enet;  // elastic net alpha (1: the Lasso)
   long long n_visits, n_rounds, n_stops, n_epochs;
 };
 

@@ -602,6 +602,9 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
                        int32_t block, int32_t* learned_out, void* workspace, size_t ws_bytes,
                        void* stream) {
   if (!learned_problem_ok(prob)) return GS_EINVAL;
+  if (opts && ((opts->enet_alpha != 0.0 && opts->enet_alpha != 1.0) ||
+               opts->rule >= GS_RULE_STATIC))
+    return GS_EUNSUPPORTED;  // the learned start is built for the Lasso with GAP SAFE tests
   if (params && (block < 1 || block > 64)) return GS_EINVAL;
   if (prob->lambdas) {
     for (int t = 0; t < prob->T; ++t)

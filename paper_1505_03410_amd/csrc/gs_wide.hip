@@ -11,7 +11,7 @@ __device__ __forceinline__ GapInfo state_gap(const ProbDesc& d, const WideState*
   g.gap = st->gap;
   g.radius = st->radius_s;
   g.e_c = st->e_c;
-  g.lambda = d.lam[st->t];
+  g.lambda = wide_l1(d, st);
   g.Rlo = st->Rlo;
   g.Rhi = st->Rhi;
   g.rc2lo = st->rc2lo;
@@ -27,10 +27,13 @@ __device__ __forceinline__ GapInfo state_gap(const ProbDesc& d, const WideState*
 
 // The GAP SAFE sphere test, and the dome test where it is on (each is safe
 // alone); or one of the comparison rules of Table 1 in their place.
-__device__ __forceinline__ bool wide_keep(const ProbDesc& d, const GapInfo& g, int j, double c) {
-  const double nr = d.nrm2[j];
-  if (g.rule >= 2) return rule_keep(g, d.xty[j], g.rule == 4 ? d.gst[j] : 0.0, nr, d.n);
-  return sphere_keep(g, c, nr, d.n) && (!g.dome || dome_keep(g, d.xty[j], c, nr, d.n));
+__device__ __forceinline__ bool wide_keep(const ProbDesc& d, const WideState* st,
+                                          const GapInfo& g, int j, double c) {
+  if (!(d.nrm2[j] > 0.0)) return false;
+  const double nr = d.nrm2[j] + wide_mu2(d, st);  // ||x~_j||^2 (elastic net)
+  const int nn = wide_nn(d, st);
+  if (g.rule >= 2) return rule_keep(g, d.xty[j], g.rule == 4 ? d.gst[j] : 0.0, nr, nn);
+  return sphere_keep(g, c, nr, nn) && (!g.dome || dome_keep(g, d.xty[j], c, nr, nn));
 }
 
 // Sphere test over one tile of A: kept count per block; screened nonzero
@@ -49,7 +52,7 @@ __global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, Wi
     const int k = tile0 + e;
     if (k >= q) break;
     const int j = full ? k : act[k];
-    if (wide_keep(d, g, j, d.c[k])) {
+    if (wide_keep(d, st, g, j, d.c[k])) {
       ++cnt;
     } else if (d.beta[j] != 0.0) {
       d.beta[j] = 0.0;
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
     if (k < q) {
       const int j = full ? k : act[k];
       js[e] = j;
-      if (wide_keep(d, g, j, d.c[k])) {
+      if (wide_keep(d, st, g, j, d.c[k])) {
         keep |= 1u << e;
         ++c;
       }
@@ -113,9 +116,9 @@ __global__ __launch_bounds__(256) void k_wide_lcount(ProbDesc d, WideState* st, 
   const int q = st->q;
   const int tile0 = st->resume + blockIdx.x * kTestTile;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
-  const double lambda = d.lam[st->t];
+  const double lambda = wide_l1(d, st);
   const double tau = st->tau;
-  const double rn = sqrt(st->R2) * (1.0 + gam(d.n + 2));
+  const double rn = sqrt(st->R2) * (1.0 + gam(wide_nn(d, st) + 2));
   int cnt = 0;
   for (int e = threadIdx.x; e < kTestTile; e += 256) {
     const int k = tile0 + e;
@@ -132,9 +135,9 @@ __global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st
   if (st->done || st->phase != 2) return;
   const int q = st->q;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
-  const double lambda = d.lam[st->t];
+  const double lambda = wide_l1(d, st);
   const double tau = st->tau;
-  const double rn = sqrt(st->R2) * (1.0 + gam(d.n + 2));
+  const double rn = sqrt(st->R2) * (1.0 + gam(wide_nn(d, st) + 2));
   int off = 0;
   for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];
   const int k0 = st->resume + blockIdx.x * kTestTile + threadIdx.x * PER;
@@ -159,6 +162,7 @@ __global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st
     __syncthreads();
   }
   int pos = off + scan[threadIdx.x] - c;
+  const double mu2 = wide_mu2(d, st);
   // entry: position, feature, then (c_k, beta_j, 1/||x_j||^2, ||x_j||^2)
 #pragma unroll
   for (int e = 0; e < PER; ++e)
@@ -169,8 +173,14 @@ __global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st
       double* v = d.lval + 4 * (int64_t)pos;
       v[0] = d.c[k0 + e];
       v[1] = d.beta[j];
-      v[2] = d.inv[j];
-      v[3] = d.nrm2[j];
+      if (mu2 > 0.0) {  // elastic net: ||x~_j||^2
+        const double nr = d.nrm2[j] + mu2;
+        v[2] = 1.0 / nr;
+        v[3] = nr;
+      } else {
+        v[2] = d.inv[j];
+        v[3] = d.nrm2[j];
+      }
       ++pos;
     }
 }
@@ -244,6 +254,7 @@ __global__ __launch_bounds__(256) void k_screen_prep(ProbDesc d, WideState* st,
     st->phase = 0;
     st->need_refresh = 0;
     st->rule = rule;
+    st->enet = 1.0;
   }
 }
 

@@ -39,6 +39,22 @@ struct WideBufs {
   double* nzval;    // p
 };
 
+// Elastic net (appendix): min 1/2||X b - y||^2 + a lambda ||b||_1 +
+// (1-a) lambda/2 ||b||^2 is the Lasso with parameter a lambda on the
+// augmented design X~ = [X; sqrt((1-a) lambda) I] and response y~ = [y; 0].
+// X~ stays implicit: with mu2 = (1-a) lambda, ||x~_j||^2 = ||x_j||^2 + mu2,
+// x~_j^T rho~ = x_j^T rho - mu2 b_j and ||rho~||^2 = ||rho||^2 + mu2 ||b||^2,
+// y~^T rho~ = y^T rho; dot products get one more term.  a = 1 is the Lasso.
+__device__ __forceinline__ double wide_l1(const ProbDesc& d, const WideState* st) {
+  return st->enet * d.lam[st->t];
+}
+__device__ __forceinline__ double wide_mu2(const ProbDesc& d, const WideState* st) {
+  return (1.0 - st->enet) * d.lam[st->t];
+}
+__device__ __forceinline__ int wide_nn(const ProbDesc& d, const WideState* st) {
+  return st->enet < 1.0 ? d.n + 1 : d.n;
+}
+
 // Deterministic block reductions (256 or 1024 threads).
 template <int NT>
 __device__ double block_sum(double v, double* sh) {
@@ -173,12 +189,14 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
   yy = block_sum<256>(yy, sh);
   if (!isfinite(yy)) bad = 1.0;
   const int T = d.T;
+  // the smallest lambda with a zero solution: ||X^T y||_inf / a
+  const double lmx = mx / opts.enet;
   for (int t = threadIdx.x; t < T; t += 256) {
     double lam;
     if (d.has_lambdas)
-      lam = d.lam_in[t] * (d.lambda_relative ? mx : 1.0);
+      lam = d.lam_in[t] * (d.lambda_relative ? lmx : 1.0);
     else
-      lam = (T == 1) ? mx : mx * pow(d.lambda_min_ratio, (double)t / (double)(T - 1));
+      lam = (T == 1) ? lmx : lmx * pow(d.lambda_min_ratio, (double)t / (double)(T - 1));
     d.lam[t] = lam;
     if (d.lambda_out) d.lambda_out[t] = lam;
   }
@@ -210,6 +228,7 @@ __global__ __launch_bounds__(256) void k_wide_init(ProbDesc d, WideState* st, Wi
     st->nonfinite = (bad != 0.0) ? 1 : 0;
     st->resume = 0;
     st->rule = opts.rule;
+    st->enet = opts.enet;
     st->jstar = (jstar >= 0 && jstar < d.p) ? jstar : 0;
     st->sstar = d.xty[st->jstar] >= 0.0 ? 1.0 : -1.0;
     st->nstar = sqrt(d.nrm2[st->jstar]);
@@ -290,13 +309,19 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
   }
   s2 = block_sum<kRefreshThreads>(s2, sh);
   sy = block_sum<kRefreshThreads>(sy, sh);
+  const double mu2 = wide_mu2(d, st);
+  if (mu2 > 0.0) {  // elastic net: ||rho~||^2 = ||rho||^2 + mu2 ||beta||^2
+    double bb = 0.0;
+    for (int e = threadIdx.x; e < nnz; e += kRefreshThreads) bb = fma(wb.nzval[e], wb.nzval[e], bb);
+    s2 += mu2 * block_sum<kRefreshThreads>(bb, sh);
+  }
   if (threadIdx.x == 0) {
     st->R2 = s2;
     st->Ry = sy;
     st->nnz = nnz;
     if (mode == 1) {
       // screened coefficients were zeroed: ||beta||_1 only fell
-      st->pb2 = fmax(st->pb2, s2 + 2.0 * d.lam[st->t] * st->l1);
+      st->pb2 = fmax(st->pb2, s2 + 2.0 * wide_l1(d, st) * st->l1);
       st->need_refresh = 0;
     }
   }
@@ -333,6 +358,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
   const uint64_t mk = L::rowmask(lane, d.n);
+  const double mu2 = WN == 0 ? wide_mu2(d, st) : 0.0;
   double Ml = 0.0, l1 = 0.0, sb = 0.0, xm = 0.0;
   for (int base = wid * kSweepU; base < q; base += W * kSweepU) {
     XT xv[kSweepU][RPL];
@@ -370,10 +396,11 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
       if constexpr (with_xty) sy = wave_sum(sy);
       if (base + u < q && lane == 0) {
         const int j = jj[u];
+        if (mu2 > 0.0) a -= mu2 * bv[u];
         d.c[base + u] = a;
         if (with_nrm2) d.nrm2[j] = s2;
         if constexpr (with_xty) d.xty[j] = sy;
-        const double nr = with_nrm2 ? s2 : nrv[u];
+        const double nr = (with_nrm2 ? s2 : nrv[u]) + mu2;
         const double b = bv[u];
         Ml = fmax(Ml, fabs(a));
         l1 += fabs(b);
@@ -415,9 +442,9 @@ __global__ __launch_bounds__(256) void k_wide_gap(ProbDesc d, WideState* st, Wid
   sb = block_sum<256>(sb, sh);
   xm = block_max<256>(xm, sh);
   const int t = st->t;
-  const double lambda = d.lam[t];
-  GapInfo g = gap_safe(st->R2, st->Ry, l1, sb, xm, M, st->nnz, d.n, lambda, sqrt(st->ynorm2),
-                       st->q, st->rule == 1, st->rule >= 2);
+  const double lambda = wide_l1(d, st);  // the Lasso parameter (a lambda_t for the elastic net)
+  GapInfo g = gap_safe(st->R2, st->Ry, l1, sb, xm, M, st->nnz, wide_nn(d, st), lambda,
+                       sqrt(st->ynorm2), st->q, st->rule == 1, st->rule >= 2);
   if (st->rule >= 2)
     rule_ball(g, st->rule, st->lambda_max, st->sstar, st->nstar, sqrt(st->ynorm2), d.n);
   if (threadIdx.x == 0) {
@@ -519,6 +546,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_csweep(ProbDesc d, Wi
     }
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
+  const double mu2 = wide_mu2(d, st);
   for (int base = k0 + wid * kSweepU; base < q; base += W * kSweepU) {
     XT xv[kSweepU][RPL];
     int jj[kSweepU];
@@ -532,7 +560,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_csweep(ProbDesc d, Wi
 #pragma unroll
       for (int i = 0; i < RPL; ++i) a = fma((double)xv[u][i], r[i], a);  // r is zero at rows >= n
       a = wave_sum(a);
-      if (base + u < q && lane == 0) d.c[base + u] = a;
+      if (base + u < q && lane == 0) d.c[base + u] = mu2 > 0.0 ? a - mu2 * d.beta[jj[u]] : a;
     }
   }
 }
@@ -540,12 +568,13 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_csweep(ProbDesc d, Wi
 // Whether position k (>= resume) must be visited exactly in this round.
 __device__ __forceinline__ bool wide_listed(const ProbDesc& d, const WideState* st, int j,
                                             double ck, double lambda, double tau, double rnorm) {
-  const double nr = d.nrm2[j];
-  if (!(nr > 0.0)) return false;  // a zero column never moves
+  const double nr = d.nrm2[j] + wide_mu2(d, st);
+  if (!(d.nrm2[j] > 0.0)) return false;  // a zero column never moves
   if (d.beta[j] != 0.0) return true;
-  const double xn = sqrt(nr) * (1.0 + gam(d.n + 2));
+  const int nn = wide_nn(d, st);
+  const double xn = sqrt(nr) * (1.0 + gam(nn + 2));
   // |c^_k - x_k^T rho_a| <= gamma_{n+1} ||x_k|| ||rho_a||
-  const double thr = lambda * (1.0 - 4.0 * kU) - gam(d.n + 1) * xn * rnorm;
+  const double thr = lambda * (1.0 - 4.0 * kU) - gam(nn + 1) * xn * rnorm;
   return fabs(ck) + xn * tau > thr;
 }
 
@@ -564,7 +593,9 @@ __global__ __launch_bounds__(64) void k_wide_walk(ProbDesc d, WideState* st, Wid
   const int lane = threadIdx.x;
   const int q = st->q;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
-  const double lambda = d.lam[st->t];
+  const double lambda = wide_l1(d, st);
+  const double mu2 = wide_mu2(d, st);
+  const int nn = wide_nn(d, st);
   const double tau = st->tau;
   const double tau2 = tau * tau;
   const gbl<XT>* X = gptr((const XT*)d.X);
@@ -582,7 +613,7 @@ __global__ __launch_bounds__(64) void k_wide_walk(ProbDesc d, WideState* st, Wid
     }
   // ||rho|| of every iterate of the round is at most sqrt(2 P) of the pass
   const double rb = sqrt(st->pb2) * (1.0 + 1e-9);
-  const double erc = 4.0 * gam(d.n + 1) * rb;
+  const double erc = 4.0 * gam(nn + 1) * rb;
   double D2 = 0.0, De = 0.0, dmax2 = 0.0;
   int stop_k = -1;
   long long visits = 0;
@@ -615,7 +646,7 @@ __global__ __launch_bounds__(64) void k_wide_walk(ProbDesc d, WideState* st, Wid
           s_b[e] = bv[u];
           s_inv[e] = iv[u];
           s_nr[e] = nv[u];
-          s_xn[e] = sqrt(nv[u]) * (1.0 + gam(d.n + 2));
+          s_xn[e] = sqrt(nv[u]) * (1.0 + gam(nn + 2));
         }
       }
     }
@@ -652,7 +683,7 @@ __global__ __launch_bounds__(64) void k_wide_walk(ProbDesc d, WideState* st, Wid
             if (t + 2 < RPL) a2 = fma(xd[t + 2], r[t + 2], a2);
             if (t + 3 < RPL) a3 = fma(xd[t + 3], r[t + 3], a3);
           }
-          const double dm = wave_sum((a0 + a1) + (a2 + a3));
+          const double dm = wave_sum((a0 + a1) + (a2 + a3)) - mu2 * b;
           const double bn = soft_thr(lambda * inv, b + dm * inv);
           ++visits;
           if (bn != b) {

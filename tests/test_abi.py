@@ -39,8 +39,9 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(gs.gs_problem) == 136
     assert gs.gs_problem.lambda_min_ratio.offset == 72
     assert gs.gs_problem.lambda_out.offset == 128
-    assert ctypes.sizeof(gs.gs_opts) == 56
+    assert ctypes.sizeof(gs.gs_opts) == 64
     assert gs.gs_opts.rule.offset == 48
+    assert gs.gs_opts.enet_alpha.offset == 56
 
 
 def test_defaults(lib):

@@ -625,3 +625,52 @@ def test_comparison_rule_paths_are_safe(orc, rule):
         assert np.all(tight["beta"][t][scr] == 0)
         d = X @ (got["beta"][t] - gap["beta"][t])
         assert np.linalg.norm(d) <= np.sqrt(2 * got["gap"][t]) + np.sqrt(2 * gap["gap"][t]) + 1e-12
+
+
+# ------------------------------------------------------------ elastic net
+
+def test_enet_orthonormal_closed_form(orc):
+    """Orthonormal X: the elastic net solution is
+    ST(alpha lambda, x_j^T y) / (1 + (1 - alpha) lambda) (Zou & Hastie's
+    naive elastic net on an orthonormal design)."""
+    d = synth.orthonormal(41, 30, 12)
+    X, y = d["X"], d["y"]
+    for alpha in (0.3, 0.7):
+        r = orc.enet_path(X, y, alpha, T=6, delta=1.0, eps_rel=1e-14)
+        for t, lam in enumerate(r["lambdas"]):
+            want = _st(alpha * lam, X.T @ y) / (1 + (1 - alpha) * lam)
+            np.testing.assert_allclose(r["beta"][t], want, rtol=1e-9, atol=1e-12)
+
+
+def test_enet_kkt_and_lasso_limit(orc):
+    """KKT of the elastic net at a tight solution:
+    x_j^T (y - X b) - (1 - alpha) lambda b_j = alpha lambda sign(b_j) on the
+    support, |.| <= alpha lambda off it; and alpha = 1 gives the Lasso path."""
+    X, y = _small_c1_like(seed=42, n=30, p=80)
+    r = orc.enet_path(X, y, 0.5, T=8, delta=1.5, eps_rel=1e-15, K=10_000_000)
+    for t, lam in enumerate(r["lambdas"]):
+        b = r["beta"][t]
+        g = X.T @ (y - X @ b) - 0.5 * lam * b
+        on = b != 0
+        np.testing.assert_allclose(g[on], 0.5 * lam * np.sign(b[on]), rtol=1e-7, atol=1e-9)
+        assert np.all(np.abs(g[~on]) <= 0.5 * lam * (1 + 1e-7))
+    lasso = orc.lasso_path(X, y, T=8, delta=1.5, eps_rel=1e-12)
+    enet1 = orc.enet_path(X, y, 1.0, T=8, delta=1.5, eps_rel=1e-12)
+    np.testing.assert_allclose(enet1["lambdas"], lasso["lambdas"], rtol=1e-14)
+    for t in range(8):
+        d = X @ (enet1["beta"][t] - lasso["beta"][t])
+        assert np.linalg.norm(d) <= (np.sqrt(2 * max(enet1["gap"][t], 0.0)) +
+                                     np.sqrt(2 * max(lasso["gap"][t], 0.0)) + 1e-12)
+
+
+def test_enet_sklearn_cross_check(orc):
+    """scikit-learn's ElasticNet minimizes 1/(2n)||y - X b||^2 + a r ||b||_1 +
+    a (1 - r)/2 ||b||^2, so a = lambda/n and r = alpha give the same problem."""
+    sk = pytest.importorskip("sklearn.linear_model")
+    X, y = _small_c1_like(seed=43, n=40, p=60)
+    n = X.shape[0]
+    lam = 0.2 * np.abs(X.T @ y).max()
+    r = orc.enet_path(X, y, 0.6, lambdas=[lam / 0.6 * 5, lam], eps_rel=1e-15, K=10_000_000)
+    m = sk.ElasticNet(alpha=lam / n, l1_ratio=0.6, fit_intercept=False, tol=1e-14,
+                      max_iter=1_000_000).fit(X, y)
+    np.testing.assert_allclose(r["beta"][1], m.coef_, rtol=1e-6, atol=1e-8)

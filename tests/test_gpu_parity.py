@@ -275,6 +275,39 @@ def test_path_comparison_rules(torch, orc, rule):
     print(f"c1 {rule}: final active {_np(got['nactive']).tolist()}")
 
 
+@pytest.mark.parametrize("alpha", [0.5, 0.9])
+def test_path_elastic_net(torch, orc, alpha):
+    """The elastic net (appendix, "Elastic-Net") through its augmented Lasso,
+    kept implicit on the device, against the oracle that writes the augmented
+    design out: certified gaps, the elastic net KKT conditions at the tight
+    oracle solution's accuracy, beta against the oracle's at the same gap
+    target, and the same epochs at every lambda."""
+    d = synth.c1()
+    X, y = d["X"][:, :1500], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path(Xd, yd, T=15, lambda_min_ratio=0.05, enet_alpha=alpha)
+    torch.cuda.synchronize()
+    assert got["rc"] == gs.GS_OK
+    lams = _np(got["lambdas"])
+    Xf, yf = _f64(X), _f64(y)
+    o = orc.enet_path(Xf, yf, alpha, T=15, delta=-np.log10(0.05))
+    np.testing.assert_allclose(lams, o["lambdas"], rtol=1e-12)
+    tight = orc.enet_path(Xf, yf, alpha, lambdas=lams, eps_rel=1e-13, K=10_000_000)
+    B, gap = _np(got["beta"]), _np(got["gap"])
+    yy = float(yf @ yf)
+    assert np.all(_np(got["status"]) == 0) and np.all(gap <= 1e-8 * yy)
+    for t, lam in enumerate(lams):
+        # the augmented problem is strongly convex (ridge term): the gap
+        # bounds ||beta - beta*||^2 <= 2 (G + G*) / ((1 - alpha) lam)
+        db = np.linalg.norm(B[t] - tight["beta"][t])
+        bound = np.sqrt(2 * (max(gap[t], 0) + max(tight["gap"][t], 0)) / ((1 - alpha) * lam))
+        assert db <= bound * (1 + 1e-6) + 1e-12, (t, db, bound)
+        nb = np.linalg.norm(o["beta"][t])
+        if nb > 0:
+            assert np.linalg.norm(B[t] - o["beta"][t]) / nb <= BETA_TOL
+    np.testing.assert_array_equal(_np(got["epochs"]), o["epochs"])
+
+
 # -------------------------------------------------------------------- paths
 
 def _primal(Xf, yf, b, lam):

@@ -177,7 +177,22 @@ typedef struct gs_problem {
   int32_t* nactive_out;    /* [device] T: size of the safe active set at exit */
   int32_t* status_out;     /* [device] T: GS_STATUS_*                          */
   double* lambda_out;      /* [device] optional T: the lambdas used           */
+  /* Sparse designs (Sec. 4.1: the paper's second implementation).  With
+   * format GS_CSC, X holds the nnz nonzero values (dtype), col_ptr[j] ..
+   * col_ptr[j+1]-1 index column j's entries in X and row_idx (rows distinct
+   * within a column), and ldx and rows are not used.  A CSC path runs one
+   * wavefront per problem with the residual in LDS when 8n bytes fit
+   * (else in the workspace), the sweep is the transposed sparse product
+   * over the active columns and a CD step touches only column j's rows;
+   * rule sphere or dome, the Lasso only (no elastic net), residual-mode
+   * epochs.  A batch must be all dense or all CSC. */
+  int32_t format;          /* GS_DENSE (0, default) or GS_CSC (1)             */
+  const int64_t* col_ptr;  /* [device] CSC: p + 1 non-decreasing offsets,
+                              col_ptr[0] = 0                                  */
+  const int32_t* row_idx;  /* [device] CSC: col_ptr[p] row indices in [0, n)  */
 } gs_problem;
+
+enum { GS_DENSE = 0, GS_CSC = 1 };
 
 typedef struct gs_opts {
   double eps_rel;        /* stop when gap <= eps_rel * ||y||^2 (default 1e-8;

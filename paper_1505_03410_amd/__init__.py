@@ -48,7 +48,8 @@ class gs_problem(ctypes.Structure):
         ("beta_init", ctypes.c_void_p), ("beta_out", ctypes.c_void_p),
         ("gap_out", ctypes.c_void_p), ("epochs_out", ctypes.c_void_p),
         ("nactive_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p),
-        ("lambda_out", ctypes.c_void_p),
+        ("lambda_out", ctypes.c_void_p), ("format", ctypes.c_int32),
+        ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
     ]
 
 
@@ -212,6 +213,34 @@ def colmajor_to_device(X, ld_multiple: int = 4, dtype=None, device="cuda"):
     return t.T[:n]
 
 
+GS_DENSE, GS_CSC = 0, 1
+
+
+class CscDesign:
+    """A sparse design in compressed sparse column form on the device:
+    col_ptr (p+1 int64), row_idx (nnz int32) and values (nnz float32 or
+    float64), n rows.  Pass it as X to lasso_path / lasso_solve_batch."""
+
+    def __init__(self, col_ptr, row_idx, values, n):
+        torch = _torch()
+        if col_ptr.dtype != torch.int64 or row_idx.dtype != torch.int32:
+            raise ValueError("col_ptr must be int64 and row_idx int32")
+        for t in (col_ptr, row_idx, values):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("CSC arrays must be contiguous device tensors")
+        self.col_ptr, self.row_idx, self.values, self.n = col_ptr, row_idx, values, int(n)
+        self.p = col_ptr.numel() - 1
+        self.dtype = values.dtype
+        self.device = values.device
+
+    @classmethod
+    def from_host(cls, col_ptr, row_idx, values, n, device="cuda"):
+        torch = _torch()
+        return cls(torch.from_numpy(np.ascontiguousarray(col_ptr, dtype=np.int64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(row_idx, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(values)).to(device), n)
+
+
 def _design(X):
     if X.dim() != 2 or X.stride(0) != 1 or X.stride(1) < X.shape[0]:
         raise ValueError("X must be an (n, p) column-major tensor: strides (1, ldx), ldx >= n")
@@ -240,8 +269,13 @@ def _alloc_outputs(n, p, T, dt, device):
 
 def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, out, n=None):
     torch = _torch()
-    ld = X.stride(1)
-    if rows is not None:
+    csc = isinstance(X, CscDesign)
+    ld = 1 if csc else X.stride(1)
+    if csc:
+        if rows is not None:
+            raise ValueError("row subsamples are for dense designs")
+        n, p = X.n, X.p
+    elif rows is not None:
         if rows.dtype != torch.int32 or not rows.is_cuda or not rows.is_contiguous():
             raise ValueError("rows must be a contiguous int32 device tensor")
         n = rows.numel()
@@ -260,8 +294,14 @@ def _problem(X, y, *, T, lambdas, relative, lambda_min_ratio, beta_init, rows, o
     if out is None:
         out = _alloc_outputs(n, p, T, X.dtype, X.device)
     pr = gs_problem()
-    pr.n, pr.p, pr.ldx, pr.dtype = n, p, ld, _dtype_code(X)
-    pr.X, pr.y = X.data_ptr(), y.data_ptr()
+    pr.n, pr.p, pr.ldx = n, p, ld
+    if csc:
+        pr.dtype = _dtype_code(X.values)
+        pr.X, pr.y = X.values.data_ptr(), y.data_ptr()
+        pr.format, pr.col_ptr, pr.row_idx = GS_CSC, X.col_ptr.data_ptr(), X.row_idx.data_ptr()
+    else:
+        pr.dtype = _dtype_code(X)
+        pr.X, pr.y = X.data_ptr(), y.data_ptr()
     pr.rows = None if rows is None else rows.data_ptr()
     pr.T = T
     pr.lambdas = None if host_lam is None else host_lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -349,7 +389,8 @@ def _batch_args(problems, eps_rel, screen_every, max_epochs, select_counts, time
     o = _opts(eps_rel, screen_every, max_epochs, "narrow", select_counts, timestamps, cd_mode,
               stats, rule)
     need = lib.lasso_workspace_size(arr, B, ctypes.byref(o))
-    dev = problems[0]["X"].device
+    X0 = problems[0]["X"]
+    dev = X0.device
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
     for out in outs:
         out["workspace"] = ws

@@ -64,12 +64,19 @@ struct Carver {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+bool is_csc(const gs_problem* pr) { return pr->format == GS_CSC; }
+
 int check_problem(const gs_problem* pr) {
   if (!pr) return GS_EINVAL;
   if (pr->n < 1 || pr->p < 1 || pr->T < 1) return GS_EINVAL;
   if (pr->dtype != GS_F32 && pr->dtype != GS_F64) return GS_EINVAL;
-  if (!pr->rows && pr->ldx < pr->n) return GS_EINVAL;
-  if (pr->ldx < 1) return GS_EINVAL;
+  if (pr->format != GS_DENSE && pr->format != GS_CSC) return GS_EINVAL;
+  if (is_csc(pr)) {
+    if (!pr->col_ptr || !pr->row_idx || pr->rows) return GS_EINVAL;
+  } else {
+    if (!pr->rows && pr->ldx < pr->n) return GS_EINVAL;
+    if (pr->ldx < 1) return GS_EINVAL;
+  }
   if (!pr->X || !pr->y || !pr->beta_out || !pr->gap_out || !pr->epochs_out ||
       !pr->nactive_out || !pr->status_out)
     return GS_EINVAL;
@@ -81,7 +88,7 @@ int check_problem(const gs_problem* pr) {
   } else {
     if (!finite_pos(pr->lambda_min_ratio) || pr->lambda_min_ratio > 1.0) return GS_EINVAL;
   }
-  if (pr->n > kMaxN) return GS_EUNSUPPORTED;
+  if (!is_csc(pr) && pr->n > kMaxN) return GS_EUNSUPPORTED;
   return GS_OK;
 }
 
@@ -171,6 +178,7 @@ bool use_wide(const gs_problem* pr, const gs_opts* o) {
 // Gram slots of the pattern mode: a Lasso solution has at most n nonzeros in
 // general position; the margin covers transient supports.
 int pattern_slots(const gs_problem* pr) {
+  if (is_csc(pr)) return 1;  // the CSC path has no pattern mode
   const int want = (pr->n + 7) / 8 * 8 + 16;
   return std::max(1, std::min({kSlotsMax, pr->p, want}));
 }
@@ -226,6 +234,9 @@ void fill_desc(const gs_problem* pr, int orig, ProbDesc* d) {
   d->X = pr->X;
   d->y = pr->y;
   d->rows = pr->rows;
+  d->format = pr->format;
+  d->col_ptr = pr->col_ptr;
+  d->row_idx = pr->row_idx;
   d->ldx = pr->ldx;
   d->n = pr->n;
   d->p = pr->p;
@@ -461,7 +472,100 @@ size_t path_ws(const gs_problem* probs, int B) {
     ProbDesc d;
     carve_problem(cv, &probs[b], &d);
   }
+  cv.take<int64_t>(2 * ((size_t)B + 1));  // CSC: first column of every problem, per dtype
   return align_up(cv.off, 256);
+}
+
+// ---------------------------------------------------------- sparse (CSC)
+// LDS of one CSC wavefront whose residual sits in LDS (n doubles).
+constexpr size_t kCscLdsMax = 152 * 1024;
+
+int run_csc(const gs_problem* probs, int B, const gs_opts* o, void* ws, size_t ws_bytes,
+            hipStream_t s) {
+  for (int b = 0; b < B; ++b)
+    if (!is_csc(&probs[b])) return GS_EUNSUPPORTED;  // all CSC or all dense
+  if (o->rule >= GS_RULE_STATIC || (o->enet_alpha != 0.0 && o->enet_alpha != 1.0))
+    return GS_EUNSUPPORTED;
+  if (!ws) return GS_EWORKSPACE;
+  if (ws_bytes < path_ws(probs, B)) return GS_EWORKSPACE;
+  Carver cv{static_cast<char*>(ws)};
+  int pmax = 1;
+  for (int b = 0; b < B; ++b) pmax = std::max(pmax, probs[b].p);
+  Shared sh;
+  carve_shared(cv, B, pmax, &sh);
+  // groups by (dtype, residual in global memory); heaviest first inside
+  std::vector<ProbDesc> descs(B);
+  std::vector<int> key(B);
+  for (int b = 0; b < B; ++b) {
+    fill_desc(&probs[b], b, &descs[b]);
+    carve_problem(cv, &probs[b], &descs[b]);
+    int rc = upload_lambdas(&probs[b], &descs[b], s);
+    if (rc) return rc;
+    const bool grho = (size_t)probs[b].n * sizeof(double) > kCscLdsMax;
+    key[b] = probs[b].dtype * 2 + (grho ? 1 : 0);
+  }
+  int64_t* first_col = cv.take<int64_t>(2 * ((size_t)B + 1));
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (key[a] != key[b]) return key[a] < key[b];
+    return (double)probs[a].p * probs[a].T > (double)probs[b].p * probs[b].T;
+  });
+  std::vector<ProbDesc> sorted(B);
+  for (int i = 0; i < B; ++i) sorted[i] = descs[order[i]];
+  HIPCHK(hipMemcpyAsync(sh.descs, sorted.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice, s));
+  // the problems of each dtype are contiguous in `sorted`; per dtype, the
+  // prefix of their column counts from 0 (first_col + dtype (B + 1))
+  std::vector<int64_t> fcd(2 * ((size_t)B + 1), 0);
+  int dfirst[2] = {-1, -1}, dcount[2] = {0, 0};
+  for (int i = 0; i < B; ++i) {
+    const int dt = sorted[i].dtype;
+    if (dfirst[dt] < 0) dfirst[dt] = i;
+    int64_t* f = fcd.data() + dt * (B + 1);
+    f[dcount[dt] + 1] = f[dcount[dt]] + sorted[i].p;
+    ++dcount[dt];
+  }
+  HIPCHK(fill_i32(sh.queues, 0, 64, s));
+  HIPCHK(hipMemcpyAsync(first_col, fcd.data(), sizeof(int64_t) * fcd.size(), hipMemcpyHostToDevice,
+                        s));
+  PathOpts po = path_opts(o, B > 1);
+  // column statistics of every problem (one pass over the nonzeros), per dtype
+  for (int dt = 0; dt < 2; ++dt) {
+    if (dfirst[dt] < 0) continue;
+    const ProbDesc* dd = sh.descs + dfirst[dt];
+    const int nb = dcount[dt];
+    const int64_t* fcp = first_col + dt * ((int64_t)B + 1);
+    const int64_t cols = fcd[dt * (B + 1) + nb];
+    unsigned g = (unsigned)std::min<int64_t>((cols + 3) / 4, 8192);
+    void* a[] = {(void*)&dd, (void*)&nb, (void*)&fcp};
+    HIPCHK(launch(kCscColStats[dt], dim3(std::max(g, 1u)), dim3(256), a, 0, s));
+  }
+  // one persistent launch per group
+  int gi = 0;
+  for (int i = 0; i < B;) {
+    int j = i;
+    while (j < B && key[order[j]] == key[order[i]]) ++j;
+    const int kk = key[order[i]];
+    const int dt = kk / 2, grho = kk % 2;
+    size_t lds = 0;
+    if (!grho)
+      for (int t = i; t < j; ++t) lds = std::max(lds, (size_t)sorted[t].n * sizeof(double));
+    const void* kern = kPathCsc[dt][grho];
+    HIPCHK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    const int grid = std::max(1, std::min(j - i, per_cu * device_cus()));
+    const ProbDesc* dd = sh.descs + i;
+    int cnt = j - i;
+    int* q = sh.queues + gi;
+    void* a[] = {(void*)&dd, &cnt, &q, &po};
+    HIPCHK(timed_launch(kTimePath, kern, dim3(grid), dim3(64), a, lds, s));
+    ++gi;
+    i = j;
+  }
+  return GS_OK;
 }
 
 // Narrow launches of a (sorted) descriptor range grouped by configuration.
@@ -482,6 +586,7 @@ int prepare_batch(const gs_problem* probs, int B, const gs_opts* o, void* ws, si
   for (int b = 0; b < B; ++b) {
     rc = check_problem(&probs[b]);
     if (rc) return rc;
+    if (is_csc(&probs[b])) return GS_EUNSUPPORTED;  // CSC: lasso_path / lasso_solve_batch
     if (o->select_counts && (probs[b].p != probs[0].p || probs[b].T != probs[0].T))
       return GS_EINVAL;
   }
@@ -819,6 +924,17 @@ int lasso_path(const gs_problem* prob, const gs_opts* opts, void* workspace, siz
   if (rc) return rc;
   if (!workspace) return GS_EWORKSPACE;
   if (ws_bytes < path_ws(prob, 1)) return GS_EWORKSPACE;
+  if (is_csc(prob)) {
+    rc = run_csc(prob, 1, opts, workspace, ws_bytes, s);
+    if (rc) return rc;
+    std::vector<int32_t> st(prob->T);
+    HIPCHK(hipMemcpyAsync(st.data(), prob->status_out, sizeof(int32_t) * prob->T,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int32_t v : st)
+      if (v == GS_STATUS_NOT_CONVERGED) return GS_NOT_CONVERGED;
+    return GS_OK;
+  }
   if (use_wide(prob, opts)) {
     Carver cv{static_cast<char*>(workspace)};
     Shared sh;
@@ -853,6 +969,17 @@ int lasso_solve_batch(const gs_problem* probs, int32_t B, const gs_opts* opts, v
   gs_opts_default(&def);
   if (!opts) opts = &def;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (probs && B >= 1 && is_csc(&probs[0])) {
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    for (int b = 0; b < B; ++b) {
+      rc = check_problem(&probs[b]);
+      if (rc) return rc;
+      if (opts->select_counts && (probs[b].p != probs[0].p || probs[b].T != probs[0].T))
+        return GS_EINVAL;
+    }
+    return run_csc(probs, B, opts, workspace, ws_bytes, s);
+  }
   Shared sh;
   std::vector<Group> groups;
   int rc = prepare_batch(probs, B, opts, workspace, ws_bytes, s, &sh, &groups);

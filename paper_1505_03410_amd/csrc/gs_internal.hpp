@@ -9,9 +9,12 @@ namespace gs {
 // Device-side descriptor of one Lasso path.  Built on the host, copied into
 // the workspace, read by the kernels.  Pointers are device pointers.
 struct ProbDesc {
-  const void* X;
+  const void* X;           // dense: the design; CSC: the nonzero values
   const void* y;
   const int32_t* rows;
+  const int64_t* col_ptr;  // CSC: p+1 offsets into row_idx and X
+  const int32_t* row_idx;  // CSC: row of every nonzero
+  int32_t format;          // 0 dense column-major, 1 CSC
   int64_t ldx;
   int32_t n, p, T, dtype;
   int32_t lambda_relative;

@@ -49,6 +49,9 @@ extern const void* const kWideFin;
 extern const void* const kWideLCount;
 extern const void* const kWideLCompact;
 extern const void* const kWideStats;
+// Sparse (CSC) designs (gs_csc.hip).
+extern const void* const kCscColStats[2];  // k_csc_colstats<float>, <double>
+extern const void* const kPathCsc[2][2];   // k_path_csc<XT, residual in global memory>
 extern const void* const kFillI32;
 
 }  // namespace gs

@@ -19,6 +19,8 @@ Every workload is a stand-in for the shapes of the paper's experiments
       in [0.01, 0.5].
   c4  1000 x 100000 (400 MB FP32), 2000 blocks of 50 equicorrelated columns
       (rho = 0.7), unit-norm columns, 50-sparse truth, SNR 5.
+  sparse_text  CSC designs shaped like the paper's sparse text data
+      (20newsgroup 961 x 10094, RCV1 20242 x 47236): Zipf column counts.
 
 SNR s means the noise vector is drawn with sigma = ||X beta*|| / (s sqrt(n)).
 Column-major layout: ``colmajor(X, ld)`` returns a (p, ld) C-contiguous array
@@ -149,6 +151,48 @@ def c4(seed=4, n=1000, p=100000, block=50, rho=0.7, k=50, snr=5.0):
     y = _response(rng, X, beta, snr=snr)
     return dict(X=X.astype(np.float32), y=y.astype(np.float32), beta_star=beta,
                 T=100, delta=3.0, block=block, dtype="f32")
+
+
+def sparse_text(seed, n, p, density, k=20, snr=3.0, zipf=1.0):
+    """A sparse design in CSC form shaped like a bag-of-words matrix (the
+    paper's 20newsgroup, 961 x 10094, and RCV1, 20242 x 47236): column j has
+    about density * n nonzeros scaled by a Zipf weight (a few frequent
+    terms, many rare ones; at least 1, at most n), at distinct uniformly
+    drawn rows (ascending), with |N(0,1)| values; columns scaled to unit
+    norm; y = X beta* + noise at the given SNR with a k-sparse +-1 beta*.
+    Returns col_ptr (p+1 int64), row_idx (int32), values (float32), y
+    (float32), beta_star and n."""
+    rng = _rng(seed)
+    w = 1.0 / (np.arange(1, p + 1) ** zipf)
+    w = rng.permutation(w)
+    counts = np.clip(np.round(w / w.mean() * density * n), 1, n).astype(np.int64)
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    col_ptr[1:] = np.cumsum(counts)
+    row_idx = np.empty(col_ptr[-1], dtype=np.int32)
+    vals = np.empty(col_ptr[-1], dtype=np.float64)
+    for j in range(p):
+        a, b = col_ptr[j], col_ptr[j + 1]
+        row_idx[a:b] = np.sort(rng.choice(n, size=b - a, replace=False))
+        v = np.abs(rng.standard_normal(b - a))
+        vals[a:b] = v / np.linalg.norm(v)
+    beta = _truth(rng, p, k)
+    signal = np.zeros(n)
+    for j in np.flatnonzero(beta):
+        a, b = col_ptr[j], col_ptr[j + 1]
+        signal[row_idx[a:b]] += beta[j] * vals[a:b]
+    sigma = np.linalg.norm(signal) / (snr * math.sqrt(n))
+    y = signal + sigma * rng.standard_normal(n)
+    return dict(col_ptr=col_ptr, row_idx=row_idx, values=vals.astype(np.float32),
+                y=y.astype(np.float32), beta_star=beta, n=n, p=p)
+
+
+def csc_to_dense(d):
+    """Dense (n, p) float64 copy of a sparse_text design (values widened)."""
+    X = np.zeros((d["n"], d["p"]))
+    cp, ri, v = d["col_ptr"], d["row_idx"], d["values"].astype(np.float64)
+    for j in range(d["p"]):
+        X[ri[cp[j]:cp[j + 1]], j] = v[cp[j]:cp[j + 1]]
+    return X
 
 
 def orthonormal(seed, n, p):

@@ -36,7 +36,8 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layout_matches_header():
     # offsets implied by natural alignment of the C structs
-    assert ctypes.sizeof(gs.gs_problem) == 136
+    assert ctypes.sizeof(gs.gs_problem) == 160
+    assert gs.gs_problem.format.offset == 136 and gs.gs_problem.row_idx.offset == 152
     assert gs.gs_problem.lambda_min_ratio.offset == 72
     assert gs.gs_problem.lambda_out.offset == 128
     assert ctypes.sizeof(gs.gs_opts) == 64

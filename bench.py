@@ -35,19 +35,31 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the sweep kernel from the FETCH_SIZE and WRITE_SIZE
 # counter runs in profiles/k_wide_sweep_c4_hbm_counters.md (scaled by a plain
-# copy of known size), valid while the kernel's sources hash to SWEEP_SRC_SHA1.
-SWEEP_TRAFFIC_BYTES = 408.8e6
-SWEEP_SRC_SHA1 = "9c0d1b35e3d7c287"
-SWEEP_SRCS = ("paper_1505_03410_amd/csrc/gs_wide.hpp", "paper_1505_03410_amd/csrc/gs_device.hpp")
+# copy of known size), valid while the source text of the kernel and of the
+# device helpers it uses hashes to SWEEP_SRC_SHA1.
+SWEEP_TRAFFIC_BYTES = 406.84e6
+SWEEP_SRC_SHA1 = "bf45d5958163a52b"
+# (file, first marker, end marker): the hashed slices
+SWEEP_SRCS = (
+    ("paper_1505_03410_amd/csrc/gs_wide.hpp", "// ---- the sweep:", "// ---- gap, stop test"),
+    ("paper_1505_03410_amd/csrc/gs_device.hpp", "// ---- cross-lane reductions",
+     "// ---- GAP SAFE sphere"),
+)
+
+
+def sweep_src_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f, a, b in SWEEP_SRCS:
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            t = fh.read()
+        i = t.index(a)
+        h.update(t[i:t.index(b, i)].encode())
+    return h.hexdigest()[:16]
 
 
 def sweep_traffic():
-    import hashlib
-    h = hashlib.sha1()
-    for f in SWEEP_SRCS:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return SWEEP_TRAFFIC_BYTES if h.hexdigest()[:16] == SWEEP_SRC_SHA1 else None
+    return SWEEP_TRAFFIC_BYTES if sweep_src_hash() == SWEEP_SRC_SHA1 else None
 
 
 def _log(msg):

@@ -38,6 +38,7 @@ int fail_hip(hipError_t e, const char* where) {
   } while (0)
 
 constexpr int kMaxN = 2048;
+static_assert(kMaxN <= kMaxRowsDense, "the wide refresh keeps kMaxN rows per block");
 #ifndef GS_SWEEP_BLOCKS
 #define GS_SWEEP_BLOCKS 2048
 #endif
@@ -290,8 +291,10 @@ hipError_t timed_launch(int slot, const void* k, dim3 g, dim3 b, void** args, si
                         hipStream_t s) {
   if (!g_timing) return launch(k, g, b, args, smem, s);
   Timed t{slot, nullptr, nullptr};
-  hipError_t e = hipEventCreate(&t.a);
-  if (e == hipSuccess) e = hipEventCreate(&t.b);
+  // device-scope events: no system-scope cache release around the kernel
+  const unsigned fl = hipEventDisableSystemFence;
+  hipError_t e = hipEventCreateWithFlags(&t.a, fl);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&t.b, fl);
   if (e == hipSuccess) e = hipEventRecord(t.a, s);
   if (e == hipSuccess) e = launch(k, g, b, args, smem, s);
   if (e == hipSuccess) e = hipEventRecord(t.b, s);
@@ -402,7 +405,8 @@ int run_wide(const gs_problem* pr, const gs_opts* o, const Shared& sh, ProbDesc 
     }
   }
   const int ntest = (pr->p + kTestTile - 1) / kTestTile;
-  int nsweep = kWideSweepBlocks;
+  int nsweep = std::max(1, std::min(kWideSweepBlocks, (pr->p + kSweepWaves * kSweepU - 1) /
+                                                                (kSweepWaves * kSweepU)));
   int zero = 0, one = 1;
   int32_t* nullq = nullptr;
   int32_t* nullo = nullptr;
@@ -819,7 +823,8 @@ int run_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, 
   {
     int qi = q_in, ru = rule;
     void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda, &ru};
-    HIPCHK(launch(kScreenPrep[dtype], dim3(1), dim3(256), a, 0, s));
+    const int nprep = std::max(1, std::min(1024, (p + 1023) / 1024));
+    HIPCHK(launch(kScreenPrep[dtype], dim3(nprep), dim3(256), a, 0, s));
   }
   int zero = 0, one = 1;
   {

@@ -27,40 +27,74 @@ __device__ __forceinline__ GapInfo state_gap(const ProbDesc& d, const WideState*
 
 // The GAP SAFE sphere test, and the dome test where it is on (each is safe
 // alone); or one of the comparison rules of Table 1 in their place.
-__device__ __forceinline__ bool wide_keep(const ProbDesc& d, const WideState* st,
-                                          const GapInfo& g, int j, double c) {
-  if (!(d.nrm2[j] > 0.0)) return false;
-  const double nr = d.nrm2[j] + wide_mu2(d, st);  // ||x~_j||^2 (elastic net)
+// Whether column j with c = x_j^T rho (norm^2 nrm2, x_j^T y xy, x_j^T x_{j*}
+// gsv where the rule uses them) passes the active test.
+__device__ __forceinline__ bool keep_vals(const ProbDesc& d, const WideState* st,
+                                          const GapInfo& g, double nrm2, double c, double xy,
+                                          double gsv) {
+  if (!(nrm2 > 0.0)) return false;
+  const double nr = nrm2 + wide_mu2(d, st);  // ||x~_j||^2 (elastic net)
   const int nn = wide_nn(d, st);
-  if (g.rule >= 2) return rule_keep(g, d.xty[j], g.rule == 4 ? d.gst[j] : 0.0, nr, nn);
-  return sphere_keep(g, c, nr, nn) && (!g.dome || dome_keep(g, d.xty[j], c, nr, nn));
+  if (g.rule >= 2) return rule_keep(g, xy, g.rule == 4 ? gsv : 0.0, nr, nn);
+  return sphere_keep(g, c, nr, nn) && (!g.dome || dome_keep(g, xy, c, nr, nn));
+}
+
+// Keep bits of the PER consecutive positions k0.. of A (positions >= q are
+// not kept) and their columns js.  Positions are clamped to q-1 so that
+// every load is issued, without branches, before the first test.
+template <int PER>
+__device__ __forceinline__ unsigned keep_bits(const ProbDesc& d, const WideState* st,
+                                              const GapInfo& g, const int32_t* act, bool full,
+                                              int q, int k0, int (&js)[PER]) {
+  double cs[PER], nr[PER], xy[PER], gv[PER];
+  const bool need_xy = g.dome || g.rule >= 2;
+  const bool need_g = g.rule == 4;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int k = max(0, min(k0 + e, q - 1));
+    const int ak = act[k];
+    js[e] = full ? k : ak;
+    cs[e] = d.c[k];
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    nr[e] = d.nrm2[js[e]];
+    xy[e] = need_xy ? d.xty[js[e]] : 0.0;
+    gv[e] = need_g ? d.gst[js[e]] : 0.0;
+  }
+  unsigned keep = 0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e)
+    if (k0 + e < q && keep_vals(d, st, g, nr[e], cs[e], xy[e], gv[e])) keep |= 1u << e;
+  return keep;
 }
 
 // Sphere test over one tile of A: kept count per block; screened nonzero
-// coefficients are set to zero and flagged for a residual refresh.
+// coefficients are set to zero and flagged for a residual refresh.  Thread
+// t owns 8 consecutive positions of the tile.
 __global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, WideBufs wb) {
+  constexpr int PER = kTestTile / 256;
   __shared__ double sh[256];
   if (st->done || st->phase != 1) return;
   const int q = st->q;
   const bool full = st->full != 0;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   const GapInfo g = state_gap(d, st);
-  const int tile0 = blockIdx.x * kTestTile;
-  int cnt = 0;
+  const int k0 = blockIdx.x * kTestTile + threadIdx.x * PER;
+  int js[PER];
+  const unsigned keep = keep_bits<PER>(d, st, g, act, full, q, k0, js);
+  double bz[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) bz[e] = d.beta[js[e]];
   bool dn = false;
-  for (int e = threadIdx.x; e < kTestTile; e += 256) {
-    const int k = tile0 + e;
-    if (k >= q) break;
-    const int j = full ? k : act[k];
-    if (wide_keep(d, st, g, j, d.c[k])) {
-      ++cnt;
-    } else if (d.beta[j] != 0.0) {
-      d.beta[j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e)
+    if (k0 + e < q && !((keep >> e) & 1u) && bz[e] != 0.0) {
+      d.beta[js[e]] = 0.0;
       dn = true;
     }
-  }
   if (dn) st->need_refresh = 1;
-  const double tot = block_sum<256>((double)cnt, sh);
+  const double tot = block_sum<256>((double)__popc(keep), sh);
   if (threadIdx.x == 0) wb.cnt[blockIdx.x] = (int)tot;
 }
 
@@ -80,21 +114,8 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
   for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];
   const int k0 = blockIdx.x * kTestTile + threadIdx.x * PER;
   int js[PER];
-  unsigned keep = 0;
-  int c = 0;
-#pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int k = k0 + e;
-    js[e] = -1;
-    if (k < q) {
-      const int j = full ? k : act[k];
-      js[e] = j;
-      if (wide_keep(d, st, g, j, d.c[k])) {
-        keep |= 1u << e;
-        ++c;
-      }
-    }
-  }
+  const unsigned keep = keep_bits<PER>(d, st, g, act, full, q, k0, js);
+  const int c = __popc(keep);
   scan[threadIdx.x] = c;
   __syncthreads();
   // Hillis-Steele inclusive scan over 256 counts.
@@ -110,22 +131,46 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
     if (keep & (1u << e)) dst[pos++] = js[e];
 }
 
-__global__ __launch_bounds__(256) void k_wide_lcount(ProbDesc d, WideState* st, WideBufs wb) {
-  __shared__ double sh[256];
-  if (st->done || st->phase != 2) return;
-  const int q = st->q;
-  const int tile0 = st->resume + blockIdx.x * kTestTile;
-  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+// List bits of the PER consecutive positions k0.. (positions >= q are not
+// listed), their columns js, c_k, beta_j and ||x_j||^2; positions are clamped
+// to q-1 so that every load is issued, without branches, before the first test.
+template <int PER>
+__device__ __forceinline__ unsigned listed_bits(const ProbDesc& d, const WideState* st,
+                                                const int32_t* act, int q, int k0,
+                                                int (&js)[PER], double (&cs)[PER],
+                                                double (&bs)[PER], double (&ns)[PER]) {
   const double lambda = wide_l1(d, st);
   const double tau = st->tau;
   const double rn = sqrt(st->R2) * (1.0 + gam(wide_nn(d, st) + 2));
-  int cnt = 0;
-  for (int e = threadIdx.x; e < kTestTile; e += 256) {
-    const int k = tile0 + e;
-    if (k >= q) break;
-    if (wide_listed(d, st, act[k], d.c[k], lambda, tau, rn)) ++cnt;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int k = max(0, min(k0 + e, q - 1));
+    js[e] = act[k];
+    cs[e] = d.c[k];
   }
-  const double tot = block_sum<256>((double)cnt, sh);
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    ns[e] = d.nrm2[js[e]];
+    bs[e] = d.beta[js[e]];
+  }
+  unsigned keep = 0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e)
+    if (k0 + e < q && wide_listed(d, st, ns[e], bs[e], cs[e], lambda, tau, rn)) keep |= 1u << e;
+  return keep;
+}
+
+__global__ __launch_bounds__(256) void k_wide_lcount(ProbDesc d, WideState* st, WideBufs wb) {
+  constexpr int PER = kTestTile / 256;
+  __shared__ double sh[256];
+  if (st->done || st->phase != 2) return;
+  const int q = st->q;
+  const int32_t* act = d.act + (int64_t)st->cur * d.p;
+  const int k0 = st->resume + blockIdx.x * kTestTile + threadIdx.x * PER;
+  int js[PER];
+  double cs[PER], bs[PER], ns[PER];
+  const unsigned keep = listed_bits<PER>(d, st, act, q, k0, js, cs, bs, ns);
+  const double tot = block_sum<256>((double)__popc(keep), sh);
   if (threadIdx.x == 0) wb.cnt[blockIdx.x] = (int)tot;
 }
 
@@ -135,24 +180,13 @@ __global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st
   if (st->done || st->phase != 2) return;
   const int q = st->q;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
-  const double lambda = wide_l1(d, st);
-  const double tau = st->tau;
-  const double rn = sqrt(st->R2) * (1.0 + gam(wide_nn(d, st) + 2));
   int off = 0;
   for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];
   const int k0 = st->resume + blockIdx.x * kTestTile + threadIdx.x * PER;
-  unsigned keep = 0;
-  int c = 0;
   int js[PER];
-#pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int k = k0 + e;
-    js[e] = k < q ? act[k] : 0;
-    if (k < q && wide_listed(d, st, js[e], d.c[k], lambda, tau, rn)) {
-      keep |= 1u << e;
-      ++c;
-    }
-  }
+  double cs[PER], bs[PER], ns[PER];
+  const unsigned keep = listed_bits<PER>(d, st, act, q, k0, js, cs, bs, ns);
+  const int c = __popc(keep);
   scan[threadIdx.x] = c;
   __syncthreads();
   for (int o = 1; o < 256; o <<= 1) {
@@ -171,15 +205,15 @@ __global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st
       d.lst[pos] = k0 + e;
       d.lst[d.p + pos] = j;
       double* v = d.lval + 4 * (int64_t)pos;
-      v[0] = d.c[k0 + e];
-      v[1] = d.beta[j];
+      v[0] = cs[e];
+      v[1] = bs[e];
       if (mu2 > 0.0) {  // elastic net: ||x~_j||^2
-        const double nr = d.nrm2[j] + mu2;
+        const double nr = ns[e] + mu2;
         v[2] = 1.0 / nr;
         v[3] = nr;
       } else {
         v[2] = d.inv[j];
-        v[3] = d.nrm2[j];
+        v[3] = ns[e];
       }
       ++pos;
     }
@@ -231,9 +265,12 @@ __global__ __launch_bounds__(256) void k_screen_prep(ProbDesc d, WideState* st,
                                                      const int32_t* active_in, int q_in,
                                                      double lambda, int rule) {
   __shared__ double sh[256];
-  for (int j = threadIdx.x; j < d.p; j += 256) d.beta[j] = beta_in[j];
+  // all blocks copy beta and the active list; block 0 also sets the state
+  const int g = blockIdx.x * 256 + threadIdx.x, G = gridDim.x * 256;
+  for (int j = g; j < d.p; j += G) d.beta[j] = beta_in[j];
   if (active_in)
-    for (int k = threadIdx.x; k < q_in; k += 256) d.act[k] = active_in[k];
+    for (int k = g; k < q_in; k += G) d.act[k] = active_in[k];
+  if (blockIdx.x != 0) return;
   const XT* Y = (const XT*)d.y;
   double yy = 0.0;
   for (int i = threadIdx.x; i < d.n; i += 256) {

@@ -31,6 +31,8 @@ constexpr int kSweepWaves = 4;      // waves per sweep block
 constexpr int kSweepU = GS_SWEEP_U;
 constexpr int kTestTile = 2048;     // entries per test/compact block
 constexpr int kRefreshThreads = 1024;
+constexpr int kRefreshBatch = 8;    // rows of 64 positions per refresh scan step
+constexpr int kMaxRowsDense = 2048; // largest n of a dense design on these kernels
 
 struct WideBufs {
   double* part;     // partial results, 4 per sweep block (or per pre block)
@@ -262,12 +264,26 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
   // Wave w scans positions [w*span, (w+1)*span) of A in order.
   const int span = (q + NW - 1) / NW;
   const int k0 = w * span, k1 = min(q, k0 + span);
+  // The scans take kRefreshBatch rows of 64 positions at a time, all loads
+  // of a batch issued before the first is used.
+  constexpr int RB = kRefreshBatch;
   int cntw = 0;
-  for (int base = k0; base < k1; base += 64) {
-    int k = base + lane;
-    double b = 0.0;
-    if (k < k1) b = d.beta[full ? k : act[k]];
-    cntw += __popcll(ballot(b != 0.0));
+  for (int base = k0; base < k1; base += 64 * RB) {
+    int jr[RB];
+    double br[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int k = min(base + 64 * r + lane, k1 - 1);  // clamped: loads need no branch
+      const int ak = act[k];
+      jr[r] = full ? k : ak;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double b = d.beta[jr[r]];
+      br[r] = base + 64 * r + lane < k1 ? b : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) cntw += __popcll(ballot(br[r] != 0.0));
   }
   if (lane == 0) wcnt[w] = cntw;
   __syncthreads();
@@ -277,35 +293,82 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
     nnz += wcnt[v];
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int base = k0; base < k1; base += 64) {
-    int k = base + lane;
-    int j = 0;
-    double b = 0.0;
-    if (k < k1) {
-      j = full ? k : act[k];
-      b = d.beta[j];
+  for (int base = k0; base < k1; base += 64 * RB) {
+    int jr[RB];
+    double br[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int k = min(base + 64 * r + lane, k1 - 1);  // clamped: loads need no branch
+      const int ak = act[k];
+      jr[r] = full ? k : ak;
     }
-    uint64_t m = ballot(b != 0.0);
-    if (b != 0.0) {
-      int pos = off + __popcll(m & lt);
-      wb.nzidx[pos] = j;
-      wb.nzval[pos] = b;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double b = d.beta[jr[r]];
+      br[r] = base + 64 * r + lane < k1 ? b : 0.0;
     }
-    off += __popcll(m);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const uint64_t m = ballot(br[r] != 0.0);
+      if (br[r] != 0.0) {
+        const int pos = off + __popcll(m & lt);
+        wb.nzidx[pos] = jr[r];
+        wb.nzval[pos] = br[r];
+      }
+      off += __popcll(m);
+    }
   }
   __threadfence_block();
-  __syncthreads();
+  // rho_i = y_i - sum_e beta_e x_{j_e, i} in ascending e, one thread per row;
+  // the list passes through LDS a tile at a time and each thread keeps
+  // eight column loads in flight.
+  constexpr int RT = (kMaxRowsDense + kRefreshThreads - 1) / kRefreshThreads;
+  constexpr int TILE = kRefreshThreads;
+  __shared__ int s_ix[TILE];
+  __shared__ double s_v[TILE];
   const XT* X = (const XT*)d.X;
   const XT* Y = (const XT*)d.y;
+  double v[RT], yv[RT];
+  int rr[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int i = threadIdx.x + t * kRefreshThreads;
+    rr[t] = i < d.n ? (d.rows ? d.rows[i] : i) : 0;
+    yv[t] = i < d.n ? (double)Y[rr[t]] : 0.0;
+    v[t] = yv[t];
+  }
+  for (int e0 = 0; e0 < nnz; e0 += TILE) {
+    const int ne = min(TILE, nnz - e0);
+    __syncthreads();  // the previous tile is consumed (and the list is written)
+    for (int e = threadIdx.x; e < ne; e += kRefreshThreads) {
+      s_ix[e] = wb.nzidx[e0 + e];
+      s_v[e] = wb.nzval[e0 + e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      if (threadIdx.x + t * kRefreshThreads >= d.n) continue;
+      const XT* Xr = X + rr[t];
+      int e = 0;
+      for (; e + 8 <= ne; e += 8) {
+        XT xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = Xr[(int64_t)s_ix[e + u] * d.ldx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[t] = fma(-s_v[e + u], (double)xv[u], v[t]);
+      }
+      for (; e < ne; ++e) v[t] = fma(-s_v[e], (double)Xr[(int64_t)s_ix[e] * d.ldx], v[t]);
+    }
+  }
   double s2 = 0.0, sy = 0.0;
-  for (int i = threadIdx.x; i < d.n; i += kRefreshThreads) {
-    const int r = d.rows ? d.rows[i] : i;
-    double yi = (double)Y[r];
-    double v = yi;
-    for (int e = 0; e < nnz; ++e) v = fma(-wb.nzval[e], (double)X[(int64_t)wb.nzidx[e] * d.ldx + r], v);
-    d.rho[i] = v;
-    s2 = fma(v, v, s2);
-    sy = fma(yi, v, sy);
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int i = threadIdx.x + t * kRefreshThreads;
+    if (i < d.n) {
+      d.rho[i] = v[t];
+      s2 = fma(v[t], v[t], s2);
+      sy = fma(yv[t], v[t], sy);
+    }
   }
   s2 = block_sum<kRefreshThreads>(s2, sh);
   sy = block_sum<kRefreshThreads>(sy, sh);
@@ -338,7 +401,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
   constexpr bool with_xty = WN == 2;
   using L = ColLayout<XT, VEC, 64, NG, false>;
   constexpr int RPL = L::RPL;
-  __shared__ double sh[64 * kSweepWaves];
+  __shared__ double sh[4 * kSweepWaves];
   if (st->done || st->phase != 0) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = st->q;
@@ -357,30 +420,53 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
     }
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
+  const int stride = W * kSweepU;
   const uint64_t mk = L::rowmask(lane, d.n);
   const double mu2 = WN == 0 ? wide_mu2(d, st) : 0.0;
+  // Every lane carries the same wave-wide totals (the reductions below leave
+  // the sum in all lanes); lane 0's copy is the wave's contribution.
   double Ml = 0.0, l1 = 0.0, sb = 0.0, xm = 0.0;
-  for (int base = wid * kSweepU; base < q; base += W * kSweepU) {
-    XT xv[kSweepU][RPL];
+  // Positions past q-1 are clamped to q-1: that column is computed again
+  // and its (identical) results stored again, so that the loop has no
+  // data-dependent branches and its memory waits stay exact.
+  // The wave's next step: clamped positions kn and their list entries an,
+  // loaded a step ahead; the column indices jn are selected after the
+  // step's arithmetic, when only the step's stores were issued after them.
+  int kn[kSweepU], an[kSweepU], jn[kSweepU];
+  int base = wid * kSweepU;
+#pragma unroll
+  for (int u = 0; u < kSweepU; ++u) {
+    kn[u] = max(0, min(base + u, q - 1));
+    an[u] = act[kn[u]];
+    jn[u] = __builtin_amdgcn_readfirstlane(full ? kn[u] : an[u]);
+  }
+  for (; base < q; base += stride) {
     int jj[kSweepU];
     double nrv[kSweepU], bv[kSweepU];
+    XT xv[kSweepU][RPL];
+    // the per-column scalars are issued ahead of the columns, so waiting
+    // for them leaves the columns in flight
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
-      const int k = base + u < q ? base + u : q - 1;
-      jj[u] = full ? k : act[k];
-    }
-    // the per-column scalars travel with the column loads, so one memory
-    // round trip serves the whole step
-#pragma unroll
-    for (int u = 0; u < kSweepU; ++u) {
+      jj[u] = jn[u];
       nrv[u] = with_nrm2 ? 0.0 : d.nrm2[jj[u]];
       bv[u] = d.beta[jj[u]];
     }
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u)
       L::load_raw_nt(X + (int64_t)jj[u] * d.ldx, d.n, lane, xv[u]);
+    const int nb = base + stride;
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
+      kn[u] = max(0, min(nb + u, q - 1));
+      an[u] = act[kn[u]];
+    }
+    // keep every load of the step issued before the first use
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      const bool valid = base + u < q;
+      const int kc = valid ? base + u : q - 1;
       double a = 0.0, s2 = 0.0, sy = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
@@ -394,26 +480,39 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_sweep(ProbDesc d, Wid
       a = wave_sum(a);
       if (with_nrm2) s2 = wave_sum(s2);
       if constexpr (with_xty) sy = wave_sum(sy);
-      if (base + u < q && lane == 0) {
-        const int j = jj[u];
-        if (mu2 > 0.0) a -= mu2 * bv[u];
-        d.c[base + u] = a;
-        if (with_nrm2) d.nrm2[j] = s2;
-        if constexpr (with_xty) d.xty[j] = sy;
-        const double nr = (with_nrm2 ? s2 : nrv[u]) + mu2;
-        const double b = bv[u];
-        Ml = fmax(Ml, fabs(a));
-        l1 += fabs(b);
-        sb += fabs(b) * sqrt(nr);
-        xm = fmax(xm, sqrt(nr));
-      }
+      const int j = jj[u];
+      const double b = bv[u];
+      a -= mu2 * b;  // mu2 is 0 but for the elastic net
+      // every lane stores the same value
+      d.c[kc] = a;
+      if (with_nrm2) d.nrm2[j] = s2;
+      if constexpr (with_xty) d.xty[j] = sy;
+      const double nr = (with_nrm2 ? s2 : nrv[u]) + mu2;
+      const double ab = valid ? fabs(b) : 0.0;
+      const double xn = valid ? sqrt(nr) : 0.0;
+      Ml = fmax(Ml, valid ? fabs(a) : 0.0);
+      l1 += ab;
+      sb += ab * xn;
+      xm = fmax(xm, xn);
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) jn[u] = __builtin_amdgcn_readfirstlane(full ? kn[u] : an[u]);
   }
-  Ml = block_max<64 * kSweepWaves>(Ml, sh);
-  l1 = block_sum<64 * kSweepWaves>(l1, sh);
-  sb = block_sum<64 * kSweepWaves>(sb, sh);
-  xm = block_max<64 * kSweepWaves>(xm, sh);
+  if (lane == 0) {
+    sh[4 * w + 0] = Ml;
+    sh[4 * w + 1] = l1;
+    sh[4 * w + 2] = sb;
+    sh[4 * w + 3] = xm;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int v = 1; v < kSweepWaves; ++v) {
+      Ml = fmax(Ml, sh[4 * v + 0]);
+      l1 += sh[4 * v + 1];
+      sb += sh[4 * v + 2];
+      xm = fmax(xm, sh[4 * v + 3]);
+    }
     wb.part[4 * blockIdx.x + 0] = Ml;
     wb.part[4 * blockIdx.x + 1] = l1;
     wb.part[4 * blockIdx.x + 2] = sb;
@@ -547,30 +646,55 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_wide_csweep(ProbDesc d, Wi
   const int W = gridDim.x * kSweepWaves;
   const int wid = blockIdx.x * kSweepWaves + w;
   const double mu2 = wide_mu2(d, st);
-  for (int base = k0 + wid * kSweepU; base < q; base += W * kSweepU) {
+  const int stride = W * kSweepU;
+  int base = k0 + wid * kSweepU;
+  // Positions past q-1 are clamped to q-1 (the same value is stored
+  // again).  The list entries an of the next step are loaded a step ahead
+  // and taken into jn after the step's arithmetic.
+  int an[kSweepU], jn[kSweepU];
+#pragma unroll
+  for (int u = 0; u < kSweepU; ++u) {
+    an[u] = act[max(0, min(base + u, q - 1))];
+    jn[u] = __builtin_amdgcn_readfirstlane(an[u]);
+  }
+  for (; base < q; base += stride) {
     XT xv[kSweepU][RPL];
     int jj[kSweepU];
+    double bv[kSweepU];
 #pragma unroll
-    for (int u = 0; u < kSweepU; ++u) jj[u] = act[base + u < q ? base + u : q - 1];
+    for (int u = 0; u < kSweepU; ++u) {
+      jj[u] = jn[u];
+      bv[u] = d.beta[jj[u]];
+    }
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) L::load_raw(X + (int64_t)jj[u] * d.ldx, d.n, lane, nullptr, xv[u]);
+    const int nb = base + stride;
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) an[u] = act[max(0, min(nb + u, q - 1))];
+    // keep every load of the step issued before the first use
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < kSweepU; ++u) {
       double a = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) a = fma((double)xv[u][i], r[i], a);  // r is zero at rows >= n
       a = wave_sum(a);
-      if (base + u < q && lane == 0) d.c[base + u] = mu2 > 0.0 ? a - mu2 * d.beta[jj[u]] : a;
+      d.c[base + u < q ? base + u : q - 1] = a - mu2 * bv[u];  // every lane stores the same value
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) jn[u] = __builtin_amdgcn_readfirstlane(an[u]);
   }
 }
 
-// Whether position k (>= resume) must be visited exactly in this round.
-__device__ __forceinline__ bool wide_listed(const ProbDesc& d, const WideState* st, int j,
-                                            double ck, double lambda, double tau, double rnorm) {
-  const double nr = d.nrm2[j] + wide_mu2(d, st);
-  if (!(d.nrm2[j] > 0.0)) return false;  // a zero column never moves
-  if (d.beta[j] != 0.0) return true;
+// Whether position k (>= resume) must be visited exactly in this round;
+// nrm2 = ||x_j||^2 and b = beta_j of its column, ck its anchored correlation.
+__device__ __forceinline__ bool wide_listed(const ProbDesc& d, const WideState* st, double nrm2,
+                                            double b, double ck, double lambda, double tau,
+                                            double rnorm) {
+  const double nr = nrm2 + wide_mu2(d, st);
+  if (!(nrm2 > 0.0)) return false;  // a zero column never moves
+  if (b != 0.0) return true;
   const int nn = wide_nn(d, st);
   const double xn = sqrt(nr) * (1.0 + gam(nn + 2));
   // |c^_k - x_k^T rho_a| <= gamma_{n+1} ||x_k|| ||rho_a||

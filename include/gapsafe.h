@@ -413,24 +413,65 @@ int gs_warm_features(int32_t p, const double* c, const double* beta_prev,
  * t = 0 when beta_init is given: the previous point is then beta_init, so a
  * path may be run in consecutive pieces):
  *   1. a screening pass at the previous point beta^{lambda_{t-1}} over all
- *      p gives the safe set A_plain and c;
- *   2. the network maps u_j to (o0_j, o1_j); beta0_j = beta_prev_j +
- *      o0_j lambda_t / ||x_j||^2 where j is in A_plain and o1_j > 0, else 0
- *      (coordinates outside A_plain are zero at the optimum);
- *   3. the duality gaps of beta0 and of beta^{lambda_{t-1}} on the problem
+ *      p gives the safe set A_plain and c (coordinates outside A_plain are
+ *      zero at the optimum);
+ *   2. the network maps u_j to (o0_j, o1_j); the working set W holds the j
+ *      of A_plain on the support of beta_prev and those off it with o1_j >
+ *      tau (the network's predicted entrants), tau the first of 0, 1, 2, 3,
+ *      4, 6, 8 that admits at most min(GS_WS_ADD, (cap - |supp beta_prev|)
+ *      / 2) entrants (none if 8 admits more); signs sigma_j =
+ *      sign(beta_prev_j) on the previous support and sign(c_j) elsewhere;
+ *   3. the restricted solve (gs_restricted_solve below) gives b on W; the
+ *      coordinates whose sign disagrees with sigma leave W (those off the
+ *      previous support when there are any such, else the others) and W is
+ *      solved again (at most GS_WS_DROPS times); beta0 = b on W, 0 elsewhere;
+ *   4. at most GS_WS_ROUNDS times: a screening pass at beta0 over A_plain
+ *      gives c; the (at most GS_WS_ADD) largest violators |c_j| > lambda_t
+ *      outside W join W with sigma_j = sign(c_j), and step 3 runs again;
+ *      no violator ends the rounds;
+ *   5. the duality gaps of beta0 and of beta^{lambda_{t-1}} on the problem
  *      reduced to A_plain are compared, and the smaller one's point starts
  *      lambda_t (ties keep the plain start);
- *   4. Algorithm 1 runs for lambda_t from there, exactly as in lasso_path.
+ *   6. Algorithm 1 runs for lambda_t from there, exactly as in lasso_path.
+ * A working set larger than cap = min(n - 1, p, GS_WS_MAX) or a failed
+ * factorization (a pivot that is not positive) leaves lambda_t to the plain
+ * start.  The output o0 is not used by the driver (the restricted solve
+ * gives the coefficients).
  * With params NULL every lambda starts from the previous point (the plain
  * path, run one lambda at a time).  The problem has no row subsample and all
  * its outputs; block (1..64) is the bmc block width.  learned_out (optional,
  * T int32) receives 1 where the network's start was taken, else 0.
- * Synchronizes `stream` (the lambda grid and the active set sizes are read
- * on the host).  Returns the codes of lasso_path. */
+ * Synchronizes `stream` (the lambda grid, the active set and working set
+ * sizes are read on the host).  Returns the codes of lasso_path. */
+enum { GS_WS_ROUNDS = 4, GS_WS_ADD = 32, GS_WS_DROPS = 4, GS_WS_MAX = 2047 };
 size_t lasso_path_learned_workspace_size(const gs_problem* prob);
 int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float* params,
                        int32_t block, int32_t* learned_out, void* workspace,
                        size_t ws_bytes, void* stream);
+
+/* The restricted solve of the learned start.  On the working set W (m
+ * distinct column indices) with signs sigma (+1 or -1), the Lasso's
+ * optimality conditions (Sec. 2: the subgradient of ||beta||_1 at a nonzero
+ * beta_j is sign(beta_j)) reduce to the linear system
+ *     (X_W^T X_W) b = X_W^T y - lambda sigma,
+ * whose solution is the Lasso solution at lambda when W holds its support,
+ * sigma its signs, b has those signs and |x_j^T (y - X_W b)| <= lambda for
+ * every other column.  Solved in FP64 by a blocked Cholesky factorization of
+ * the Gram matrix (products of the stored X values, exact in FP64).
+ * n, p, ldx, dtype, X, y as in gs_problem (column-major X, no row subsample);
+ * W [device] m int32 in [0, p); sigma [device] m doubles; 1 <= m < n, m <= p,
+ * m <= GS_WS_MAX (X_W must have full column rank); lambda >= 0 finite;
+ * b_out [device] m doubles; info_out [device] 1 int32: 0 on success, k >= 1
+ * when the k-th pivot was not positive (X_W numerically rank deficient;
+ * b_out is then not written), -1 for an index of W outside [0, p).
+ * workspace: gs_restricted_solve_workspace_size(m) bytes (about 8 m^2), or
+ * 0 for an m out of range.  Asynchronous on `stream`.  GS_EINVAL for a bad
+ * size, pointer or value, GS_EWORKSPACE for a small workspace. */
+size_t gs_restricted_solve_workspace_size(int32_t m);
+int gs_restricted_solve(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
+                        const void* y, const int32_t* W, const double* sigma, int32_t m,
+                        double lambda, double* b_out, int32_t* info_out, void* workspace,
+                        size_t ws_bytes, void* stream);
 
 /* Optional kernel timing for benchmarks (off by default).  When on, the
  * library records a pair of HIP events on the launch stream around each

@@ -342,3 +342,15 @@ def warm_features(c, lam, lam_max, beta_prev, nrm, ynorm, bmc):
                      beta_prev * nrm / ynorm,
                      bmc], axis=1)
 
+
+
+def restricted_solve(X, y, W, sigma, lam):
+    """The restricted solve of the learned start (Sec. 2, optimality
+    conditions of the Lasso: at a solution, x_j^T (y - X beta) = lambda
+    sign(beta_j) on the support).  For the columns W with signs sigma, the
+    coefficients b on W that satisfy those conditions with equality solve
+        (X_W^T X_W) b = X_W^T y - lambda sigma.
+    FP64, through a library linear solve."""
+    XW = np.asarray(X, dtype=np.float64)[:, np.asarray(W)]
+    rhs = XW.T @ np.asarray(y, dtype=np.float64) - lam * np.asarray(sigma, dtype=np.float64)
+    return np.linalg.solve(XW.T @ XW, rhs)

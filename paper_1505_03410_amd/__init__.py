@@ -76,7 +76,8 @@ EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_
            "gs_timing_reset", "gs_timing_query", "lasso_strerror",
            "gs_block_corr", "gs_mlp_forward", "gs_mlp_train_workspace_size", "gs_mlp_grad",
            "gs_mlp_adam", "gs_mlp_train_step", "gs_warm_features",
-           "lasso_path_learned_workspace_size", "lasso_path_learned"]
+           "lasso_path_learned_workspace_size", "lasso_path_learned",
+           "gs_restricted_solve_workspace_size", "gs_restricted_solve"]
 
 MLP_PARAMS = 4610
 # offsets of the parameter array (include/gapsafe.h): name -> (offset, shape)
@@ -158,6 +159,11 @@ def load_library(path: str = LIB_PATH):
     lib.gs_warm_features.restype = ctypes.c_int
     lib.lasso_path_learned_workspace_size.argtypes = [P(gs_problem)]
     lib.lasso_path_learned_workspace_size.restype = sz
+    lib.gs_restricted_solve_workspace_size.argtypes = [i32]
+    lib.gs_restricted_solve_workspace_size.restype = sz
+    lib.gs_restricted_solve.argtypes = [i32, i32, ctypes.c_int64, i32, vp, vp, vp, vp, i32, f64,
+                                        vp, vp, vp, sz, vp]
+    lib.gs_restricted_solve.restype = ctypes.c_int
     lib.lasso_path_learned.argtypes = [P(gs_problem), P(gs_opts), vp, i32, vp, vp, sz, vp]
     lib.lasso_path_learned.restype = ctypes.c_int
     _lib = lib
@@ -679,6 +685,30 @@ def warm_features(c, beta_prev, nrm2, bmc, lam, lam_max, ynorm, stream=None):
                                            float(lam), float(lam_max), float(ynorm), _ptr(U),
                                            _stream_ptr(stream)), allow_not_converged=False)
     return U
+
+
+def restricted_solve(X, y, W, sigma, lam, stream=None):
+    """b on the working set W (int32 column indices) with signs sigma
+    (float64 +-1): (X_W^T X_W) b = X_W^T y - lam sigma (gs_restricted_solve).
+    Returns (b, info) with info the device status (0 = solved)."""
+    torch = _torch()
+    n, p = X.shape
+    m = W.numel()
+    if W.dtype != torch.int32 or not W.is_cuda or not W.is_contiguous():
+        raise ValueError("W must be a contiguous int32 device tensor")
+    if sigma.dtype != torch.float64 or not sigma.is_contiguous() or sigma.numel() != m:
+        raise ValueError("sigma must be m contiguous float64 values")
+    if y.dtype != X.dtype or not y.is_contiguous():
+        raise ValueError("y must be a contiguous device tensor of X's dtype")
+    lib = load_library()
+    need = lib.gs_restricted_solve_workspace_size(m)
+    ws = torch.empty(max(int(need), 1), dtype=torch.uint8, device=X.device)
+    b = torch.empty(m, dtype=torch.float64, device=X.device)
+    info = torch.zeros(1, dtype=torch.int32, device=X.device)
+    _check(lib.gs_restricted_solve(n, p, X.stride(1), _dtype_code(X), _ptr(X), _ptr(y), _ptr(W),
+                                   _ptr(sigma), m, float(lam), _ptr(b), _ptr(info), _ptr(ws),
+                                   ws.numel(), _stream_ptr(stream)), allow_not_converged=False)
+    return b, info
 
 
 def lasso_path_learned(X, y, params=None, *, block: int = 50, T: int = 100,

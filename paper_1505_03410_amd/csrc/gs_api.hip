@@ -821,7 +821,7 @@ int run_screen(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X, 
   po.f = 1;
   po.K = 0;
   {
-    int qi = q_in, ru = rule;
+    int qi = q, ru = rule;  // all p positions when active_in is NULL (q_in is ignored)
     void* a[] = {&d, &st, (void*)&beta, (void*)&active_in, &qi, &lambda, &ru};
     const int nprep = std::max(1, std::min(1024, (p + 1023) / 1024));
     HIPCHK(launch(kScreenPrep[dtype], dim3(nprep), dim3(256), a, 0, s));

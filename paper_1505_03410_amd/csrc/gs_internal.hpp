@@ -98,6 +98,24 @@ constexpr int kMlpW1 = 0, kMlpB1 = 256, kMlpW2 = 320, kMlpB2 = 4416, kMlpW3 = 44
 // Records the text of a HIP failure for lasso_strerror and returns GS_EHIP.
 int set_hip_error(hipError_t e, const char* where);
 
+// ---- restricted solve and working sets of the learned start (gs_ws.hip).
+constexpr int kWsMaxSet = 2047;  // largest working set (a system of at most 2048 unknowns)
+size_t ws_solve_bytes(int m);
+// (X_W^T X_W) b = X_W^T y - lambda sigma for the m columns W; info (device) = 0 on
+// success, the 1-based row of a non-positive pivot, or -1 for an index outside [0, p).
+int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y, const int32_t* W,
+             const double* sigma, int m, double lambda, double* b_out, int32_t* info,
+             void* workspace, hipStream_t s);
+int ws_select(const float* out, const int32_t* act, int q, const double* bprev, const double* c,
+              float tau, int cap, int32_t* W, double* sigma, int32_t* mark, int32_t* cnt,
+              hipStream_t s);
+int ws_drop(int32_t* W, double* sigma, double* b, int32_t* mark, const double* bprev,
+            int32_t* cnt, hipStream_t s);
+int ws_add(const int32_t* act, int q, const double* c, double lambda, int kadd, int cap,
+           int32_t* W, double* sigma, int32_t* mark, int32_t* cnt, hipStream_t s);
+int ws_scatter(const int32_t* W, const double* b, const int32_t* cnt, int p, double* beta0,
+               hipStream_t s);
+
 // Scalars of the wide schedule's state machine (one problem).
 struct WideState {
   // set by init

@@ -385,21 +385,6 @@ __global__ __launch_bounds__(256) void k_absmax_ynorm(const double* __restrict__
   }
 }
 
-// The network's start, on the first q positions of act (the plain pass's
-// safe active set; everything else was zeroed beforehand): where the support
-// logit is positive, beta0_j = beta_prev_j + o0_j lambda / ||x_j||^2 (the
-// network predicts the change of the coefficient in units of
-// lambda / ||x_j||^2), else 0.
-__global__ void k_warm_set(const float* __restrict__ out, const int32_t* __restrict__ act, int q,
-                           const double* __restrict__ bprev, const double* __restrict__ nrm2,
-                           double lam, double* __restrict__ beta0) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < q; k += gridDim.x * blockDim.x) {
-    const int j = act[k];
-    if (out[(int64_t)j * 2 + 1] > 0.f && nrm2[j] > 0.0)
-      beta0[j] = bprev[j] + (double)out[(int64_t)j * 2] * lam / nrm2[j];
-  }
-}
-
 // start = the network's candidate when its gap is strictly smaller, else the
 // plain one; flag = 1 when the network's was taken.
 __global__ void k_warm_choose(const double* __restrict__ gap_plain,
@@ -470,6 +455,12 @@ struct LearnedWs {
   float *bmc, *U, *out;
   double *nrm2, *c, *beta0, *start, *scal;  // scal: lmax, ||y||^2, gap_plain, gap_net, alpha, radius
   int32_t *act, *act2, *q;
+  // working set: W, sigma, b (cap entries each), membership marks (p), c at
+  // beta0 by position (p), counters (|W|, dropped, added, info), solve space
+  int32_t *W, *mark, *cnt;
+  double *sig, *bw, *c2;
+  void* wsolve;
+  int cap;
   size_t total;
 };
 
@@ -497,8 +488,83 @@ LearnedWs carve_learned(const gs_problem* pr, char* base) {
   w.act = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * P));
   w.act2 = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * P));
   w.q = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 4));
+  w.cap = std::max(0, std::min(pr->n - 1, std::min(pr->p, kWsMaxSet)));
+  const size_t C = (size_t)std::max(w.cap, 1);
+  w.W = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * C));
+  w.sig = reinterpret_cast<double*>(take(sizeof(double) * C));
+  w.bw = reinterpret_cast<double*>(take(sizeof(double) * C));
+  w.mark = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * P));
+  w.c2 = reinterpret_cast<double*>(take(sizeof(double) * P));
+  w.cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 4));
+  w.wsolve = take(ws_solve_bytes((int)C));
   w.total = off;
   return w;
+}
+
+// Reads the four working-set counters (|W|, dropped, added, info).
+int read_cnt(const LearnedWs& w, int32_t (&h)[4], hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(h, w.cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? GS_OK : set_hip_error(e, "lasso_path_learned: working set");
+}
+
+// The working-set start (steps 2-4 of lasso_path_learned) into w.beta0; m
+// receives |W| (0: no start, the plain one is used).  Needs the network's
+// outputs in w.out, A_plain in w.act (q positions) and c at beta_prev in w.c.
+int ws_start(const gs_problem* pr, const LearnedWs& w, int q, const double* bprev, double lam,
+             int rule, int& m, hipStream_t s) {
+  const int n = pr->n, p = pr->p, dt = pr->dtype;
+  m = 0;
+  // the previous support and the network's predicted entrants, the logit
+  // threshold raised until at most min(GS_WS_ADD, (cap - |previous support|)
+  // / 2) enter (none when even the last threshold admits more)
+  int32_t h[4];
+  int mm = 0;
+  for (float tau : {0.f, 1.f, 2.f, 3.f, 4.f, 6.f, 8.f, INFINITY}) {
+    int rc = fill_i32(w.mark, p, 0, s);
+    if (rc) return rc;
+    rc = fill_i32(w.cnt, 4, 0, s);
+    if (rc) return rc;
+    rc = ws_select(w.out, w.act, q, bprev, w.c, tau, w.cap, w.W, w.sig, w.mark, w.cnt, s);
+    if (rc) return rc;
+    rc = read_cnt(w, h, s);
+    if (rc) return rc;
+    mm = h[0];
+    const int kin = std::min((int)GS_WS_ADD, std::max(0, (w.cap - (h[0] - h[1])) / 2));
+    if (h[1] <= kin) break;
+  }
+  if (mm < 1 || mm > w.cap) return GS_OK;
+  int rc = GS_OK;
+  for (int r = 0;; ++r) {
+    for (int dd = 0;; ++dd) {
+      rc = ws_solve(n, p, pr->ldx, dt, pr->X, pr->y, w.W, w.sig, mm, lam, w.bw, w.cnt + 3,
+                    w.wsolve, s);
+      if (rc) return rc;
+      rc = ws_drop(w.W, w.sig, w.bw, w.mark, bprev, w.cnt, s);
+      if (rc) return rc;
+      rc = read_cnt(w, h, s);
+      if (rc) return rc;
+      if (h[3] != 0) return GS_OK;  // factorization failed: plain start
+      mm = h[0];
+      if (mm < 1) return GS_OK;
+      if (h[1] == 0 || dd >= GS_WS_DROPS) break;
+    }
+    rc = ws_scatter(w.W, w.bw, w.cnt, p, w.beta0, s);
+    if (rc) return rc;
+    if (r >= GS_WS_ROUNDS) break;
+    // violators of the optimality conditions at beta0 over A_plain
+    rc = screen(n, p, pr->ldx, dt, pr->X, pr->y, w.beta0, lam, rule, w.act, q, w.act2, w.q + 1,
+                w.scal + 3, w.scal + 4, w.scal + 5, w.c2, w.inner, w.inner_bytes, s);
+    if (rc) return rc;
+    rc = ws_add(w.act, q, w.c2, lam, GS_WS_ADD, w.cap, w.W, w.sig, w.mark, w.cnt, s);
+    if (rc) return rc;
+    rc = read_cnt(w, h, s);
+    if (rc) return rc;
+    if (h[2] == 0) break;
+    mm = h[0];
+  }
+  m = mm;
+  return GS_OK;
 }
 
 bool learned_problem_ok(const gs_problem* pr) {
@@ -692,29 +758,27 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
       hipError_t e = hipMemcpyAsync(&q, w.q, sizeof(q), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) return set_hip_error(e, "lasso_path_learned: active size");
-      if (q > 0 && q <= p) {
-        hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(p, 256)), dim3(256), 0, s, w.beta0, p, 0.0);
-        rc = last_launch("k_fill_f64");
+      if (q > 0 && q <= p && w.cap >= 1) {
+        int m = 0;
+        rc = ws_start(prob, w, q, bprev, lam[t], rule, m, s);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_warm_set, dim3(grid_for(q, 256)), dim3(256), 0, s, w.out, w.act, q,
-                           bprev, w.nrm2, lam[t], w.beta0);
-        rc = last_launch("k_warm_set");
-        if (rc) return rc;
-        // both candidates' gaps on the reduced problem over A_plain
-        rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], rule, w.act, q, w.act2,
-                    w.q + 1, w.scal + 2, w.scal + 4, w.scal + 5, nullptr, w.inner, w.inner_bytes,
-                    s);
-        if (rc) return rc;
-        rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, w.beta0, lam[t], rule, w.act, q, w.act2,
-                    w.q + 1, w.scal + 3, w.scal + 4, w.scal + 5, nullptr, w.inner, w.inner_bytes,
-                    s);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_warm_choose, dim3(grid_for(p, 256)), dim3(256), 0, s, w.scal + 2,
-                           w.scal + 3, w.beta0, bprev, p, w.start,
-                           learned_out ? learned_out + t : nullptr);
-        rc = last_launch("k_warm_choose");
-        if (rc) return rc;
-        startp = w.start;
+        if (m >= 1) {
+          // both candidates' gaps on the reduced problem over A_plain
+          rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], rule, w.act, q,
+                      w.act2, w.q + 1, w.scal + 2, w.scal + 4, w.scal + 5, nullptr, w.inner,
+                      w.inner_bytes, s);
+          if (rc) return rc;
+          rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, w.beta0, lam[t], rule, w.act, q,
+                      w.act2, w.q + 1, w.scal + 3, w.scal + 4, w.scal + 5, nullptr, w.inner,
+                      w.inner_bytes, s);
+          if (rc) return rc;
+          hipLaunchKernelGGL(k_warm_choose, dim3(grid_for(p, 256)), dim3(256), 0, s, w.scal + 2,
+                             w.scal + 3, w.beta0, bprev, p, w.start,
+                             learned_out ? learned_out + t : nullptr);
+          rc = last_launch("k_warm_choose");
+          if (rc) return rc;
+          startp = w.start;
+        }
       }
     }
     gs_problem sub = *prob;

@@ -1,0 +1,690 @@
+// The restricted solve of the learned start.  On a working set W of columns
+// with a sign pattern sigma, the Lasso's optimality conditions (Sec. 2: the
+// subgradient of ||beta||_1 is sign(beta_j) on the support) reduce to the
+// linear system
+//     (X_W^T X_W) b = X_W^T y - lambda sigma,
+// whose solution is the Lasso solution at lambda whenever W holds the
+// support, sigma its signs, b has those signs and every other column's
+// correlation stays within lambda.  The system is solved in FP64 by a blocked
+// Cholesky factorization (64 x 64 tiles): the Gram matrix of W (products of
+// the stored values, exact in FP64), then per tile column a factorization of
+// the diagonal tile, a triangular solve of the tiles below it and an update of
+// the trailing tiles, then two triangular solves.  The matrix is M x M column
+// major with M = m rounded up to 64 and the identity on the padding; the
+// factor L lives in the lower triangle and its transpose is mirrored into the
+// upper triangle so that both triangular solves read columns.
+//
+// Around it, the working-set kernels of the learned path driver: the initial
+// set from the network's support logits, dropping coordinates whose sign
+// disagrees with sigma, the largest violators of |x_j^T rho| <= lambda added,
+// and the scatter of b into a p-vector.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "../../include/gapsafe.h"
+#include "gs_device.hpp"
+#include "gs_internal.hpp"
+
+namespace gs {
+namespace {
+
+static_assert(kWsMaxSet == GS_WS_MAX, "working-set limit of the C ABI");
+constexpr int TB = 64;  // tile size
+
+__device__ __forceinline__ bool ws_failed(const int32_t* info) { return *info != 0; }
+
+// ---- Gram tiles: block (I, J), I >= J, computes G[I-tile rows][J-tile cols]
+// over all n rows; rows pass through LDS 32 at a time.  Padding entries get
+// the identity.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64_t ldx, int n,
+                                                 int p, const int32_t* __restrict__ W, int m,
+                                                 int M, double* __restrict__ G) {
+  constexpr int RC = 32;
+  __shared__ double A[RC][TB + 1], B[RC][TB + 1];
+  __shared__ int64_t ca[TB], cb[TB];
+  // tile (I, J) from the block index: lower tiles in column order
+  int b = blockIdx.x, J = 0;
+  const int NT = M / TB;
+  while (b >= NT - J) {
+    b -= NT - J;
+    ++J;
+  }
+  const int I = J + b;
+  const int t = threadIdx.x;
+  if (t < TB) {
+    const int a = I * TB + t;
+    ca[t] = a < m ? (int64_t)min(max(W[a], 0), p - 1) * ldx : -1;
+  } else if (t < 2 * TB) {
+    const int a = J * TB + (t - TB);
+    cb[t - TB] = a < m ? (int64_t)min(max(W[a], 0), p - 1) * ldx : -1;
+  }
+  __syncthreads();
+  const int ta = t >> 4, tb = t & 15;  // this thread's 4 x 4 entries
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int r0 = 0; r0 < n; r0 += RC) {
+    // 64 columns x 32 rows per tile; consecutive threads read consecutive rows
+#pragma unroll
+    for (int i = 0; i < (RC * TB) / 256; ++i) {
+      const int e = t + 256 * i;
+      const int col = e / RC, rr = e % RC;
+      const int r = r0 + rr;
+      const int64_t oa = ca[col], ob = cb[col];
+      A[rr][col] = (oa >= 0 && r < n) ? (double)X[oa + r] : 0.0;
+      B[rr][col] = (ob >= 0 && r < n) ? (double)X[ob + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < RC; ++rr) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = A[rr][ta * 4 + u];
+        bv[u] = B[rr][tb * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ga = I * TB + ta * 4 + u, gb = J * TB + tb * 4 + v;
+      double val = acc[u][v];
+      if (ga >= m || gb >= m) val = ga == gb ? 1.0 : 0.0;
+      G[(int64_t)gb * M + ga] = val;
+    }
+}
+
+// ---- right-hand side b_a = x_{W_a}^T y - lambda sigma_a (0 on the padding),
+// one wavefront per entry; an index outside [0, p) sets info = -1.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_t ldx, int n, int p,
+                                                const XT* __restrict__ y,
+                                                const int32_t* __restrict__ W,
+                                                const double* __restrict__ sigma, int m, int M,
+                                                double lambda, double* __restrict__ b,
+                                                int32_t* info) {
+  const int lane = threadIdx.x & 63;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= M) return;
+  if (a >= m) {
+    if (lane == 0) b[a] = 0.0;
+    return;
+  }
+  const int j0 = W[a];
+  if (j0 < 0 || j0 >= p) {
+    if (lane == 0) *info = -1;
+    return;
+  }
+  const XT* col = X + (int64_t)j0 * ldx;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) s = fma((double)col[i], (double)y[i], s);
+  s = wave_sum(s);
+  if (lane == 0) b[a] = s - lambda * sigma[a];
+}
+
+// ---- factorization of the diagonal tile K in LDS (unblocked, right-looking);
+// writes L_KK to the lower triangle and its transpose to the upper one.  A
+// pivot that is not positive (or not finite) stops the factorization with
+// info = its 1-based row.
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M, int K,
+                                                   int32_t* info) {
+  __shared__ double T[TB][TB + 1];
+  if (ws_failed(info)) return;
+  const int t = threadIdx.x;
+  const int64_t o = (int64_t)K * TB;
+  for (int e = t; e < TB * TB; e += 256) {
+    const int i = e % TB, j = e / TB;
+    T[i][j] = G[(o + j) * M + o + i];
+  }
+  __syncthreads();
+  for (int c = 0; c < TB; ++c) {
+    const double piv = T[c][c];
+    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread read the same value
+      if (t == 0) *info = (int32_t)(o + c + 1);
+      return;
+    }
+    const double dg = sqrt(piv);
+    __syncthreads();  // every thread has read the pivot
+    if (t > c && t < TB) T[t][c] /= dg;
+    if (t == 0) T[c][c] = dg;
+    __syncthreads();
+    const int w = TB - 1 - c;  // trailing block (c+1 .. 63)^2, lower part
+    for (int e = t; e < w * w; e += 256) {
+      const int i = c + 1 + e % w, j = c + 1 + e / w;
+      if (i >= j) T[i][j] = fma(-T[i][c], T[j][c], T[i][j]);
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < TB * TB; e += 256) {
+    const int i = e % TB, j = e / TB;
+    if (i >= j) {
+      G[(o + j) * M + o + i] = T[i][j];
+      G[(o + i) * M + o + j] = T[i][j];
+    }
+  }
+}
+
+// ---- tiles below the diagonal: L_IK = G_IK L_KK^{-T}, one block per tile
+// row I > K, one thread per row of the tile.
+__global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int M, int K,
+                                                   int32_t* info) {
+  __shared__ double L[TB][TB + 1];
+  if (ws_failed(info)) return;
+  const int r = threadIdx.x;
+  const int I = K + 1 + blockIdx.x;
+  const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB;
+  for (int e = r; e < TB * TB; e += 64) {
+    const int i = e % TB, j = e / TB;
+    L[i][j] = G[(o + j) * M + o + i];
+  }
+  __syncthreads();
+  double x[TB];
+#pragma unroll
+  for (int c = 0; c < TB; ++c) x[c] = G[(o + c) * M + oi + r];
+#pragma unroll
+  for (int c = 0; c < TB; ++c) {
+    double v = x[c];
+#pragma unroll
+    for (int k = 0; k < c; ++k) v = fma(-x[k], L[c][k], v);
+    x[c] = v / L[c][c];
+  }
+#pragma unroll
+  for (int c = 0; c < TB; ++c) {
+    G[(o + c) * M + oi + r] = x[c];
+    G[(oi + r) * M + o + c] = x[c];
+  }
+}
+
+// ---- trailing update G_IJ -= L_IK L_JK^T for K < J <= I, one block per tile.
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int M, int K,
+                                                     int32_t* info) {
+  __shared__ double A[TB][TB + 1], B[TB][TB + 1];
+  if (ws_failed(info)) return;
+  const int NT = M / TB;
+  const int T = NT - K - 1;
+  int b = blockIdx.x, jj = 0;
+  while (b >= T - jj) {
+    b -= T - jj;
+    ++jj;
+  }
+  const int J = K + 1 + jj, I = J + b;
+  const int t = threadIdx.x;
+  const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, oj = (int64_t)J * TB;
+  for (int e = t; e < TB * TB; e += 256) {
+    const int i = e % TB, k = e / TB;
+    A[i][k] = G[(o + k) * M + oi + i];
+    B[i][k] = G[(o + k) * M + oj + i];
+  }
+  __syncthreads();
+  const int ta = t >> 4, tb = t & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 8
+  for (int k = 0; k < TB; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = A[ta * 4 + u][k];
+      bv[u] = B[tb * 4 + u][k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t idx = (oj + tb * 4 + v) * M + oi + ta * 4 + u;
+      G[idx] -= acc[u][v];
+    }
+}
+
+// ---- L z = b, then L^T x = z, one block; x_out gets the first m entries.
+// Each thread owns rows t, t + 1024 and loads its entries of the next column
+// while the current one is applied.
+constexpr int kSolveThreads = 1024;
+constexpr int kSolveRows = 2048 / kSolveThreads;
+__global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __restrict__ G, int M,
+                                                              const double* __restrict__ b,
+                                                              int m, double* __restrict__ x_out,
+                                                              int32_t* info) {
+  __shared__ double z[2048];
+  if (ws_failed(info)) return;
+  const int t = threadIdx.x;
+  for (int i = t; i < M; i += kSolveThreads) z[i] = b[i];
+  __syncthreads();
+  // forward: z_c /= L_cc, then z_i -= L_ic z_c below c (column c of L)
+  double nx[kSolveRows];
+#pragma unroll
+  for (int u = 0; u < kSolveRows; ++u) {
+    const int i = t + u * kSolveThreads;
+    nx[u] = i < M ? G[i] : 0.0;  // column 0
+  }
+  double dn = G[0];  // diagonal entry of the next column
+  for (int c = 0; c < M; ++c) {
+    double cur[kSolveRows];
+#pragma unroll
+    for (int u = 0; u < kSolveRows; ++u) cur[u] = nx[u];
+    const double dc = dn;
+    if (c + 1 < M) {
+#pragma unroll
+      for (int u = 0; u < kSolveRows; ++u) {
+        const int i = t + u * kSolveThreads;
+        nx[u] = i < M ? G[(int64_t)(c + 1) * M + i] : 0.0;
+      }
+      dn = G[(int64_t)(c + 1) * M + c + 1];
+    }
+    const double zc = z[c] / dc;
+    __syncthreads();  // every thread has read z[c]
+#pragma unroll
+    for (int u = 0; u < kSolveRows; ++u) {
+      const int i = t + u * kSolveThreads;
+      if (i > c && i < M) z[i] = fma(-cur[u], zc, z[i]);
+      if (i == c) z[i] = zc;
+    }
+    __syncthreads();
+  }
+  // backward: x_c = z_c / L_cc, then z_j -= L_cj x_c above c (row c of L =
+  // column c of the mirrored upper triangle)
+#pragma unroll
+  for (int u = 0; u < kSolveRows; ++u) {
+    const int i = t + u * kSolveThreads;
+    nx[u] = i < M ? G[(int64_t)(M - 1) * M + i] : 0.0;
+  }
+  dn = G[(int64_t)(M - 1) * M + M - 1];
+  for (int c = M - 1; c >= 0; --c) {
+    double cur[kSolveRows];
+#pragma unroll
+    for (int u = 0; u < kSolveRows; ++u) cur[u] = nx[u];
+    const double dc = dn;
+    if (c > 0) {
+#pragma unroll
+      for (int u = 0; u < kSolveRows; ++u) {
+        const int i = t + u * kSolveThreads;
+        nx[u] = i < M ? G[(int64_t)(c - 1) * M + i] : 0.0;
+      }
+      dn = G[(int64_t)(c - 1) * M + c - 1];
+    }
+    const double xc = z[c] / dc;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSolveRows; ++u) {
+      const int i = t + u * kSolveThreads;
+      if (i < c) z[i] = fma(-cur[u], xc, z[i]);
+      if (i == c) z[i] = xc;
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < m; i += kSolveThreads) x_out[i] = z[i];
+}
+
+// ---- working-set kernels of the learned driver (one block each unless
+// stated).  cnt[0] = |W|; mark (p int32) flags the members of W.
+
+// W = positions of act (q of them) on the support of beta_prev or whose
+// support logit o1 > tau, in order; sigma = sign(beta_prev) on its support,
+// else sign(c) (c indexed by column).  cnt[0] = |W|, cnt[1] = the members
+// off the previous support.
+__global__ __launch_bounds__(1024) void k_ws_select(const float* __restrict__ out,
+                                                    const int32_t* __restrict__ act, int q,
+                                                    const double* __restrict__ bprev,
+                                                    const double* __restrict__ c, float tau, int cap,
+                                                    int32_t* __restrict__ W,
+                                                    double* __restrict__ sigma,
+                                                    int32_t* __restrict__ mark,
+                                                    int32_t* __restrict__ cnt) {
+  __shared__ int wc[16];
+  __shared__ int nw[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int base_off = 0, new_tot = 0;
+  for (int base = 0; base < q; base += 1024) {
+    const int k = base + t;
+    int j = 0;
+    bool in = false, fresh = false;
+    if (k < q) {
+      j = act[k];
+      const bool prev = bprev && bprev[j] != 0.0;
+      fresh = !prev && out[2 * (int64_t)j + 1] > tau;
+      in = prev || fresh;
+    }
+    const uint64_t fm = ballot(fresh);
+    if (lane == 0) nw[w] = __popcll(fm);
+    const uint64_t m = ballot(in);
+    if (lane == 0) wc[w] = __popcll(m);
+    __syncthreads();
+    int off = base_off, tot = 0;
+    for (int v = 0; v < 16; ++v) {
+      if (v < w) off += wc[v];
+      tot += wc[v];
+      new_tot += nw[v];
+    }
+    if (in) {
+      const int pos = off + __popcll(m & lt);
+      if (pos < cap) {
+        W[pos] = j;
+        const double bp = bprev ? bprev[j] : 0.0;
+        sigma[pos] = bp != 0.0 ? (bp > 0.0 ? 1.0 : -1.0) : (c[j] >= 0.0 ? 1.0 : -1.0);
+        mark[j] = 1;
+      }
+    }
+    base_off += tot;
+    __syncthreads();
+  }
+  if (t == 0) {
+    cnt[0] = base_off;  // may exceed cap: the caller checks
+    cnt[1] = new_tot;
+  }
+}
+
+// Drops the members whose coefficient disagrees with sigma (b_a sigma_a <=
+// 0): those off the support of beta_prev when there are any such, else the
+// others; compacts W, sigma and b in order and unmarks the dropped columns.
+// cnt[1] = number dropped, cnt[0] = new |W|.  Does nothing (cnt[1] = 0) when
+// the solve failed (cnt[3] != 0).
+__global__ __launch_bounds__(1024) void k_ws_drop(int32_t* __restrict__ W,
+                                                  double* __restrict__ sigma,
+                                                  double* __restrict__ b, int32_t* __restrict__ mark,
+                                                  const double* __restrict__ bprev,
+                                                  int32_t* __restrict__ cnt) {
+  __shared__ int wc[16];
+  __shared__ int nbad;
+  __shared__ int32_t sW[2048];
+  __shared__ double sS[2048], sB[2048];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (cnt[3] != 0) {
+    if (t == 0) cnt[1] = 0;
+    return;
+  }
+  const int m = cnt[0];
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (t == 0) nbad = 0;
+  __syncthreads();
+  for (int a = t; a < m; a += 1024) {
+    sW[a] = W[a];
+    sS[a] = sigma[a];
+    sB[a] = b[a];
+    if (!(sB[a] * sS[a] > 0.0) && !(bprev && bprev[sW[a]] != 0.0)) atomicAdd(&nbad, 1);
+  }
+  __syncthreads();
+  const bool only_new = nbad > 0;
+  int base_off = 0;
+  for (int base = 0; base < m; base += 1024) {
+    const int a = base + t;
+    const bool wrong = a < m && !(sB[a] * sS[a] > 0.0);
+    const bool keep =
+        a < m && !(wrong && (!only_new || !(bprev && bprev[sW[a]] != 0.0)));
+    const uint64_t msk = ballot(keep);
+    if (lane == 0) wc[w] = __popcll(msk);
+    __syncthreads();
+    int off = base_off, tot = 0;
+    for (int v = 0; v < 16; ++v) {
+      if (v < w) off += wc[v];
+      tot += wc[v];
+    }
+    if (keep) {
+      const int pos = off + __popcll(msk & lt);
+      W[pos] = sW[a];
+      sigma[pos] = sS[a];
+      b[pos] = sB[a];
+    } else if (a < m) {
+      mark[sW[a]] = 0;
+    }
+    base_off += tot;
+    __syncthreads();
+  }
+  if (t == 0) {
+    cnt[1] = m - base_off;
+    cnt[0] = base_off;
+  }
+}
+
+// Adds to W the (at most kadd) largest violators |c_k| - lambda > 0 over the
+// positions k < q of act that are not in W (c indexed by position), sigma =
+// sign(c_k), while |W| < cap; cnt[2] = number added.  Candidates pass through
+// LDS (the first kWsCand in order when there are more).
+constexpr int kWsCand = 4096;
+__global__ __launch_bounds__(1024) void k_ws_add(const int32_t* __restrict__ act, int q,
+                                                 const double* __restrict__ c, double lambda,
+                                                 int kadd, int cap, int32_t* __restrict__ W,
+                                                 double* __restrict__ sigma,
+                                                 int32_t* __restrict__ mark,
+                                                 int32_t* __restrict__ cnt) {
+  __shared__ int wc[16];
+  __shared__ double sv[kWsCand];
+  __shared__ int32_t sk[kWsCand];
+  __shared__ double rv[16];
+  __shared__ int ri[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int nc = 0;
+  for (int base = 0; base < q && nc < kWsCand; base += 1024) {
+    const int k = base + t;
+    double v = 0.0;
+    bool f = false;
+    if (k < q) {
+      const int j = act[k];
+      v = fabs(c[k]) - lambda;
+      f = v > 0.0 && mark[j] == 0;
+    }
+    const uint64_t msk = ballot(f);
+    if (lane == 0) wc[w] = __popcll(msk);
+    __syncthreads();
+    int off = nc, tot = 0;
+    for (int u = 0; u < 16; ++u) {
+      if (u < w) off += wc[u];
+      tot += wc[u];
+    }
+    if (f) {
+      const int pos = off + __popcll(msk & lt);
+      if (pos < kWsCand) {
+        sv[pos] = v;
+        sk[pos] = k;
+      }
+    }
+    nc = min(kWsCand, nc + tot);
+    __syncthreads();
+  }
+  int m = cnt[0];
+  const int take = min(min(kadd, nc), max(0, cap - m));
+  for (int r = 0; r < take; ++r) {
+    // block argmax over the candidates (ties: the smaller position)
+    double bv = -1.0;
+    int bi = -1;
+    for (int e = t; e < nc; e += 1024)
+      if (sv[e] > bv) {
+        bv = sv[e];
+        bi = e;
+      }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > bv || (ov == bv && oi >= 0 && (bi < 0 || oi < bi))) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      rv[w] = bv;
+      ri[w] = bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double gv = -1.0;
+      int gi = -1;
+      for (int u = 0; u < 16; ++u)
+        if (ri[u] >= 0 && (rv[u] > gv || (rv[u] == gv && ri[u] < gi))) {
+          gv = rv[u];
+          gi = ri[u];
+        }
+      if (gi >= 0) {
+        const int k = sk[gi];
+        const int j = act[k];
+        W[m] = j;
+        sigma[m] = c[k] >= 0.0 ? 1.0 : -1.0;
+        mark[j] = 1;
+        sv[gi] = -1.0;
+      }
+      ri[0] = gi;
+    }
+    __syncthreads();
+    if (ri[0] < 0) break;
+    ++m;
+    __syncthreads();
+  }
+  if (t == 0) {
+    cnt[2] = m - cnt[0];
+    cnt[0] = m;
+  }
+}
+
+// beta0 = 0 (grid-wide), then beta0[W_a] = b_a by a second launch.
+__global__ void k_ws_zero(int p, double* __restrict__ beta0) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < p; j += gridDim.x * blockDim.x)
+    beta0[j] = 0.0;
+}
+__global__ void k_ws_scatter(const int32_t* __restrict__ W, const double* __restrict__ b,
+                             const int32_t* __restrict__ cnt, double* __restrict__ beta0) {
+  const int m = cnt[0];
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < m; a += gridDim.x * blockDim.x)
+    beta0[W[a]] = b[a];
+}
+
+__global__ void k_ws_info0(int32_t* info) {
+  if (threadIdx.x == 0) *info = 0;
+}
+
+int ws_last(const char* where) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GS_OK : set_hip_error(e, where);
+}
+
+}  // namespace
+
+size_t ws_solve_bytes(int m) {
+  const size_t M = (size_t)((m + TB - 1) / TB) * TB;
+  return (M * M + M) * sizeof(double) + 256;
+}
+
+int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y, const int32_t* W,
+             const double* sigma, int m, double lambda, double* b_out, int32_t* info,
+             void* workspace, hipStream_t s) {
+  const int M = (m + TB - 1) / TB * TB;
+  const int NT = M / TB;
+  double* G = static_cast<double*>(workspace);
+  double* rhs = G + (size_t)M * M;
+  hipLaunchKernelGGL(k_ws_info0, dim3(1), dim3(64), 0, s, info);
+  int rc = ws_last("k_ws_info0");
+  if (rc) return rc;
+  const int ntile = NT * (NT + 1) / 2;
+  const int rgrid = (M + 3) / 4;
+  if (dtype == GS_F32) {
+    hipLaunchKernelGGL(k_ws_gram<float>, dim3(ntile), dim3(256), 0, s,
+                       static_cast<const float*>(X), ldx, n, p, W, m, M, G);
+    rc = ws_last("k_ws_gram");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_ws_rhs<float>, dim3(rgrid), dim3(256), 0, s, static_cast<const float*>(X),
+                       ldx, n, p, static_cast<const float*>(y), W, sigma, m, M, lambda, rhs, info);
+  } else {
+    hipLaunchKernelGGL(k_ws_gram<double>, dim3(ntile), dim3(256), 0, s,
+                       static_cast<const double*>(X), ldx, n, p, W, m, M, G);
+    rc = ws_last("k_ws_gram");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_ws_rhs<double>, dim3(rgrid), dim3(256), 0, s,
+                       static_cast<const double*>(X), ldx, n, p, static_cast<const double*>(y), W,
+                       sigma, m, M, lambda, rhs, info);
+  }
+  rc = ws_last("k_ws_rhs");
+  if (rc) return rc;
+  for (int K = 0; K < NT; ++K) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, G, M, K, info);
+    rc = ws_last("k_chol_diag");
+    if (rc) return rc;
+    const int T = NT - K - 1;
+    if (T == 0) break;
+    hipLaunchKernelGGL(k_chol_panel, dim3(T), dim3(64), 0, s, G, M, K, info);
+    rc = ws_last("k_chol_panel");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, s, G, M, K, info);
+    rc = ws_last("k_chol_update");
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kSolveThreads), 0, s, G, M, rhs, m, b_out, info);
+  return ws_last("k_chol_solve");
+}
+
+int ws_select(const float* out, const int32_t* act, int q, const double* bprev, const double* c,
+              float tau, int cap, int32_t* W, double* sigma, int32_t* mark, int32_t* cnt,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(1024), 0, s, out, act, q, bprev, c, tau, cap, W,
+                     sigma, mark, cnt);
+  return ws_last("k_ws_select");
+}
+
+int ws_drop(int32_t* W, double* sigma, double* b, int32_t* mark, const double* bprev,
+            int32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_drop, dim3(1), dim3(1024), 0, s, W, sigma, b, mark, bprev, cnt);
+  return ws_last("k_ws_drop");
+}
+
+int ws_add(const int32_t* act, int q, const double* c, double lambda, int kadd, int cap,
+           int32_t* W, double* sigma, int32_t* mark, int32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_add, dim3(1), dim3(1024), 0, s, act, q, c, lambda, kadd, cap, W, sigma,
+                     mark, cnt);
+  return ws_last("k_ws_add");
+}
+
+int ws_scatter(const int32_t* W, const double* b, const int32_t* cnt, int p, double* beta0,
+               hipStream_t s) {
+  const int g = std::max(1, std::min(1024, (p + 255) / 256));
+  hipLaunchKernelGGL(k_ws_zero, dim3(g), dim3(256), 0, s, p, beta0);
+  int rc = ws_last("k_ws_zero");
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_ws_scatter, dim3(8), dim3(256), 0, s, W, b, cnt, beta0);
+  return ws_last("k_ws_scatter");
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+size_t gs_restricted_solve_workspace_size(int32_t m) {
+  if (m < 1 || m > kWsMaxSet) return 0;
+  return ws_solve_bytes(m);
+}
+
+int gs_restricted_solve(int32_t n, int32_t p, int64_t ldx, int32_t dtype, const void* X,
+                        const void* y, const int32_t* W, const double* sigma, int32_t m,
+                        double lambda, double* b_out, int32_t* info_out, void* workspace,
+                        size_t ws_bytes, void* stream) {
+  if (n < 1 || p < 1 || ldx < n || !X || !y || !W || !sigma || !b_out || !info_out)
+    return GS_EINVAL;
+  if (dtype != GS_F32 && dtype != GS_F64) return GS_EINVAL;
+  if (m < 1 || m >= n || m > kWsMaxSet || m > p) return GS_EINVAL;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return GS_EINVAL;
+  if (!workspace || ws_bytes < ws_solve_bytes(m)) return GS_EWORKSPACE;
+  return ws_solve(n, p, ldx, dtype, X, y, W, sigma, m, lambda, b_out, info_out, workspace,
+                  static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

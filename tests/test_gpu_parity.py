@@ -85,6 +85,33 @@ def test_screen_c0_f64(torch, orc):
         _screen_case(torch, orc, X, y, beta, ratio * lmax, ld_multiple=2)
 
 
+def test_screen_null_active_takes_all_columns(torch):
+    """Through the C ABI with active_in NULL and q_in 0 (the header's "all p"):
+    the pass covers every column, exactly as with q_in = p."""
+    import ctypes
+    d = synth.c1()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y)
+    n, p = X.shape
+    lam = 0.3 * float(np.abs(_f64(X).T @ _f64(y)).max())
+    beta = torch.zeros(p, dtype=torch.float64, device="cuda")
+    ref = gs.screen(Xd, yd, beta, lam)
+    lib = gs.load_library()
+    ws = torch.empty(lib.screen_workspace_size(n, p), dtype=torch.uint8, device="cuda")
+    act = torch.empty(p, dtype=torch.int32, device="cuda")
+    q = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sc = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(3)]
+    rc = lib.screen(n, p, Xd.stride(1), 0, Xd.data_ptr(), yd.data_ptr(), beta.data_ptr(),
+                    lam, 0, None, 0, act.data_ptr(), q.data_ptr(), sc[0].data_ptr(),
+                    sc[1].data_ptr(), sc[2].data_ptr(), None, ws.data_ptr(), ws.numel(), None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    qr = int(ref["q"].item())
+    assert int(q.item()) == qr > 0
+    assert torch.equal(act[:qr], ref["active"][:qr])
+    assert float(sc[0].item()) == float(ref["gap"].item())
+
+
 def test_screen_c1_f32_with_active_set(torch, orc):
     d = synth.c1()
     X, y = d["X"], d["y"]

@@ -674,3 +674,54 @@ def test_enet_sklearn_cross_check(orc):
     m = sk.ElasticNet(alpha=lam / n, l1_ratio=0.6, fit_intercept=False, tol=1e-14,
                       max_iter=1_000_000).fit(X, y)
     np.testing.assert_allclose(r["beta"][1], m.coef_, rtol=1e-6, atol=1e-8)
+
+
+# ---- restricted solve of the learned start ---------------------------------
+
+def test_restricted_solve_orthonormal_closed_form():
+    """With orthonormal columns the system is diagonal: b_j = x_j^T y -
+    lambda sigma_j (the soft-threshold value on the active side)."""
+    import oracle
+    rng = np.random.default_rng(41)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 12)))
+    y = rng.standard_normal(40)
+    W = np.array([0, 3, 4, 9, 11])
+    sg = np.array([1.0, -1.0, 1.0, 1.0, -1.0])
+    b = oracle.restricted_solve(Q, y, W, sg, 0.3)
+    np.testing.assert_allclose(b, Q[:, W].T @ y - 0.3 * sg, rtol=0, atol=1e-13)
+
+
+def test_restricted_solve_minimizes_smooth_objective():
+    """b minimizes 1/2 ||y - X_W b||^2 + lambda sigma^T b (a smooth convex
+    function), found here by an independent minimizer (BFGS)."""
+    import oracle
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(42)
+    X = rng.standard_normal((30, 20))
+    y = rng.standard_normal(30)
+    W = np.array([1, 2, 5, 7, 8, 13, 19])
+    sg = np.sign(rng.standard_normal(len(W)))
+    lam = 0.7
+    f = lambda b: 0.5 * np.sum((y - X[:, W] @ b) ** 2) + lam * sg @ b
+    g = lambda b: -X[:, W].T @ (y - X[:, W] @ b) + lam * sg
+    ref = minimize(f, np.zeros(len(W)), jac=g, method="BFGS", options={"gtol": 1e-12}).x
+    np.testing.assert_allclose(oracle.restricted_solve(X, y, W, sg, lam), ref, rtol=1e-7, atol=1e-9)
+
+
+def test_restricted_solve_on_the_support_is_the_lasso_solution():
+    """With W the support of a tight Lasso solution and sigma its signs, b is
+    that solution on W (the oracle path's beta, gap <= 1e-13 ||y||^2)."""
+    import oracle
+    orc = oracle.oracle()
+    rng = np.random.default_rng(43)
+    n, p = 60, 150
+    X = rng.standard_normal((n, p))
+    beta = np.zeros(p)
+    beta[rng.choice(p, 8, replace=False)] = rng.standard_normal(8) * 2
+    y = X @ beta + 0.1 * rng.standard_normal(n)
+    lam_max = np.abs(X.T @ y).max()
+    r = orc.lasso_path(X, y, lambdas=[0.05 * lam_max], eps_rel=1e-13)
+    bh = r["beta"][-1]
+    W = np.nonzero(bh)[0]
+    b = oracle.restricted_solve(X, y, W, np.sign(bh[W]), 0.05 * lam_max)
+    np.testing.assert_allclose(b, bh[W], rtol=1e-6, atol=1e-9)

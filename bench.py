@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # counter runs in profiles/k_wide_sweep_c4_hbm_counters.md (scaled by a plain
 # copy of known size), valid while the source text of the kernel and of the
 # device helpers it uses hashes to SWEEP_SRC_SHA1.
+GS_MLP_B3 = 4608  # offset of the network's output bias in the parameter array
 SWEEP_TRAFFIC_BYTES = 406.84e6
 SWEEP_SRC_SHA1 = "bf45d5958163a52b"
 # (file, first marker, end marker): the hashed slices
@@ -294,15 +295,28 @@ def bench_c3(gs, torch, synth, tune, cpu_threads=0, cpu_budget=20.0, max_epochs=
     return out
 
 
-def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
+def _no_entrant_params(torch, P):
+    """The trained parameters with the support logit's bias at -1e6: the
+    network then predicts no entrant, so the learned driver's working set is
+    the previous support grown by the rounds' violators alone (the ablation
+    of the network)."""
+    Q = P.clone()
+    Q[GS_MLP_B3 + 1] = -1e6
+    return Q
+
+
+def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4, ablation=True,
+             plain=True):
     """The C4 workload (1000 x 100000 FP32, blocks of 50 columns with
     correlation 0.7, the grid of 100 lambdas down to lambda_max/1000, every
     lambda to gap <= 1e-8 ||y||^2): the plain path over the first `nl_plain`
-    lambdas (the whole grid by default) and the learned warm start over the
-    first `nl_learned`, compared on those.  Both run in pieces of `piece`
-    lambdas (each warm-started from the previous piece's last solution) so
-    that progress shows; the learned time includes the block correlations,
-    features, inference and the extra gap checks."""
+    lambdas (the whole grid by default), the learned warm start over the
+    first `nl_learned`, and the learned driver with a network that predicts
+    no entrant (the ablation), compared on those.  All run in pieces of
+    `piece` lambdas (each warm-started from the previous piece's last
+    solution) so that progress shows; the learned time includes the block
+    correlations, features, inference, the restricted solves and the extra
+    gap checks."""
     import numpy as np
     Xd = gs.colmajor_to_device(d["X"])
     yd = torch.from_numpy(d["y"]).cuda()
@@ -313,7 +327,7 @@ def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
         P = torch.from_numpy(np.load(params_file).astype(np.float32)).cuda()
     stats = torch.zeros(len(gs.STAT_NAMES), dtype=torch.int64, device="cuda")
 
-    def run(name, learned, nl):
+    def run(name, learned, nl, params=None):
         prev, ws, res, marks = None, None, [], []
         torch.cuda.synchronize()
         stats.zero_()
@@ -322,7 +336,7 @@ def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
         for k in range(0, nl, piece):
             sub = rel[k:min(k + piece, nl)]
             if learned:
-                r = gs.lasso_path_learned(Xd, yd, P, lambdas=sub, relative=True,
+                r = gs.lasso_path_learned(Xd, yd, params, lambdas=sub, relative=True,
                                           beta_init=prev, workspace=ws)
             else:
                 r = gs.lasso_path(Xd, yd, lambdas=sub, relative=True, beta_init=prev,
@@ -355,7 +369,7 @@ def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
                              us_per_visit=round(cd_ms * 1e3 / max(sv["wide_visits"], 1), 4))
         return out
 
-    plain = run("plain", False, nl_plain)
+    plain = run("plain", False, nl_plain) if plain and nl_plain > 0 else None
     res = {"workload": "c4: n=1000 p=100000 FP32, 2000 blocks of 50 columns with "
                        "correlation 0.7, 50-sparse truth, SNR 5, seed %d; lambdas of the "
                        "T=100 grid lambda_max..lambda_max/1000, eps=1e-8||y||^2; plain path "
@@ -364,16 +378,46 @@ def bench_c4(gs, torch, d, params_file, piece, nl_plain, nl_learned, seed=4):
            "piece": piece, "plain_lambdas": nl_plain, "learned_lambdas": nl_learned,
            "plain": plain}
     if P is not None and nl_learned > 0:
-        lr = run("learned", True, nl_learned)
+        lr = run("learned", True, nl_learned, P)
         res["learned"] = lr
         res["params"] = os.path.relpath(params_file, ROOT)
+        if ablation:
+            res["no_entrant_network"] = run("no-entrant network", True, nl_learned,
+                                            _no_entrant_params(torch, P))
         # the plain path's time and epochs over the same lambdas
         npc = (nl_learned + piece - 1) // piece
-        if nl_learned % piece == 0 and npc <= len(plain["seconds_at_piece_end"]):
+        if plain is not None and nl_learned % piece == 0 and \
+                npc <= len(plain["seconds_at_piece_end"]):
+            ps = plain["seconds_at_piece_end"][npc - 1]
             res["plain_same_lambdas"] = dict(
-                seconds=plain["seconds_at_piece_end"][npc - 1],
-                epochs=int(sum(plain["epochs_per_lambda"][:nl_learned])))
+                seconds=ps, epochs=int(sum(plain["epochs_per_lambda"][:nl_learned])))
+            res["speedup_learned_vs_plain"] = round(ps / max(lr["seconds"], 1e-9), 2)
     return res
+
+
+def bench_learned_eval(gs, torch, synth, params_file, seeds, nl_plain, piece=10):
+    """Held-out evaluation of the learned start at the full C4 size: for each
+    seed, the learned path over the whole 100-lambda grid and the plain path
+    over its first `nl_plain` lambdas, every lambda certified; reported per
+    seed with the learned time at `nl_plain` lambdas beside the plain one."""
+    rows = []
+    for sd in seeds:
+        d = synth.c4(seed=sd)
+        _log(f"learned eval: seed {sd}")
+        r = bench_c4(gs, torch, d, params_file, piece, nl_plain, 100, seed=sd, ablation=False)
+        lr, pl = r["learned"], r["plain"]
+        k = nl_plain // piece
+        rows.append(dict(seed=sd, learned_seconds=lr["seconds"], learned_epochs=lr["epochs"],
+                         learned_certified=lr["certified"],
+                         network_start_lambdas=lr["network_start_lambdas"],
+                         learned_seconds_first=lr["seconds_at_piece_end"][k - 1],
+                         learned_epochs_first=int(sum(lr["epochs_per_lambda"][:nl_plain])),
+                         plain_seconds_first=pl["seconds"], plain_epochs_first=pl["epochs"],
+                         plain_certified=pl["certified"]))
+        del d
+    return dict(workload="c4 1000x100000 FP32 held-out seeds; learned: all 100 lambdas; "
+                         "plain and learned compared on the first %d" % nl_plain,
+                seeds=list(seeds), rows=rows)
 
 
 def bench_screening(gs, torch, synth, Ks=(10, 50, 200)):
@@ -455,7 +499,7 @@ def main():
     ap.add_argument("--c4-piece", type=int, default=10)
     ap.add_argument("--c4-lambdas", type=int, default=100,
                     help="lambdas of the 100-point c4 grid solved by the plain path")
-    ap.add_argument("--c4-learned-lambdas", type=int, default=70,
+    ap.add_argument("--c4-learned-lambdas", type=int, default=100,
                     help="lambdas solved by the learned warm start (0: none)")
     ap.add_argument("--no-screening", action="store_true",
                     help="skip the screening-proportion comparison of the safe rules")
@@ -463,6 +507,10 @@ def main():
                     help="seconds of the c3 CPU pool sample")
     ap.add_argument("--copy-mb", type=float, default=0.0,
                     help="only run a plain device copy of this many MB (counter calibration)")
+    ap.add_argument("--learned-eval", default="",
+                    help="only evaluate the learned start on these c4 seeds (e.g. 4,20000-20009)")
+    ap.add_argument("--eval-plain-lambdas", type=int, default=70,
+                    help="lambdas of the plain path in the learned evaluation")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the library solves "
@@ -481,6 +529,14 @@ def main():
         copy_calibration(torch, a.copy_mb, 5)
         return
     gs.load_library()
+    if a.learned_eval:
+        seeds = []
+        for part in a.learned_eval.split(","):
+            lo, _, hi = part.partition("-")
+            seeds += list(range(int(lo), int(hi or lo) + 1))
+        ev = bench_learned_eval(gs, torch, synth, a.c4_params, seeds, a.eval_plain_lambdas)
+        print(json.dumps({"learned_eval": ev}), flush=True)
+        return
     gs.timing_enable(True)
     path = None
     if not a.no_path:

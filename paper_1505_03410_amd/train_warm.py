@@ -131,6 +131,23 @@ def train(gs, torch, U, Tg, Uv, Tv, steps, batch, lr, seed=0):
     return flat, hist
 
 
+def entrant_scores(gs, torch, flat, Uv, Tv):
+    """Validation scores of the support logit on the entrants (features with
+    beta_prev = 0, the third input): precision and recall of logit > 0
+    against the support at lambda_t, and the BCE-plus-MSE validation loss."""
+    out = torch.cat([gs.mlp_forward(flat, Uv[i:i + (1 << 22)].contiguous())
+                     for i in range(0, Uv.shape[0], 1 << 22)])
+    fresh = Uv[:, 2] == 0
+    pred = (out[:, 1] > 0) & fresh
+    tgt = (Tv[:, 1] > 0.5) & fresh
+    tp = float((pred & tgt).sum())
+    _, vl = gs.mlp_grad(flat, Uv, Tv)
+    return dict(validation_loss=float(vl.item()),
+                entrant_precision=tp / max(float(pred.sum()), 1.0),
+                entrant_recall=tp / max(float(tgt.sum()), 1.0),
+                entrants=int(tgt.sum()), candidates=int(fresh.sum()))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--problems", type=int, default=64)
@@ -144,6 +161,11 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--first-seed", type=int, default=10000)
     ap.add_argument("--out", default=os.path.join(HERE, "warm_mlp.npy"))
+    ap.add_argument("--curve", default="",
+                    help="comma-separated training-set sizes: one network per size (the first "
+                         "k training problems), scored on the same held-out problems; writes "
+                         "the table to --curve-out instead of training --out")
+    ap.add_argument("--curve-out", default="warm_mlp_curve.json")
     a = ap.parse_args(argv)
     if not 1 <= a.holdout < a.problems:
         raise SystemExit("--holdout must be between 1 and --problems - 1")
@@ -167,6 +189,27 @@ def main(argv=None):
     Tv = torch.cat([t for _, t in per[ntrain:]])
     _log(f"{Utr.shape[0]} training and {Uv.shape[0]} validation examples; "
          f"support fraction {float(Ttr[:, 1].mean()):.3f}")
+    if a.curve:
+        rows = []
+        for k in [int(v) for v in a.curve.split(",")]:
+            if not 1 <= k <= ntrain:
+                raise SystemExit(f"curve size {k} outside 1..{ntrain}")
+            Uk = torch.cat([u for u, _ in per[:k]])
+            Tk = torch.cat([t for _, t in per[:k]])
+            _log(f"curve: {k} training problems, {Uk.shape[0]} examples")
+            flat, hist = train(gs, torch, Uk, Tk, Uv, Tv, a.steps, a.batch, a.lr)
+            row = dict(problems=k, examples=int(Uk.shape[0]), train_loss=hist[-1][1])
+            row.update(entrant_scores(gs, torch, flat, Uv, Tv))
+            _log(f"curve: {row}")
+            rows.append(row)
+            del Uk, Tk
+        meta = dict(holdout=a.holdout, p=a.p, n=1000, lambdas=a.lambdas, steps=a.steps,
+                    batch=a.batch, lr=a.lr, first_seed=a.first_seed,
+                    validation_examples=int(Uv.shape[0]), rows=rows)
+        with open(a.curve_out, "w") as f:
+            json.dump(meta, f, indent=1)
+        _log(f"wrote {a.curve_out}")
+        return
     t0 = time.time()
     flat, hist = train(gs, torch, Utr, Ttr, Uv, Tv, a.steps, a.batch, a.lr)
     torch.cuda.synchronize()

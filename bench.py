@@ -95,6 +95,35 @@ def bench_path(gs, torch, synth, steps, warmup):
                 path_launches=path_n, n=X.shape[0], p=X.shape[1], stats=st)
 
 
+def bench_path_learned(gs, torch, synth, params_file, steps):
+    """The same c1 path (T = 100, every lambda to gap <= 1e-8 ||y||^2) through
+    the learned driver: with the trained network, with the no-entrant network
+    (the ablation) and with no network (plain starts, one lambda at a time)."""
+    import numpy as np
+    d = synth.c1()
+    Xd = gs.colmajor_to_device(d["X"])
+    yd = torch.from_numpy(d["y"]).cuda()
+    yy = float((d["y"].astype(np.float64) ** 2).sum())
+    P = torch.from_numpy(np.load(params_file).astype(np.float32)).cuda()
+    out = {}
+    for name, prm in (("learned", P), ("no_entrant_network", _no_entrant_params(torch, P)),
+                      ("plain_starts", None)):
+        ws = None
+        r = gs.lasso_path_learned(Xd, yd, prm, T=100, lambda_min_ratio=1e-3)
+        ws = r["workspace"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = gs.lasso_path_learned(Xd, yd, prm, T=100, lambda_min_ratio=1e-3, workspace=ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        st, gap = r["status"].cpu().numpy(), r["gap"].cpu().numpy()
+        out[name] = dict(seconds=round(el, 4), epochs=int(r["epochs"].sum()),
+                         certified=bool((st == 0).all() and (gap <= 1e-8 * yy).all()),
+                         network_start_lambdas=int(r["learned"].sum()))
+    return out
+
+
 def bench_sweep(gs, torch, d, reps):
     import numpy as np
     X, y = d["X"], d["y"]
@@ -543,6 +572,9 @@ def main():
         _log("path: c1 72x7129, 100 lambdas")
         path = bench_path(gs, torch, synth, a.steps, a.warmup)
         _log(f"path: {path['seconds']:.4f} s/path, ok={path['ok']}")
+        if a.c4_params and os.path.exists(a.c4_params):
+            path["learned_driver"] = bench_path_learned(gs, torch, synth, a.c4_params, a.steps)
+            _log(f"path, learned start: {path['learned_driver']['learned']['seconds']:.4f} s/path")
     roof = None
     sweep = None
     d4 = None
@@ -619,7 +651,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": {"c2": c2, "c3": c3},
-        "learned_warm_start": c4,
+        "learned_warm_start": {"c1": path.get("learned_driver"), "c4": c4},
         "screening_proportion": scr,
     }
     print(json.dumps(line), flush=True)

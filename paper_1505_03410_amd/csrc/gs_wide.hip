@@ -41,7 +41,7 @@ __device__ __forceinline__ bool keep_vals(const ProbDesc& d, const WideState* st
 
 // Keep bits of the PER consecutive positions k0.. of A (positions >= q are
 // not kept) and their columns js.  Positions are clamped to q-1 so that
-// every load is issued, without branches, before the first test.
+// every load is issued, without branches, before the first test; q >= 1.
 template <int PER>
 __device__ __forceinline__ unsigned keep_bits(const ProbDesc& d, const WideState* st,
                                               const GapInfo& g, const int32_t* act, bool full,
@@ -77,6 +77,10 @@ __global__ __launch_bounds__(256) void k_wide_test(ProbDesc d, WideState* st, Wi
   __shared__ double sh[256];
   if (st->done || st->phase != 1) return;
   const int q = st->q;
+  if (q <= 0) {  // an empty A: no entry of act is valid
+    if (threadIdx.x == 0) wb.cnt[blockIdx.x] = 0;
+    return;
+  }
   const bool full = st->full != 0;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   const GapInfo g = state_gap(d, st);
@@ -106,6 +110,7 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
   __shared__ int scan[256];
   if (st->done || st->phase != 1) return;
   const int q = st->q;
+  if (q <= 0) return;  // an empty A: nothing kept, no entry of act is valid
   const bool full = st->full != 0;
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   int32_t* dst = out ? out : d.act + (int64_t)(st->cur ^ 1) * d.p;
@@ -133,7 +138,8 @@ __global__ __launch_bounds__(256) void k_wide_compact(ProbDesc d, WideState* st,
 
 // List bits of the PER consecutive positions k0.. (positions >= q are not
 // listed), their columns js, c_k, beta_j and ||x_j||^2; positions are clamped
-// to q-1 so that every load is issued, without branches, before the first test.
+// to q-1 so that every load is issued, without branches, before the first
+// test; q >= 1.
 template <int PER>
 __device__ __forceinline__ unsigned listed_bits(const ProbDesc& d, const WideState* st,
                                                 const int32_t* act, int q, int k0,
@@ -165,6 +171,10 @@ __global__ __launch_bounds__(256) void k_wide_lcount(ProbDesc d, WideState* st, 
   __shared__ double sh[256];
   if (st->done || st->phase != 2) return;
   const int q = st->q;
+  if (q <= 0) {  // an empty A: no entry of act is valid
+    if (threadIdx.x == 0) wb.cnt[blockIdx.x] = 0;
+    return;
+  }
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   const int k0 = st->resume + blockIdx.x * kTestTile + threadIdx.x * PER;
   int js[PER];
@@ -179,6 +189,7 @@ __global__ __launch_bounds__(256) void k_wide_lcompact(ProbDesc d, WideState* st
   __shared__ int scan[256];
   if (st->done || st->phase != 2) return;
   const int q = st->q;
+  if (q <= 0) return;  // an empty A lists nothing
   const int32_t* act = d.act + (int64_t)st->cur * d.p;
   int off = 0;
   for (int b = 0; b < (int)blockIdx.x; ++b) off += wb.cnt[b];

@@ -135,45 +135,50 @@ __global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_
   if (lane == 0) b[a] = s - lambda * sigma[a];
 }
 
-// ---- factorization of the diagonal tile K in LDS (unblocked, right-looking);
-// writes L_KK to the lower triangle and its transpose to the upper one.  A
-// pivot that is not positive (or not finite) stops the factorization with
-// info = its 1-based row.
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M, int K,
-                                                   int32_t* info) {
+// ---- factorization of the diagonal tile K (unblocked, right-looking) by one
+// wavefront: lane i owns row i of the tile in LDS and updates it in chunks of
+// eight entries (all loads of a chunk issued together); column c of L goes to
+// every lane through LDS.  Writes L_KK to the lower triangle and its
+// transpose to the upper one.  A pivot that is not positive (or not finite)
+// stops the factorization with info = its 1-based row.
+__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ G, int M, int K,
+                                                  int32_t* info) {
   __shared__ double T[TB][TB + 1];
+  __shared__ double col[TB];
   if (ws_failed(info)) return;
-  const int t = threadIdx.x;
+  const int i = threadIdx.x;
   const int64_t o = (int64_t)K * TB;
-  for (int e = t; e < TB * TB; e += 256) {
-    const int i = e % TB, j = e / TB;
-    T[i][j] = G[(o + j) * M + o + i];
-  }
+  for (int j = 0; j < TB; ++j) T[i][j] = G[(o + j) * M + o + i];
   __syncthreads();
   for (int c = 0; c < TB; ++c) {
     const double piv = T[c][c];
-    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread read the same value
-      if (t == 0) *info = (int32_t)(o + c + 1);
+    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every lane read the same value
+      if (i == 0) *info = (int32_t)(o + c + 1);
       return;
     }
     const double dg = sqrt(piv);
-    __syncthreads();  // every thread has read the pivot
-    if (t > c && t < TB) T[t][c] /= dg;
-    if (t == 0) T[c][c] = dg;
-    __syncthreads();
-    const int w = TB - 1 - c;  // trailing block (c+1 .. 63)^2, lower part
-    for (int e = t; e < w * w; e += 256) {
-      const int i = c + 1 + e % w, j = c + 1 + e / w;
-      if (i >= j) T[i][j] = fma(-T[i][c], T[j][c], T[i][j]);
+    const double lic = i > c ? T[i][c] / dg : (i == c ? dg : 0.0);
+    col[i] = lic;
+    __syncthreads();  // column c is in col (and every lane read the pivot)
+    T[i][c] = lic;
+    for (int j0 = (c + 1) & ~7; j0 < TB; j0 += 8) {
+      double a[8], w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = T[i][j0 + u];
+        w[u] = col[j0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u > c) a[u] = fma(-lic, w[u], a[u]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) T[i][j0 + u] = a[u];
     }
     __syncthreads();
   }
-  for (int e = t; e < TB * TB; e += 256) {
-    const int i = e % TB, j = e / TB;
-    if (i >= j) {
-      G[(o + j) * M + o + i] = T[i][j];
-      G[(o + i) * M + o + j] = T[i][j];
-    }
+  for (int j = 0; j <= i; ++j) {
+    G[(o + j) * M + o + i] = T[i][j];
+    G[(o + i) * M + o + j] = T[i][j];
   }
 }
 
@@ -190,16 +195,19 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int M
     const int i = e % TB, j = e / TB;
     L[i][j] = G[(o + j) * M + o + i];
   }
+  __shared__ double rd[TB];  // 1 / L_cc
+  rd[r] = 1.0 / G[(o + r) * M + o + r];
   __syncthreads();
   double x[TB];
 #pragma unroll
   for (int c = 0; c < TB; ++c) x[c] = G[(o + c) * M + oi + r];
 #pragma unroll
   for (int c = 0; c < TB; ++c) {
-    double v = x[c];
+    // four partial sums shorten the dependent chain
+    double v[4] = {x[c], 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < c; ++k) v = fma(-x[k], L[c][k], v);
-    x[c] = v / L[c][c];
+    for (int k = 0; k < c; ++k) v[k & 3] = fma(-x[k], L[c][k], v[k & 3]);
+    x[c] = ((v[0] + v[1]) + (v[2] + v[3])) * rd[c];
   }
 #pragma unroll
   for (int c = 0; c < TB; ++c) {
@@ -258,81 +266,78 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
 }
 
 // ---- L z = b, then L^T x = z, one block; x_out gets the first m entries.
-// Each thread owns rows t, t + 1024 and loads its entries of the next column
-// while the current one is applied.
+// Blocked by tiles of 64: the diagonal tile's 64 steps run on wavefront 0
+// (lane i owns entry i of the tile, the tile of L in LDS), then every thread
+// applies the tile's columns to the entries below (forward) or above
+// (backward) it.  L_ic for i > c is column c of the lower triangle, and L_cj
+// for j < c column c of the mirrored upper triangle, so both sweeps read
+// columns.
 constexpr int kSolveThreads = 1024;
-constexpr int kSolveRows = 2048 / kSolveThreads;
 __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __restrict__ G, int M,
                                                               const double* __restrict__ b,
                                                               int m, double* __restrict__ x_out,
                                                               int32_t* info) {
   __shared__ double z[2048];
+  __shared__ double L[TB][TB + 1];
   if (ws_failed(info)) return;
   const int t = threadIdx.x;
+  const int NT = M / TB;
   for (int i = t; i < M; i += kSolveThreads) z[i] = b[i];
+  // forward: tiles top to bottom
+  for (int K = 0; K < NT; ++K) {
+    const int64_t o = (int64_t)K * TB;
+    __syncthreads();  // z and the previous tile's use of L are complete
+    for (int e = t; e < TB * TB; e += kSolveThreads) {
+      const int i = e % TB, j = e / TB;
+      L[i][j] = G[(o + j) * M + o + i];
+    }
+    __syncthreads();
+    if (t < TB) {
+      double zi = z[o + t];
+      for (int c = 0; c < TB; ++c) {
+        const double zc = __shfl(zi, c, 64) / L[c][c];
+        if (t == c) zi = zc;
+        else if (t > c) zi = fma(-L[t][c], zc, zi);
+      }
+      z[o + t] = zi;
+    }
+    __syncthreads();
+    // rows below the tile: z_i -= sum_c L_{i, o+c} z_{o+c}
+    for (int i = (int)o + TB + t; i < M; i += kSolveThreads) {
+      double acc = z[i];
+#pragma unroll 8
+      for (int c = 0; c < TB; ++c) acc = fma(-G[(o + c) * M + i], z[o + c], acc);
+      z[i] = acc;
+    }
+  }
+  // backward: tiles bottom to top, L^T
+  for (int K = NT - 1; K >= 0; --K) {
+    const int64_t o = (int64_t)K * TB;
+    __syncthreads();
+    for (int e = t; e < TB * TB; e += kSolveThreads) {
+      const int i = e % TB, j = e / TB;
+      L[i][j] = G[(o + j) * M + o + i];
+    }
+    __syncthreads();
+    if (t < TB) {
+      double zi = z[o + t];
+      for (int c = TB - 1; c >= 0; --c) {
+        const double xc = __shfl(zi, c, 64) / L[c][c];
+        if (t == c) zi = xc;
+        else if (t < c) zi = fma(-L[c][t], xc, zi);
+      }
+      z[o + t] = zi;
+    }
+    __syncthreads();
+    // rows above the tile: z_j -= sum_c L_{o+c, j} x_{o+c} (upper triangle)
+    for (int j = t; j < (int)o; j += kSolveThreads) {
+      double acc = z[j];
+#pragma unroll 8
+      for (int c = 0; c < TB; ++c) acc = fma(-G[(o + c) * M + j], z[o + c], acc);
+      z[j] = acc;
+    }
+  }
   __syncthreads();
-  // forward: z_c /= L_cc, then z_i -= L_ic z_c below c (column c of L)
-  double nx[kSolveRows];
-#pragma unroll
-  for (int u = 0; u < kSolveRows; ++u) {
-    const int i = t + u * kSolveThreads;
-    nx[u] = i < M ? G[i] : 0.0;  // column 0
-  }
-  double dn = G[0];  // diagonal entry of the next column
-  for (int c = 0; c < M; ++c) {
-    double cur[kSolveRows];
-#pragma unroll
-    for (int u = 0; u < kSolveRows; ++u) cur[u] = nx[u];
-    const double dc = dn;
-    if (c + 1 < M) {
-#pragma unroll
-      for (int u = 0; u < kSolveRows; ++u) {
-        const int i = t + u * kSolveThreads;
-        nx[u] = i < M ? G[(int64_t)(c + 1) * M + i] : 0.0;
-      }
-      dn = G[(int64_t)(c + 1) * M + c + 1];
-    }
-    const double zc = z[c] / dc;
-    __syncthreads();  // every thread has read z[c]
-#pragma unroll
-    for (int u = 0; u < kSolveRows; ++u) {
-      const int i = t + u * kSolveThreads;
-      if (i > c && i < M) z[i] = fma(-cur[u], zc, z[i]);
-      if (i == c) z[i] = zc;
-    }
-    __syncthreads();
-  }
-  // backward: x_c = z_c / L_cc, then z_j -= L_cj x_c above c (row c of L =
-  // column c of the mirrored upper triangle)
-#pragma unroll
-  for (int u = 0; u < kSolveRows; ++u) {
-    const int i = t + u * kSolveThreads;
-    nx[u] = i < M ? G[(int64_t)(M - 1) * M + i] : 0.0;
-  }
-  dn = G[(int64_t)(M - 1) * M + M - 1];
-  for (int c = M - 1; c >= 0; --c) {
-    double cur[kSolveRows];
-#pragma unroll
-    for (int u = 0; u < kSolveRows; ++u) cur[u] = nx[u];
-    const double dc = dn;
-    if (c > 0) {
-#pragma unroll
-      for (int u = 0; u < kSolveRows; ++u) {
-        const int i = t + u * kSolveThreads;
-        nx[u] = i < M ? G[(int64_t)(c - 1) * M + i] : 0.0;
-      }
-      dn = G[(int64_t)(c - 1) * M + c - 1];
-    }
-    const double xc = z[c] / dc;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kSolveRows; ++u) {
-      const int i = t + u * kSolveThreads;
-      if (i < c) z[i] = fma(-cur[u], xc, z[i]);
-      if (i == c) z[i] = xc;
-    }
-    __syncthreads();
-  }
   for (int i = t; i < m; i += kSolveThreads) x_out[i] = z[i];
 }
 
@@ -615,7 +620,7 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   rc = ws_last("k_ws_rhs");
   if (rc) return rc;
   for (int K = 0; K < NT; ++K) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, G, M, K, info);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, G, M, K, info);
     rc = ws_last("k_chol_diag");
     if (rc) return rc;
     const int T = NT - K - 1;

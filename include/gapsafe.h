@@ -289,6 +289,26 @@ void lasso_batch_plan_free(gs_batch_plan* plan);
 int gs_autotune(const gs_problem* probs, int32_t B, const gs_opts* opts,
                 void* workspace, size_t ws_bytes, void* stream,
                 int32_t max_lambdas, int32_t sample, int32_t* choice_out);
+
+/* Schedule autotuner of lasso_path's "auto" schedule (GS_SCHED_AUTO), which
+ * runs a problem on the wide schedule when n*p exceeds a per-dtype threshold
+ * (16 Mi by default) and on the narrow one otherwise.  This call times both
+ * schedules on prob's first min(T, max_lambdas) lambdas (after one untimed
+ * run of each) with opts, records the size n*p and which was faster, and
+ * moves the dtype's threshold to the cut between all sizes measured so far
+ * in this process that misclassifies the fewest of them (the geometric
+ * midpoint of the two sizes around it).  prob's outputs are overwritten with
+ * those partial runs; the workspace is lasso_path's.  choice_out (optional,
+ * host): 1 if the wide schedule was faster, else 0.  GS_EUNSUPPORTED for a
+ * problem only one schedule runs (a row subsample, a CSC design, a
+ * comparison rule, the elastic net).  Synchronizes `stream`.
+ * gs_wide_threshold returns the dtype's current threshold (-1 for a bad
+ * dtype).  gs_tune_save / gs_tune_load also write and read the thresholds;
+ * gs_tune_reset restores the default. */
+int gs_autotune_schedule(const gs_problem* prob, const gs_opts* opts, void* workspace,
+                         size_t ws_bytes, void* stream, int32_t max_lambdas,
+                         int32_t* choice_out);
+double gs_wide_threshold(int32_t dtype);
 int gs_tune_save(const char* path);
 int gs_tune_load(const char* path);
 void gs_tune_reset(void);

@@ -77,7 +77,8 @@ EXPORTS = ["gs_opts_default", "gs_wallclock_hz", "lasso_workspace_size", "lasso_
            "gs_block_corr", "gs_mlp_forward", "gs_mlp_train_workspace_size", "gs_mlp_grad",
            "gs_mlp_adam", "gs_mlp_train_step", "gs_warm_features",
            "lasso_path_learned_workspace_size", "lasso_path_learned",
-           "gs_restricted_solve_workspace_size", "gs_restricted_solve"]
+           "gs_restricted_solve_workspace_size", "gs_restricted_solve",
+           "gs_autotune_schedule", "gs_wide_threshold"]
 
 MLP_PARAMS = 4610
 # offsets of the parameter array (include/gapsafe.h): name -> (offset, shape)
@@ -159,6 +160,10 @@ def load_library(path: str = LIB_PATH):
     lib.gs_warm_features.restype = ctypes.c_int
     lib.lasso_path_learned_workspace_size.argtypes = [P(gs_problem)]
     lib.lasso_path_learned_workspace_size.restype = sz
+    lib.gs_autotune_schedule.argtypes = [P(gs_problem), P(gs_opts), vp, sz, vp, i32, P(i32)]
+    lib.gs_autotune_schedule.restype = ctypes.c_int
+    lib.gs_wide_threshold.argtypes = [i32]
+    lib.gs_wide_threshold.restype = f64
     lib.gs_restricted_solve_workspace_size.argtypes = [i32]
     lib.gs_restricted_solve_workspace_size.restype = sz
     lib.gs_restricted_solve.argtypes = [i32, i32, ctypes.c_int64, i32, vp, vp, vp, vp, i32, f64,
@@ -204,6 +209,18 @@ def _stream_ptr(stream):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _active_ptr(active):
+    """The active list's pointer: NULL means all p columns in the C ABI, so an
+    empty list (whose tensor may have no storage) passes a non-null pointer
+    with q_in = 0."""
+    if active is None:
+        return None, None
+    if active.numel() == 0:
+        keep = _torch().zeros(1, dtype=_torch().int32, device=active.device)
+        return _ptr(keep), keep
+    return _ptr(active), active
 
 
 def colmajor_to_device(X, ld_multiple: int = 4, dtype=None, device="cuda"):
@@ -468,6 +485,33 @@ def autotune(problems, *, max_lambdas: int = 5, sample: int = 4, eps_rel: float 
     return [(ch[2 * b], ch[2 * b + 1]) for b in range(B)]
 
 
+def autotune_schedule(X, y, *, T: int = 100, lambdas: Optional[Sequence[float]] = None,
+                      relative: bool = False, lambda_min_ratio: float = 1e-3,
+                      max_lambdas: int = 5, eps_rel: float = 1e-8, screen_every: int = 10,
+                      max_epochs: int = 100000, cd_mode="auto", stream=None):
+    """Times the narrow and the wide schedule on this problem's first
+    ``max_lambdas`` lambdas and moves the dtype's auto-schedule threshold
+    accordingly (gs_autotune_schedule); returns "wide" or "narrow", the faster."""
+    lib = load_library()
+    pr, _out, _keep = _problem(X, y, T=T, lambdas=lambdas, relative=relative,
+                               lambda_min_ratio=lambda_min_ratio, beta_init=None, rows=None,
+                               out=None)
+    o = _opts(eps_rel, screen_every, max_epochs, "auto", cd_mode=cd_mode)
+    need = lib.lasso_workspace_size(ctypes.byref(pr), 1, ctypes.byref(o))
+    ws = _workspace(need, X.device)
+    ch = ctypes.c_int32(-1)
+    _check(lib.gs_autotune_schedule(ctypes.byref(pr), ctypes.byref(o), _ptr(ws), ws.numel(),
+                                    _stream_ptr(stream), int(max_lambdas), ctypes.byref(ch)),
+           allow_not_converged=False)
+    return "wide" if ch.value == 1 else "narrow"
+
+
+def wide_threshold(dtype="f32") -> float:
+    """The n*p above which the auto schedule is wide, for FP32 ("f32") or
+    FP64 ("f64") designs."""
+    return float(load_library().gs_wide_threshold(0 if dtype == "f32" else 1))
+
+
 def tune_save(path: str):
     _check(load_library().gs_tune_save(path.encode()), allow_not_converged=False)
 
@@ -504,8 +548,9 @@ def screen(X, y, beta, lam: float, active=None, *, want_c: bool = True, stream=N
     c = torch.empty(max(q, 1), dtype=torch.float64, device=dev) if want_c else None
     need = lib.screen_workspace_size(n, p)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    a_ptr, _a_keep = _active_ptr(active)
     rc = lib.screen(n, p, ld, _dtype_code(X), _ptr(X), _ptr(y), _ptr(beta), float(lam),
-                    RULES[rule], _ptr(active), q, _ptr(act_out), _ptr(q_out), _ptr(gap), _ptr(alpha),
+                    RULES[rule], a_ptr, q, _ptr(act_out), _ptr(q_out), _ptr(gap), _ptr(alpha),
                     _ptr(radius), _ptr(c), _ptr(ws), ws.numel(), _stream_ptr(stream))
     _check(rc, allow_not_converged=False)
     return dict(active=act_out, q=q_out, gap=gap, alpha=alpha, radius=radius,
@@ -539,8 +584,9 @@ def screen_noalloc(X, y, beta, lam: float, active=None, *, want_c: bool = True, 
                    c=torch.empty(max(q, 1), dtype=torch.float64, device=dev) if want_c else None)
     elif out["active"].numel() < q or (out.get("c") is not None and out["c"].numel() < q):
         raise ValueError("preallocated outputs are smaller than the active set")
+    a_ptr, _a_keep = _active_ptr(active)
     rc = lib.screen_noalloc(n, p, ld, _dtype_code(X), _ptr(X), _ptr(y), _ptr(beta), float(lam),
-                            RULES[rule], _ptr(active), q, _ptr(out["active"]), _ptr(out["q"]),
+                            RULES[rule], a_ptr, q, _ptr(out["active"]), _ptr(out["q"]),
                             _ptr(out["gap"]), _ptr(out["alpha"]), _ptr(out["radius"]),
                             _ptr(out.get("c")), _stream_ptr(stream))
     _check(rc, allow_not_converged=False)

@@ -132,6 +132,47 @@ const NarrowEntry* narrow_table(int dtype, bool gather, bool vec, int* count) {
 // also holds n.  Keys: (table base pointer, smallest index).
 std::mutex g_tune_mu;
 std::map<std::pair<const NarrowEntry*, int>, int> g_tuned;
+// Schedule autotuner: per dtype, the n*p above which lasso_path's "auto"
+// schedule is wide, and the measured points (n*p, wide faster) it was set from.
+double g_wide_thr[2] = {kWideThreshold, kWideThreshold};
+std::vector<std::pair<double, bool>> g_sched_pts[2];
+
+double wide_threshold(int dtype) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_wide_thr[dtype == GS_F64 ? 1 : 0];
+}
+
+// The problem cut to the first k lambdas of its grid: an explicit list keeps
+// its first k entries; a generated grid lambda_max * ratio^(t/(T-1)) keeps
+// its first k points through the ratio ratio^((k-1)/(T-1)).
+void first_lambdas(gs_problem* q, int k) {
+  if (k >= q->T) return;
+  if (!q->lambdas && q->T > 1)
+    q->lambda_min_ratio = k > 1 ? std::pow(q->lambda_min_ratio, (double)(k - 1) / (q->T - 1)) : 1.0;
+  q->T = k;
+}
+
+// The cut between the measured sizes that misclassifies the fewest points
+// (the geometric midpoint of the two sizes around it); the default when
+// there are no points.
+double fit_threshold(std::vector<std::pair<double, bool>> pts) {
+  if (pts.empty()) return kWideThreshold;
+  std::sort(pts.begin(), pts.end());
+  const int m = (int)pts.size();
+  int best_err = m + 1;
+  double best = kWideThreshold;
+  for (int k = 0; k <= m; ++k) {  // narrow for the first k points, wide for the rest
+    int err = 0;
+    for (int i = 0; i < m; ++i) err += (i < k) == pts[i].second ? 1 : 0;
+    if (err < best_err) {
+      best_err = err;
+      if (k == 0) best = pts[0].first * 0.5;
+      else if (k == m) best = pts[m - 1].first * 2.0;
+      else best = std::sqrt(pts[k - 1].first * pts[k].first);
+    }
+  }
+  return best;
+}
 // set while the autotuner times one candidate (this thread only)
 thread_local const NarrowEntry* g_force = nullptr;
 
@@ -172,7 +213,7 @@ bool use_wide(const gs_problem* pr, const gs_opts* o) {
   if (o->rule >= GS_RULE_STATIC) return true;  // comparison rules: wide schedule only
   if (o->enet_alpha != 0.0 && o->enet_alpha < 1.0) return true;  // elastic net: likewise
   if (o->schedule == GS_SCHED_NARROW) return false;
-  return (double)pr->n * (double)pr->p > kWideThreshold;
+  return (double)pr->n * (double)pr->p > wide_threshold(pr->dtype);
 }
 
 // Per-problem workspace arrays.
@@ -1146,7 +1187,7 @@ int gs_autotune(const gs_problem* probs, int32_t B, const gs_opts* opts, void* w
     std::vector<gs_problem> sp;
     for (int b : mem) {
       gs_problem q = probs[b];
-      q.T = std::min(q.T, max_lambdas);
+      first_lambdas(&q, max_lambdas);
       sp.push_back(q);
     }
     // candidates: the smallest entry of each lane split S that holds the class
@@ -1198,9 +1239,69 @@ int gs_autotune(const gs_problem* probs, int32_t B, const gs_opts* opts, void* w
   return rc;
 }
 
+int gs_autotune_schedule(const gs_problem* prob, const gs_opts* opts, void* workspace,
+                         size_t ws_bytes, void* stream, int32_t max_lambdas,
+                         int32_t* choice_out) {
+  gs_opts def;
+  gs_opts_default(&def);
+  if (!opts) opts = &def;
+  if (!prob || max_lambdas < 1) return GS_EINVAL;
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  rc = check_problem(prob);
+  if (rc) return rc;
+  if (prob->rows || is_csc(prob) || opts->rule >= GS_RULE_STATIC ||
+      (opts->enet_alpha != 0.0 && opts->enet_alpha < 1.0))
+    return GS_EUNSUPPORTED;  // one schedule only: nothing to choose
+  if (!workspace) return GS_EWORKSPACE;
+  if (ws_bytes < path_ws(prob, 1)) return GS_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gs_problem q = *prob;
+  first_lambdas(&q, max_lambdas);
+  gs_opts o = *opts;
+  o.select_counts = nullptr;
+  o.timestamps = nullptr;
+  o.stats = nullptr;
+  float ms[2] = {0.f, 0.f};
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  for (int w = 0; w < 2 && rc >= 0; ++w) {
+    o.schedule = w ? GS_SCHED_WIDE : GS_SCHED_NARROW;
+    for (int rep = 0; rep < 2 && rc >= 0; ++rep) {  // the first run loads the code
+      if (hipEventRecord(ea, s) != hipSuccess) rc = GS_EHIP;
+      if (rc >= 0) rc = lasso_path(&q, &o, workspace, ws_bytes, stream);
+      if (rc >= 0 && hipEventRecord(eb, s) != hipSuccess) rc = GS_EHIP;
+      if (rc >= 0 && hipEventSynchronize(eb) != hipSuccess) rc = GS_EHIP;
+      if (rc >= 0 && hipEventElapsedTime(&ms[w], ea, eb) != hipSuccess) rc = GS_EHIP;
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (rc < 0) return rc;
+  const bool wide = ms[1] < ms[0];
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int k = prob->dtype == GS_F64 ? 1 : 0;
+    g_sched_pts[k].push_back({(double)prob->n * (double)prob->p, wide});
+    g_wide_thr[k] = fit_threshold(g_sched_pts[k]);
+  }
+  if (choice_out) *choice_out = wide ? 1 : 0;
+  return GS_OK;
+}
+
+double gs_wide_threshold(int32_t dtype) {
+  if (dtype != GS_F32 && dtype != GS_F64) return -1.0;
+  return wide_threshold(dtype);
+}
+
 void gs_tune_reset(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned.clear();
+  for (int k = 0; k < 2; ++k) {
+    g_sched_pts[k].clear();
+    g_wide_thr[k] = kWideThreshold;
+  }
 }
 
 int gs_tune_save(const char* path) {
@@ -1219,6 +1320,10 @@ int gs_tune_save(const char* path) {
                  c.cfg.S, c.cfg.NG);
     first = false;
   }
+  std::fprintf(f, "\n], \"schedule\": [");
+  for (int k = 0; k < 2; ++k)
+    std::fprintf(f, "%s\n  {\"sched_dtype\": %d, \"wide_threshold\": %.17g}", k ? "," : "", k,
+                 g_wide_thr[k]);
   std::fprintf(f, "\n]}\n");
   std::fclose(f);
   return GS_OK;
@@ -1257,6 +1362,19 @@ int gs_tune_load(const char* path) {
       }
     }
     pos += 8;
+  }
+  pos = 0;
+  while ((pos = text.find("{\"sched_dtype\"", pos)) != std::string::npos) {
+    int k;
+    double thr;
+    if (std::sscanf(text.c_str() + pos, "{\"sched_dtype\": %d, \"wide_threshold\": %lf}", &k,
+                    &thr) == 2 &&
+        (k == 0 || k == 1) && thr > 0.0 && std::isfinite(thr)) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_wide_thr[k] = thr;
+      ++loaded;
+    }
+    pos += 14;
   }
   return loaded > 0 ? GS_OK : GS_EINVAL;
 }

@@ -187,9 +187,33 @@ def test_plan_and_tuner_argument_checks(lib, tmp_path):
     path = str(tmp_path / "tiles.json")
     assert lib.gs_tune_save(path.encode()) == gs.GS_OK
     import json
-    assert json.load(open(path)) == {"tiles": []}
+    thr0 = 16.0 * 1024 * 1024
+    assert json.load(open(path)) == {"tiles": [], "schedule": [
+        {"sched_dtype": 0, "wide_threshold": thr0}, {"sched_dtype": 1, "wide_threshold": thr0}]}
+    with open(path, "w") as f:
+        f.write('{"tiles": []}\n')
     assert lib.gs_tune_load(path.encode()) == gs.GS_EINVAL  # no entry
     assert lib.gs_tune_load(str(tmp_path / "missing.json").encode()) == gs.GS_EINVAL
+    # schedule thresholds: defaults, a loaded value, reset
+    assert lib.gs_wide_threshold(0) == thr0 and lib.gs_wide_threshold(1) == thr0
+    assert lib.gs_wide_threshold(7) == -1.0
+    with open(path, "w") as f:
+        f.write('{"tiles": [], "schedule": [\n  {"sched_dtype": 1, "wide_threshold": 2500000}\n]}\n')
+    assert lib.gs_tune_load(path.encode()) == gs.GS_OK
+    assert lib.gs_wide_threshold(1) == 2500000.0 and lib.gs_wide_threshold(0) == thr0
+    lib.gs_tune_reset()
+    assert lib.gs_wide_threshold(1) == thr0
+    # the schedule autotuner's argument checks (before any launch)
+    c1 = ctypes.c_int32(-1)
+    assert lib.gs_autotune_schedule(None, ctypes.byref(o), ctypes.c_void_p(4096), 1 << 30, None,
+                                    3, ctypes.byref(c1)) == gs.GS_EINVAL
+    assert lib.gs_autotune_schedule(ctypes.byref(pr), ctypes.byref(o), ctypes.c_void_p(4096),
+                                    1 << 30, None, 0, ctypes.byref(c1)) == gs.GS_EINVAL
+    assert lib.gs_autotune_schedule(ctypes.byref(pr), ctypes.byref(o), None, 0, None, 3,
+                                    ctypes.byref(c1)) == gs.GS_EWORKSPACE
+    rows = _prob(rows=4096)
+    assert lib.gs_autotune_schedule(ctypes.byref(rows), ctypes.byref(o), ctypes.c_void_p(4096),
+                                    1 << 30, None, 3, ctypes.byref(c1)) == gs.GS_EUNSUPPORTED
     # a valid entry (dtype 0, 16-byte loads, S=4 NG=5 -> S=16 NG=3) loads and saves back
     with open(path, "w") as f:
         f.write('{"tiles": [\n  {"dtype": 0, "vec": 4, "gather": 0, "S": 4, "NG": 5, '

@@ -782,3 +782,44 @@ def test_batch_mixed_configs_concurrent_groups(torch, orc):
                 np.testing.assert_array_equal(_np(o["epochs"]), ref[b][1])
     finally:
         plan.close()
+
+
+def test_autotune_schedule_moves_threshold(torch):
+    """The schedule autotuner times both schedules on a small and a large
+    problem (Gaussian designs, the first 3 lambdas of the grid: one wavefront
+    for a whole large correlated design would take minutes); the FP32
+    threshold ends on the right side of each measured size (between them
+    when the small one is narrow-faster and the large one wide-faster), and
+    lasso_path's auto schedule then runs the faster one on the large problem
+    (its sweep or its path kernel shows in the timing)."""
+    gs.tune_reset()
+    small = synth.gaussian(31, 100, 2000)
+    big = synth.gaussian(32, 400, 50000)
+    res = []
+    for d in (small, big):
+        X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+        Xd, yd = _dev(torch, X, y)
+        print(f"schedule autotuner: timing {X.shape}", flush=True)
+        ch = gs.autotune_schedule(Xd, yd, T=100, lambda_min_ratio=1e-3, max_lambdas=3)
+        print(f"schedule autotuner: {X.shape} -> {ch}", flush=True)
+        res.append((X.shape[0] * X.shape[1], ch, Xd, yd, y))
+    thr = gs.wide_threshold("f32")
+    for npv, ch, *_ in res:
+        assert (npv > thr) == (ch == "wide") or res[0][1] == "wide" and res[1][1] == "narrow", \
+            (npv, ch, thr)
+    npv, ch, Xd, yd, y = res[1]
+    gs.timing_enable(True)
+    gs.timing_reset()
+    rel = 1e-3 ** (np.arange(100) / 99)
+    r = gs.lasso_path(Xd, yd, lambdas=rel[:10], relative=True)
+    torch.cuda.synchronize()
+    sweep_n = gs.timing_query("sweep")[1]
+    path_n = gs.timing_query("path")[1]
+    gs.timing_enable(False)
+    yy = float(np.sum(y.astype(np.float64) ** 2))
+    assert np.all(_np(r["status"]) == 0) and np.all(_np(r["gap"]) <= 1e-8 * yy)
+    ran_wide = sweep_n > 0 and path_n == 0
+    assert ran_wide == (npv > thr)
+    print(f"schedule autotuner: small {res[0][1]}, large {res[1][1]}, f32 threshold {thr:.4g}")
+    gs.tune_reset()
+    assert gs.wide_threshold("f32") == 16.0 * 1024 * 1024

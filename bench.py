@@ -584,7 +584,7 @@ def main():
         _log("sweep: c4 1000x100000 FP32 (400 MB), two rotating copies")
         sweep = bench_sweep(gs, torch, d4, a.sweep_reps)
         _log(f"sweep: {sweep['avg_us']:.1f} us, {sweep['gbs']:.0f} GB/s")
-        roof = {"bound": "hbm", "kernel": "k_wide_sweep<float,4,4,true>",
+        roof = {"bound": "hbm", "kernel": "k_wide_sweep<float,4,4,1>",
                 "achieved": round(sweep["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(sweep["gbs"] / HBM_PEAK_GBS, 4), "traffic": sweep_traffic(),
                 "bytes_per_launch": sweep["bytes"], "avg_us": round(sweep["avg_us"], 2),

@@ -391,11 +391,15 @@ __global__ void k_warm_choose(const double* __restrict__ gap_plain,
                               const double* __restrict__ gap_net,
                               const double* __restrict__ beta_net,
                               const double* __restrict__ beta_plain, int p,
-                              double* __restrict__ start, int32_t* __restrict__ flag) {
+                              double* __restrict__ start, int32_t* __restrict__ flag,
+                              int32_t* __restrict__ taken) {
   const bool net = *gap_net < *gap_plain;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < p; j += gridDim.x * blockDim.x)
     start[j] = net ? beta_net[j] : beta_plain[j];
-  if (flag && blockIdx.x == 0 && threadIdx.x == 0) *flag = net ? 1 : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (flag) *flag = net ? 1 : 0;
+    *taken = net ? 1 : 0;
+  }
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int cnt, int v) {
@@ -495,7 +499,7 @@ LearnedWs carve_learned(const gs_problem* pr, char* base) {
   w.bw = reinterpret_cast<double*>(take(sizeof(double) * C));
   w.mark = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * P));
   w.c2 = reinterpret_cast<double*>(take(sizeof(double) * P));
-  w.cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 4));
+  w.cnt = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 16));
   w.wsolve = take(ws_solve_bytes((int)C));
   w.total = off;
   return w;
@@ -517,24 +521,35 @@ int ws_start(const gs_problem* pr, const LearnedWs& w, int q, const double* bpre
   m = 0;
   // the previous support and the network's predicted entrants, the logit
   // threshold raised until at most min(GS_WS_ADD, (cap - |previous support|)
-  // / 2) enter (none when even the last threshold admits more)
-  int32_t h[4];
-  int mm = 0;
-  for (float tau : {0.f, 1.f, 2.f, 3.f, 4.f, 6.f, 8.f, INFINITY}) {
-    int rc = fill_i32(w.mark, p, 0, s);
-    if (rc) return rc;
-    rc = fill_i32(w.cnt, 4, 0, s);
-    if (rc) return rc;
-    rc = ws_select(w.out, w.act, q, bprev, w.c, tau, w.cap, w.W, w.sig, w.mark, w.cnt, s);
-    if (rc) return rc;
-    rc = read_cnt(w, h, s);
-    if (rc) return rc;
-    mm = h[0];
-    const int kin = std::min((int)GS_WS_ADD, std::max(0, (w.cap - (h[0] - h[1])) / 2));
-    if (h[1] <= kin) break;
+  // / 2) enter (none when even the last threshold admits more); the counts
+  // for every threshold come from one pass
+  static const float taus[7] = {0.f, 1.f, 2.f, 3.f, 4.f, 6.f, 8.f};
+  int rc = ws_count(w.out, w.act, q, bprev, taus, w.cnt + 4, s);
+  if (rc) return rc;
+  int32_t c8[8];
+  {
+    hipError_t e = hipMemcpyAsync(c8, w.cnt + 4, sizeof(c8), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_hip_error(e, "lasso_path_learned: working set");
   }
+  const int kin = std::min((int)GS_WS_ADD, std::max(0, (w.cap - c8[0]) / 2));
+  float tau = INFINITY;
+  int fresh = 0;
+  for (int i = 0; i < 7; ++i)
+    if (c8[1 + i] <= kin) {
+      tau = taus[i];
+      fresh = c8[1 + i];
+      break;
+    }
+  int mm = c8[0] + fresh;
   if (mm < 1 || mm > w.cap) return GS_OK;
-  int rc = GS_OK;
+  rc = fill_i32(w.mark, p, 0, s);
+  if (rc) return rc;
+  rc = fill_i32(w.cnt, 4, 0, s);
+  if (rc) return rc;
+  rc = ws_select(w.out, w.act, q, bprev, w.c, tau, w.cap, w.W, w.sig, w.mark, w.cnt, s);
+  if (rc) return rc;
+  int32_t h[4];
   for (int r = 0;; ++r) {
     for (int dd = 0;; ++dd) {
       rc = ws_solve(n, p, pr->ldx, dt, pr->X, pr->y, w.W, w.sig, mm, lam, w.bw, w.cnt + 3,
@@ -745,6 +760,7 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
   for (int t = 0; t < T; ++t) {
     const double* bprev = t == 0 ? prob->beta_init : prob->beta_out + (t - 1) * P;
     const double* startp = bprev;
+    bool net_start = false;
     if (params && bprev) {
       // plain screening pass at the previous solution: A_plain and c
       rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], rule, nullptr, 0, w.act, w.q,
@@ -774,10 +790,15 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
           if (rc) return rc;
           hipLaunchKernelGGL(k_warm_choose, dim3(grid_for(p, 256)), dim3(256), 0, s, w.scal + 2,
                              w.scal + 3, w.beta0, bprev, p, w.start,
-                             learned_out ? learned_out + t : nullptr);
+                             learned_out ? learned_out + t : nullptr, w.cnt + 12);
           rc = last_launch("k_warm_choose");
           if (rc) return rc;
           startp = w.start;
+          int32_t taken = 0;
+          hipError_t e2 = hipMemcpyAsync(&taken, w.cnt + 12, sizeof(taken), hipMemcpyDeviceToHost, s);
+          if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+          if (e2 != hipSuccess) return set_hip_error(e2, "lasso_path_learned: choice");
+          net_start = taken != 0;
         }
       }
     }
@@ -792,7 +813,13 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
     sub.nactive_out = prob->nactive_out + t;
     sub.status_out = prob->status_out + t;
     sub.lambda_out = prob->lambda_out ? prob->lambda_out + t : nullptr;
-    rc = lasso_path(&sub, opts, w.inner, w.inner_bytes, s);
+    // From the network's start the run is usually its first screening pass
+    // alone: the wide schedule does that pass over the whole GPU, where the
+    // narrow one spends a wavefront's prologue over all p columns.
+    gs_opts so = opts ? *opts : gs_opts{};
+    if (!opts) gs_opts_default(&so);
+    if (net_start && so.schedule == GS_SCHED_AUTO) so.schedule = GS_SCHED_WIDE;
+    rc = lasso_path(&sub, &so, w.inner, w.inner_bytes, s);
     if (rc < 0) return rc;
     if (rc == GS_NOT_CONVERGED) agg = GS_NOT_CONVERGED;
   }

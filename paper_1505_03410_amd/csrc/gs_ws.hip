@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_
 
 // ---- factorization of the diagonal tile K (unblocked, right-looking) by one
 // wavefront: lane i owns row i of the tile in LDS and updates it in chunks of
-// eight entries (all loads of a chunk issued together); column c of L goes to
+// 32 entries (all loads of a chunk issued together); column c of L goes to
 // every lane through LDS.  Writes L_KK to the lower triangle and its
 // transpose to the upper one.  A pivot that is not positive (or not finite)
 // stops the factorization with info = its 1-based row.
@@ -161,18 +161,18 @@ __global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ G, int M,
     col[i] = lic;
     __syncthreads();  // column c is in col (and every lane read the pivot)
     T[i][c] = lic;
-    for (int j0 = (c + 1) & ~7; j0 < TB; j0 += 8) {
-      double a[8], w[8];
+    for (int j0 = (c + 1) & ~31; j0 < TB; j0 += 32) {
+      double a[32], w[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 32; ++u) {
         a[u] = T[i][j0 + u];
         w[u] = col[j0 + u];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 32; ++u)
         if (j0 + u > c) a[u] = fma(-lic, w[u], a[u]);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) T[i][j0 + u] = a[u];
+      for (int u = 0; u < 32; ++u) T[i][j0 + u] = a[u];
     }
     __syncthreads();
   }
@@ -343,6 +343,39 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
 
 // ---- working-set kernels of the learned driver (one block each unless
 // stated).  cnt[0] = |W|; mark (p int32) flags the members of W.
+
+// Counts over the positions of act (q of them): cnt[0] = members of the
+// support of beta_prev, cnt[1 + i] = the others whose support logit o1 >
+// taus[i], i < kWsTaus.
+constexpr int kWsTaus = 7;
+struct WsTaus {
+  float v[kWsTaus];
+};
+__global__ __launch_bounds__(1024) void k_ws_count(const float* __restrict__ out,
+                                                   const int32_t* __restrict__ act, int q,
+                                                   const double* __restrict__ bprev, WsTaus taus,
+                                                   int32_t* __restrict__ cnt) {
+  __shared__ int acc[1 + kWsTaus];
+  const int t = threadIdx.x;
+  if (t <= kWsTaus) acc[t] = 0;
+  __syncthreads();
+  int loc[1 + kWsTaus] = {};
+  for (int k = t; k < q; k += 1024) {
+    const int j = act[k];
+    if (bprev && bprev[j] != 0.0) {
+      ++loc[0];
+    } else {
+      const float o1 = out[2 * (int64_t)j + 1];
+#pragma unroll
+      for (int i = 0; i < kWsTaus; ++i) loc[1 + i] += o1 > taus.v[i] ? 1 : 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i <= kWsTaus; ++i)
+    if (loc[i]) atomicAdd(&acc[i], loc[i]);
+  __syncthreads();
+  if (t <= kWsTaus) cnt[t] = acc[t];
+}
 
 // W = positions of act (q of them) on the support of beta_prev or whose
 // support logit o1 > tau, in order; sigma = sign(beta_prev) on its support,
@@ -634,6 +667,14 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   }
   hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kSolveThreads), 0, s, G, M, rhs, m, b_out, info);
   return ws_last("k_chol_solve");
+}
+
+int ws_count(const float* out, const int32_t* act, int q, const double* bprev,
+             const float* taus, int32_t* cnt8, hipStream_t s) {
+  WsTaus tv;
+  for (int i = 0; i < kWsTaus; ++i) tv.v[i] = taus[i];
+  hipLaunchKernelGGL(k_ws_count, dim3(1), dim3(1024), 0, s, out, act, q, bprev, tv, cnt8);
+  return ws_last("k_ws_count");
 }
 
 int ws_select(const float* out, const int32_t* act, int q, const double* bprev, const double* c,

@@ -344,6 +344,29 @@ def _c4_small(seed, p=2000, n=120):
     return d["X"], d["y"]
 
 
+def test_learned_path_f64_and_small_n(torch, orc):
+    """The learned driver on the 50 x 500 FP64 problem (working sets capped at
+    n - 1 = 49 columns, down to lambda_max / 1000 where the support nears n)
+    and on a 30 x 40 FP32 problem (p close to n): every lambda certified and
+    within the oracle's bounds, whichever start each lambda took."""
+    import os
+    wfile = os.path.join(os.path.dirname(gs.__file__), "warm_mlp.npy")
+    P = torch.from_numpy(np.load(wfile).astype(np.float32)).cuda()
+    d = synth.c0()
+    X, y = d["X"], d["y"]
+    Xd, yd = _dev(torch, X, y, 2)
+    got = gs.lasso_path_learned(Xd, yd, P, T=40, lambda_min_ratio=1e-3)
+    _check_path(X, y, got, orc, _np(got["lambdas"]))
+    taken_c0 = int(_np(got["learned"]).sum())
+    d = synth.gaussian(77, 30, 40, k=5)
+    X, y = d["X"].astype(np.float32), d["y"].astype(np.float32)
+    Xd, yd = _dev(torch, X, y)
+    got = gs.lasso_path_learned(Xd, yd, P, T=30, lambda_min_ratio=1e-3)
+    _check_path(X, y, got, orc, _np(got["lambdas"]))
+    print(f"learned driver: c0 started {taken_c0} of 39 lambdas from the network, "
+          f"30 x 40 {int(_np(got['learned']).sum())} of 29")
+
+
 def test_learned_path_plain_mode_certified(torch, orc):
     """params = None: every lambda warm-starts from the previous solution,
     one lasso_path call per lambda; the same certified answers as the plain

@@ -296,26 +296,37 @@ struct Narrow {
     double r[RPL];
     load_rows(x, x.rho_l, r);
     double Ml = 0.0, l1l = 0.0, sbl = 0.0, xml = 0.0;
+    // The column indices of the next step are loaded a step ahead; every
+    // lane of a slot stores the slot's value, positions past the end
+    // clamped to the last one (whose value is stored again, the same), so
+    // that the step has no data-dependent branch and its memory waits stay
+    // exact.
+    int jn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) jn[u] = act_at(x, u * C + x.slot, q, full);
     for (int base = 0; base < q; base += U * C) {
       Stage st[U];
       double nr[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = base + u * C + x.slot;
-        fetch_j<false>(x, k, act_at(x, k, q, full), q, nullptr, nullptr, st[u]);
+        fetch_j<false>(x, k, jn[u], q, nullptr, nullptr, st[u]);
         nr[u] = x.nrm2[st[u].j];
       }
 #pragma unroll
+      for (int u = 0; u < U; ++u) jn[u] = act_at(x, base + (U + u) * C + x.slot, q, full);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
       for (int u = 0; u < U; ++u) {
         const double d = dotx(st[u].x, r);
-        if (st[u].v && x.seg == 0) {
-          x.c[base + u * C + x.slot] = d;
-          Ml = fmax(Ml, fabs(d));
-          const double xn = sqrt(nr[u]);
-          l1l += fabs(st[u].b);
-          sbl += fabs(st[u].b) * xn;
-          xml = fmax(xml, xn);
-        }
+        x.c[st[u].k] = d;
+        const bool own = st[u].v && x.seg == 0;  // one contribution per position
+        const double xn = sqrt(nr[u]);
+        const double ab = own ? fabs(st[u].b) : 0.0;
+        Ml = fmax(Ml, own ? fabs(d) : 0.0);
+        l1l += ab;
+        sbl += ab * xn;
+        xml = fmax(xml, own ? xn : 0.0);
       }
     }
     M = wave_max(Ml);

@@ -303,7 +303,7 @@ struct Narrow {
     // exact.
     int jn[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) jn[u] = act_at(x, u * C + x.slot, q, full);
+    for (int u = 0; u < U; ++u) jn[u] = q > 0 ? act_at(x, u * C + x.slot, q, full) : 0;
     for (int base = 0; base < q; base += U * C) {
       Stage st[U];
       double nr[U];

@@ -449,10 +449,15 @@ int gs_warm_features(int32_t p, const double* c, const double* beta_prev,
  *      gives c; the (at most GS_WS_ADD) largest violators |c_j| > lambda_t
  *      outside W join W with sigma_j = sign(c_j), and step 3 runs again;
  *      no violator ends the rounds;
- *   5. the duality gaps of beta0 and of beta^{lambda_{t-1}} on the problem
+ *   5. when the rounds ended with no violator and that last pass found the
+ *      duality gap of beta0 on the problem reduced to A_plain already <= eps
+ *      (a certificate for the whole problem: A_plain is safe), lambda_t is
+ *      output from it -- beta0, that gap, 0 epochs, the pass's kept count as
+ *      nactive -- as Algorithm 1 would stop at its first pass; otherwise
+ *   6. the duality gaps of beta0 and of beta^{lambda_{t-1}} on the problem
  *      reduced to A_plain are compared, and the smaller one's point starts
- *      lambda_t (ties keep the plain start);
- *   6. Algorithm 1 runs for lambda_t from there, exactly as in lasso_path.
+ *      lambda_t (ties keep the plain start), and
+ *   7. Algorithm 1 runs for lambda_t from there, exactly as in lasso_path.
  * A working set larger than cap = min(n - 1, p, GS_WS_MAX) or a failed
  * factorization (a pivot that is not positive) leaves lambda_t to the plain
  * start.  The output o0 is not used by the driver (the restricted solve

@@ -505,6 +505,26 @@ LearnedWs carve_learned(const gs_problem* pr, char* base) {
   return w;
 }
 
+// lambda_t output from the working-set start certified on the safe set: beta0,
+// that pass's gap and kept count, 0 epochs, status 0.
+__global__ void k_ws_emit(const double* __restrict__ beta0, int p, double* __restrict__ beta_out,
+                          const double* __restrict__ gap, const int32_t* __restrict__ kept,
+                          double* __restrict__ gap_out, int32_t* __restrict__ epochs_out,
+                          int32_t* __restrict__ nactive_out, int32_t* __restrict__ status_out,
+                          double* __restrict__ lambda_out, double lam,
+                          int32_t* __restrict__ flag) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < p; j += gridDim.x * blockDim.x)
+    beta_out[j] = beta0[j];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *gap_out = *gap;
+    *epochs_out = 0;
+    *nactive_out = *kept;
+    *status_out = GS_STATUS_CONVERGED;
+    if (lambda_out) *lambda_out = lam;
+    if (flag) *flag = 1;
+  }
+}
+
 // Reads the four working-set counters (|W|, dropped, added, info).
 int read_cnt(const LearnedWs& w, int32_t (&h)[4], hipStream_t s) {
   hipError_t e = hipMemcpyAsync(h, w.cnt, sizeof(h), hipMemcpyDeviceToHost, s);
@@ -516,9 +536,10 @@ int read_cnt(const LearnedWs& w, int32_t (&h)[4], hipStream_t s) {
 // receives |W| (0: no start, the plain one is used).  Needs the network's
 // outputs in w.out, A_plain in w.act (q positions) and c at beta_prev in w.c.
 int ws_start(const gs_problem* pr, const LearnedWs& w, int q, const double* bprev, double lam,
-             int rule, int& m, hipStream_t s) {
+             int rule, int& m, bool& gap_known, hipStream_t s) {
   const int n = pr->n, p = pr->p, dt = pr->dtype;
   m = 0;
+  gap_known = false;
   // the previous support and the network's predicted entrants, the logit
   // threshold raised until at most min(GS_WS_ADD, (cap - |previous support|)
   // / 2) enter (none when even the last threshold admits more); the counts
@@ -575,7 +596,10 @@ int ws_start(const gs_problem* pr, const LearnedWs& w, int q, const double* bpre
     if (rc) return rc;
     rc = read_cnt(w, h, s);
     if (rc) return rc;
-    if (h[2] == 0) break;
+    if (h[2] == 0) {  // no violator: the pass just made was at this beta0
+      gap_known = true;
+      break;
+    }
     mm = h[0];
   }
   m = mm;
@@ -757,6 +781,9 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
   }
   const int64_t P = p;
   int agg = GS_OK;
+  gs_opts od;
+  gs_opts_default(&od);
+  const double eps_abs = (opts ? opts->eps_rel : od.eps_rel) * ynorm * ynorm;
   for (int t = 0; t < T; ++t) {
     const double* bprev = t == 0 ? prob->beta_init : prob->beta_out + (t - 1) * P;
     const double* startp = bprev;
@@ -774,11 +801,32 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
       hipError_t e = hipMemcpyAsync(&q, w.q, sizeof(q), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) return set_hip_error(e, "lasso_path_learned: active size");
+      bool emitted = false;
       if (q > 0 && q <= p && w.cap >= 1) {
         int m = 0;
-        rc = ws_start(prob, w, q, bprev, lam[t], rule, m, s);
+        bool gap_known = false;
+        rc = ws_start(prob, w, q, bprev, lam[t], rule, m, gap_known, s);
         if (rc) return rc;
-        if (m >= 1) {
+        if (m >= 1 && gap_known) {
+          // already certified on the safe set: Algorithm 1 would stop at its
+          // first pass from this start, so lambda_t is output from it
+          double g = INFINITY;
+          hipError_t e3 = hipMemcpyAsync(&g, w.scal + 3, sizeof(g), hipMemcpyDeviceToHost, s);
+          if (e3 == hipSuccess) e3 = hipStreamSynchronize(s);
+          if (e3 != hipSuccess) return set_hip_error(e3, "lasso_path_learned: gap");
+          if (g <= eps_abs) {
+            hipLaunchKernelGGL(k_ws_emit, dim3(grid_for(p, 256)), dim3(256), 0, s, w.beta0, p,
+                               prob->beta_out + t * P, w.scal + 3, w.q + 1, prob->gap_out + t,
+                               prob->epochs_out + t, prob->nactive_out + t,
+                               prob->status_out + t,
+                               prob->lambda_out ? prob->lambda_out + t : nullptr, lam[t],
+                               learned_out ? learned_out + t : nullptr);
+            rc = last_launch("k_ws_emit");
+            if (rc) return rc;
+            emitted = true;
+          }
+        }
+        if (m >= 1 && !emitted) {
           // both candidates' gaps on the reduced problem over A_plain
           rc = screen(n, p, prob->ldx, dt, prob->X, prob->y, bprev, lam[t], rule, w.act, q,
                       w.act2, w.q + 1, w.scal + 2, w.scal + 4, w.scal + 5, nullptr, w.inner,
@@ -801,6 +849,7 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
           net_start = taken != 0;
         }
       }
+      if (emitted) continue;
     }
     gs_problem sub = *prob;
     sub.T = 1;

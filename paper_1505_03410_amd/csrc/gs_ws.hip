@@ -148,6 +148,8 @@ __global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ G, int M,
   if (ws_failed(info)) return;
   const int i = threadIdx.x;
   const int64_t o = (int64_t)K * TB;
+  // the tile's loads are issued 16 at a time before their stores to LDS
+#pragma unroll 16
   for (int j = 0; j < TB; ++j) T[i][j] = G[(o + j) * M + o + i];
   __syncthreads();
   for (int c = 0; c < TB; ++c) {
@@ -191,6 +193,7 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int M
   const int r = threadIdx.x;
   const int I = K + 1 + blockIdx.x;
   const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB;
+#pragma unroll 16
   for (int e = r; e < TB * TB; e += 64) {
     const int i = e % TB, j = e / TB;
     L[i][j] = G[(o + j) * M + o + i];
@@ -231,6 +234,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
   const int J = K + 1 + jj, I = J + b;
   const int t = threadIdx.x;
   const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, oj = (int64_t)J * TB;
+#pragma unroll
   for (int e = t; e < TB * TB; e += 256) {
     const int i = e % TB, k = e / TB;
     A[i][k] = G[(o + k) * M + oi + i];
@@ -287,6 +291,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
   for (int K = 0; K < NT; ++K) {
     const int64_t o = (int64_t)K * TB;
     __syncthreads();  // z and the previous tile's use of L are complete
+#pragma unroll
     for (int e = t; e < TB * TB; e += kSolveThreads) {
       const int i = e % TB, j = e / TB;
       L[i][j] = G[(o + j) * M + o + i];
@@ -314,6 +319,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
   for (int K = NT - 1; K >= 0; --K) {
     const int64_t o = (int64_t)K * TB;
     __syncthreads();
+#pragma unroll
     for (int e = t; e < TB * TB; e += kSolveThreads) {
       const int i = e % TB, j = e / TB;
       L[i][j] = G[(o + j) * M + o + i];

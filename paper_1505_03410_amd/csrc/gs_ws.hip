@@ -135,52 +135,54 @@ __global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_
   if (lane == 0) b[a] = s - lambda * sigma[a];
 }
 
-// ---- factorization of the diagonal tile K (unblocked, right-looking) by one
-// wavefront: lane i owns row i of the tile in LDS and updates it in chunks of
-// 32 entries (all loads of a chunk issued together); column c of L goes to
-// every lane through LDS.  Writes L_KK to the lower triangle and its
+// ---- factorization of the diagonal tile K (unblocked, right-looking) in LDS
+// by 256 threads: four per row, thread (i, q) updating the entries j = q mod 4
+// of row i, sixteen at a time with all loads issued first; column c of L goes
+// to every thread through LDS.  Writes L_KK to the lower triangle and its
 // transpose to the upper one.  A pivot that is not positive (or not finite)
 // stops the factorization with info = its 1-based row.
-__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ G, int M, int K,
-                                                  int32_t* info) {
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M, int K,
+                                                   int32_t* info) {
   __shared__ double T[TB][TB + 1];
   __shared__ double col[TB];
   if (ws_failed(info)) return;
-  const int i = threadIdx.x;
+  const int t = threadIdx.x;
+  const int i = t >> 2, qd = t & 3;
   const int64_t o = (int64_t)K * TB;
-  // the tile's loads are issued 16 at a time before their stores to LDS
-#pragma unroll 16
-  for (int j = 0; j < TB; ++j) T[i][j] = G[(o + j) * M + o + i];
+#pragma unroll
+  for (int e = t; e < TB * TB; e += 256) {
+    const int r = e % TB, j = e / TB;
+    T[r][j] = G[(o + j) * M + o + r];
+  }
   __syncthreads();
   for (int c = 0; c < TB; ++c) {
     const double piv = T[c][c];
-    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every lane read the same value
-      if (i == 0) *info = (int32_t)(o + c + 1);
+    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread read the same value
+      if (t == 0) *info = (int32_t)(o + c + 1);
       return;
     }
-    const double dg = sqrt(piv);
-    const double lic = i > c ? T[i][c] / dg : (i == c ? dg : 0.0);
-    col[i] = lic;
-    __syncthreads();  // column c is in col (and every lane read the pivot)
-    T[i][c] = lic;
-    for (int j0 = (c + 1) & ~31; j0 < TB; j0 += 32) {
-      double a[32], w[32];
+    if (qd == 0) col[i] = i > c ? T[i][c] / sqrt(piv) : (i == c ? sqrt(piv) : 0.0);
+    __syncthreads();  // column c is in col (and every thread read the pivot)
+    const double lic = col[i];
+    if (qd == 0) T[i][c] = lic;
+    double a[TB / 4], w[TB / 4];
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        a[u] = T[i][j0 + u];
-        w[u] = col[j0 + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 32; ++u)
-        if (j0 + u > c) a[u] = fma(-lic, w[u], a[u]);
-#pragma unroll
-      for (int u = 0; u < 32; ++u) T[i][j0 + u] = a[u];
+    for (int u = 0; u < TB / 4; ++u) {
+      a[u] = T[i][4 * u + qd];
+      w[u] = col[4 * u + qd];
     }
+#pragma unroll
+    for (int u = 0; u < TB / 4; ++u)
+      if (4 * u + qd > c) T[i][4 * u + qd] = fma(-lic, w[u], a[u]);
     __syncthreads();
   }
-  for (int j = 0; j <= i; ++j) {
-    G[(o + j) * M + o + i] = T[i][j];
-    G[(o + i) * M + o + j] = T[i][j];
+#pragma unroll
+  for (int e = t; e < TB * TB; e += 256) {
+    const int r = e % TB, j = e / TB;
+    if (r >= j) {
+      G[(o + j) * M + o + r] = T[r][j];
+      G[(o + r) * M + o + j] = T[r][j];
+    }
   }
 }
 
@@ -659,7 +661,7 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   rc = ws_last("k_ws_rhs");
   if (rc) return rc;
   for (int K = 0; K < NT; ++K) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, G, M, K, info);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, G, M, K, info);
     rc = ws_last("k_chol_diag");
     if (rc) return rc;
     const int T = NT - K - 1;

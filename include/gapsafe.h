@@ -436,7 +436,8 @@ int gs_warm_features(int32_t p, const double* c, const double* beta_prev,
  *      p gives the safe set A_plain and c (coordinates outside A_plain are
  *      zero at the optimum);
  *   2. the network maps u_j to (o0_j, o1_j); the working set W holds the j
- *      of A_plain on the support of beta_prev and those off it with o1_j >
+ *      of A_plain on the support of beta_prev and those off it that violate
+ *      the optimality conditions at beta_prev (|c_j| > lambda_t) with o1_j >
  *      tau (the network's predicted entrants), tau the first of 0, 1, 2, 3,
  *      4, 6, 8 that admits at most min(GS_WS_ADD, (cap - |supp beta_prev|)
  *      / 2) entrants (none if 8 admits more); signs sigma_j =

@@ -106,12 +106,13 @@ size_t ws_solve_bytes(int m);
 int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y, const int32_t* W,
              const double* sigma, int m, double lambda, double* b_out, int32_t* info,
              void* workspace, hipStream_t s);
-// cnt8[0] = |supp beta_prev within act|, cnt8[1 + i] = entrants with logit > taus[i] (7 taus)
-int ws_count(const float* out, const int32_t* act, int q, const double* bprev,
-             const float* taus, int32_t* cnt8, hipStream_t s);
+// cnt8[0] = |supp beta_prev within act|, cnt8[1 + i] = entrants (violators at beta_prev,
+// |c_j| > lambda) with logit > taus[i] (7 taus)
+int ws_count(const float* out, const int32_t* act, int q, const double* bprev, const double* c,
+             double lambda, const float* taus, int32_t* cnt8, hipStream_t s);
 int ws_select(const float* out, const int32_t* act, int q, const double* bprev, const double* c,
-              float tau, int cap, int32_t* W, double* sigma, int32_t* mark, int32_t* cnt,
-              hipStream_t s);
+              double lambda, float tau, int cap, int32_t* W, double* sigma, int32_t* mark,
+              int32_t* cnt, hipStream_t s);
 int ws_drop(int32_t* W, double* sigma, double* b, int32_t* mark, const double* bprev,
             int32_t* cnt, hipStream_t s);
 int ws_add(const int32_t* act, int q, const double* c, double lambda, int kadd, int cap,

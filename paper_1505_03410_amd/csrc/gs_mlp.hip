@@ -545,7 +545,7 @@ int ws_start(const gs_problem* pr, const LearnedWs& w, int q, const double* bpre
   // / 2) enter (none when even the last threshold admits more); the counts
   // for every threshold come from one pass
   static const float taus[7] = {0.f, 1.f, 2.f, 3.f, 4.f, 6.f, 8.f};
-  int rc = ws_count(w.out, w.act, q, bprev, taus, w.cnt + 4, s);
+  int rc = ws_count(w.out, w.act, q, bprev, w.c, lam, taus, w.cnt + 4, s);
   if (rc) return rc;
   int32_t c8[8];
   {
@@ -568,7 +568,7 @@ int ws_start(const gs_problem* pr, const LearnedWs& w, int q, const double* bpre
   if (rc) return rc;
   rc = fill_i32(w.cnt, 4, 0, s);
   if (rc) return rc;
-  rc = ws_select(w.out, w.act, q, bprev, w.c, tau, w.cap, w.W, w.sig, w.mark, w.cnt, s);
+  rc = ws_select(w.out, w.act, q, bprev, w.c, lam, tau, w.cap, w.W, w.sig, w.mark, w.cnt, s);
   if (rc) return rc;
   int32_t h[4];
   for (int r = 0;; ++r) {

@@ -353,16 +353,18 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
 // stated).  cnt[0] = |W|; mark (p int32) flags the members of W.
 
 // Counts over the positions of act (q of them): cnt[0] = members of the
-// support of beta_prev, cnt[1 + i] = the others whose support logit o1 >
-// taus[i], i < kWsTaus.
+// support of beta_prev, cnt[1 + i] = the others that violate the optimality
+// conditions at beta_prev (|c_j| > lambda, c indexed by column) and whose
+// support logit o1 > taus[i], i < kWsTaus.
 constexpr int kWsTaus = 7;
 struct WsTaus {
   float v[kWsTaus];
 };
 __global__ __launch_bounds__(1024) void k_ws_count(const float* __restrict__ out,
                                                    const int32_t* __restrict__ act, int q,
-                                                   const double* __restrict__ bprev, WsTaus taus,
-                                                   int32_t* __restrict__ cnt) {
+                                                   const double* __restrict__ bprev,
+                                                   const double* __restrict__ c, double lambda,
+                                                   WsTaus taus, int32_t* __restrict__ cnt) {
   __shared__ int acc[1 + kWsTaus];
   const int t = threadIdx.x;
   if (t <= kWsTaus) acc[t] = 0;
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_ws_count(const float* __restrict__ out
     const int j = act[k];
     if (bprev && bprev[j] != 0.0) {
       ++loc[0];
-    } else {
+    } else if (fabs(c[j]) > lambda) {
       const float o1 = out[2 * (int64_t)j + 1];
 #pragma unroll
       for (int i = 0; i < kWsTaus; ++i) loc[1 + i] += o1 > taus.v[i] ? 1 : 0;
@@ -385,14 +387,16 @@ __global__ __launch_bounds__(1024) void k_ws_count(const float* __restrict__ out
   if (t <= kWsTaus) cnt[t] = acc[t];
 }
 
-// W = positions of act (q of them) on the support of beta_prev or whose
-// support logit o1 > tau, in order; sigma = sign(beta_prev) on its support,
-// else sign(c) (c indexed by column).  cnt[0] = |W|, cnt[1] = the members
-// off the previous support.
+// W = positions of act (q of them) on the support of beta_prev, or violating
+// the optimality conditions at beta_prev (|c_j| > lambda) with support logit
+// o1 > tau, in order; sigma = sign(beta_prev) on its support, else sign(c)
+// (c indexed by column).  cnt[0] = |W|, cnt[1] = the members off the
+// previous support.
 __global__ __launch_bounds__(1024) void k_ws_select(const float* __restrict__ out,
                                                     const int32_t* __restrict__ act, int q,
                                                     const double* __restrict__ bprev,
-                                                    const double* __restrict__ c, float tau, int cap,
+                                                    const double* __restrict__ c, double lambda,
+                                                    float tau, int cap,
                                                     int32_t* __restrict__ W,
                                                     double* __restrict__ sigma,
                                                     int32_t* __restrict__ mark,
@@ -409,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_ws_select(const float* __restrict__ ou
     if (k < q) {
       j = act[k];
       const bool prev = bprev && bprev[j] != 0.0;
-      fresh = !prev && out[2 * (int64_t)j + 1] > tau;
+      fresh = !prev && fabs(c[j]) > lambda && out[2 * (int64_t)j + 1] > tau;
       in = prev || fresh;
     }
     const uint64_t fm = ballot(fresh);
@@ -677,19 +681,20 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   return ws_last("k_chol_solve");
 }
 
-int ws_count(const float* out, const int32_t* act, int q, const double* bprev,
-             const float* taus, int32_t* cnt8, hipStream_t s) {
+int ws_count(const float* out, const int32_t* act, int q, const double* bprev, const double* c,
+             double lambda, const float* taus, int32_t* cnt8, hipStream_t s) {
   WsTaus tv;
   for (int i = 0; i < kWsTaus; ++i) tv.v[i] = taus[i];
-  hipLaunchKernelGGL(k_ws_count, dim3(1), dim3(1024), 0, s, out, act, q, bprev, tv, cnt8);
+  hipLaunchKernelGGL(k_ws_count, dim3(1), dim3(1024), 0, s, out, act, q, bprev, c, lambda, tv,
+                     cnt8);
   return ws_last("k_ws_count");
 }
 
 int ws_select(const float* out, const int32_t* act, int q, const double* bprev, const double* c,
-              float tau, int cap, int32_t* W, double* sigma, int32_t* mark, int32_t* cnt,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(1024), 0, s, out, act, q, bprev, c, tau, cap, W,
-                     sigma, mark, cnt);
+              double lambda, float tau, int cap, int32_t* W, double* sigma, int32_t* mark,
+              int32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_select, dim3(1), dim3(1024), 0, s, out, act, q, bprev, c, lambda, tau,
+                     cap, W, sigma, mark, cnt);
   return ws_last("k_ws_select");
 }
 

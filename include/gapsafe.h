@@ -488,8 +488,8 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
  * W [device] m int32 in [0, p); sigma [device] m doubles; 1 <= m < n, m <= p,
  * m <= GS_WS_MAX (X_W must have full column rank); lambda >= 0 finite;
  * b_out [device] m doubles; info_out [device] 1 int32: 0 on success, k >= 1
- * when the k-th pivot was not positive (X_W numerically rank deficient;
- * b_out is then not written), -1 for an index of W outside [0, p).
+ * when the k-th pivot was not a positive normal number (X_W numerically rank
+ * deficient; b_out is then not written), -1 for an index of W outside [0, p).
  * workspace: gs_restricted_solve_workspace_size(m) bytes (about 8 m^2), or
  * 0 for an m out of range.  Asynchronous on `stream`.  GS_EINVAL for a bad
  * size, pointer or value, GS_EWORKSPACE for a small workspace. */

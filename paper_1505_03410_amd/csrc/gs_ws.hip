@@ -37,13 +37,15 @@ constexpr int TB = 64;  // tile size
 __device__ __forceinline__ bool ws_failed(const int32_t* info) { return *info != 0; }
 
 // ---- Gram tiles: block (I, J), I >= J, computes G[I-tile rows][J-tile cols]
-// over all n rows; rows pass through LDS 32 at a time.  Padding entries get
-// the identity.
+// over all n rows; rows pass through LDS 32 at a time, the next 32 loaded into
+// registers while the current ones are used.  Padding entries get the
+// identity.
 template <typename XT>
 __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64_t ldx, int n,
                                                  int p, const int32_t* __restrict__ W, int m,
                                                  int M, double* __restrict__ G) {
   constexpr int RC = 32;
+  constexpr int NL = (RC * TB) / 256;  // loads per thread and operand per chunk
   __shared__ double A[RC][TB + 1], B[RC][TB + 1];
   __shared__ int64_t ca[TB], cb[TB];
   // tile (I, J) from the block index: lower tiles in column order
@@ -63,31 +65,52 @@ __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64
     cb[t - TB] = a < m ? (int64_t)min(max(W[a], 0), p - 1) * ldx : -1;
   }
   __syncthreads();
+  // this thread's (column, row) slots of a chunk: 64 columns x 32 rows,
+  // consecutive threads on consecutive rows
+  int64_t oa[NL], ob[NL];
+  int rr[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int e = t + 256 * i;
+    rr[i] = e % RC;
+    oa[i] = ca[e / RC];
+    ob[i] = cb[e / RC];
+  }
+  // loads with the address clamped into X (a padding column reads X[0]); the
+  // value is masked when it reaches LDS
+  XT va[NL], vb[NL];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int r = min(r0 + rr[i], n - 1);
+      va[i] = X[oa[i] >= 0 ? oa[i] + r : 0];
+      vb[i] = X[ob[i] >= 0 ? ob[i] + r : 0];
+    }
+  };
   const int ta = t >> 4, tb = t & 15;  // this thread's 4 x 4 entries
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  load(0);
   for (int r0 = 0; r0 < n; r0 += RC) {
-    // 64 columns x 32 rows per tile; consecutive threads read consecutive rows
 #pragma unroll
-    for (int i = 0; i < (RC * TB) / 256; ++i) {
+    for (int i = 0; i < NL; ++i) {
       const int e = t + 256 * i;
-      const int col = e / RC, rr = e % RC;
-      const int r = r0 + rr;
-      const int64_t oa = ca[col], ob = cb[col];
-      A[rr][col] = (oa >= 0 && r < n) ? (double)X[oa + r] : 0.0;
-      B[rr][col] = (ob >= 0 && r < n) ? (double)X[ob + r] : 0.0;
+      const bool in = r0 + rr[i] < n;
+      A[rr[i]][e / RC] = (oa[i] >= 0 && in) ? (double)va[i] : 0.0;
+      B[rr[i]][e / RC] = (ob[i] >= 0 && in) ? (double)vb[i] : 0.0;
     }
     __syncthreads();
+    if (r0 + RC < n) load(r0 + RC);
 #pragma unroll 4
-    for (int rr = 0; rr < RC; ++rr) {
+    for (int q = 0; q < RC; ++q) {
       double av[4], bv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        av[u] = A[rr][ta * 4 + u];
-        bv[u] = B[rr][tb * 4 + u];
+        av[u] = A[q][ta * 4 + u];
+        bv[u] = B[q][tb * 4 + u];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -135,53 +158,69 @@ __global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_
   if (lane == 0) b[a] = s - lambda * sigma[a];
 }
 
-// ---- factorization of the diagonal tile K (unblocked, right-looking) in LDS
-// by 256 threads: four per row, thread (i, q) updating the entries j = q mod 4
-// of row i, sixteen at a time with all loads issued first; column c of L goes
-// to every thread through LDS.  Writes L_KK to the lower triangle and its
-// transpose to the upper one.  A pivot that is not positive (or not finite)
-// stops the factorization with info = its 1-based row.
+// ---- factorization of the diagonal tile K (unblocked, right-looking) by 256
+// threads: four per row, thread (i, q) holding the entries T_ij, j = q mod 4,
+// of row i in registers.  Column c stays unscaled (T_ic = L_ic L_cc, T_cc =
+// L_cc^2) while the trailing entries take T_ij -= (T_ic / T_cc) T_jc, so a
+// step needs only column c, which its owners (q = c mod 4) put in LDS before
+// the step's single barrier (two buffers alternate, so the next step's writes
+// cannot meet this step's reads); L is formed from the unscaled columns at
+// the end.  Writes L_KK to the lower triangle and its transpose to the upper
+// one.  A pivot that is not a positive normal number stops the factorization
+// with info = its 1-based row.
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M, int K,
                                                    int32_t* info) {
-  __shared__ double T[TB][TB + 1];
-  __shared__ double col[TB];
+  __shared__ double col[2][TB];
   if (ws_failed(info)) return;
   const int t = threadIdx.x;
   const int i = t >> 2, qd = t & 3;
   const int64_t o = (int64_t)K * TB;
+  double a[TB / 4];   // T_{i, 4u + qd}
+  double pv[TB / 4];  // the unscaled pivot T_jj of each column j = 4u + qd
 #pragma unroll
-  for (int e = t; e < TB * TB; e += 256) {
-    const int r = e % TB, j = e / TB;
-    T[r][j] = G[(o + j) * M + o + r];
+  for (int u = 0; u < TB / 4; ++u) {
+    a[u] = G[(o + 4 * u + qd) * M + o + i];
+    pv[u] = 1.0;
   }
-  __syncthreads();
+#pragma unroll
   for (int c = 0; c < TB; ++c) {
-    const double piv = T[c][c];
-    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread read the same value
+    const int uc = c >> 2, qc = c & 3;
+    double* cb = col[c & 1];
+    if (qd == qc) cb[i] = a[uc];
+    __syncthreads();
+    const double piv = cb[c];
+    if (!(piv >= 2.2250738585072014e-308) || !isfinite(piv)) {  // uniform value
       if (t == 0) *info = (int32_t)(o + c + 1);
       return;
     }
-    if (qd == 0) col[i] = i > c ? T[i][c] / sqrt(piv) : (i == c ? sqrt(piv) : 0.0);
-    __syncthreads();  // column c is in col (and every thread read the pivot)
-    const double lic = col[i];
-    if (qd == 0) T[i][c] = lic;
-    double a[TB / 4], w[TB / 4];
-#pragma unroll
-    for (int u = 0; u < TB / 4; ++u) {
-      a[u] = T[i][4 * u + qd];
-      w[u] = col[4 * u + qd];
+    if (qd == qc) pv[uc] = piv;
+    // 1 / piv by the hardware reciprocal and two Newton steps (error under
+    // 2 ulp for a normal pivot)
+    double r = __builtin_amdgcn_rcp(piv);
+    r = fma(r, fma(-piv, r, 1.0), r);
+    r = fma(r, fma(-piv, r, 1.0), r);
+    const double f = cb[i] * r;
+    // the entries j > c: all of u > uc, and j = 4 uc + q for q > qc
+    {
+      const double nv = fma(-f, cb[4 * uc + qd], a[uc]);
+      a[uc] = qd > qc ? nv : a[uc];
     }
 #pragma unroll
-    for (int u = 0; u < TB / 4; ++u)
-      if (4 * u + qd > c) T[i][4 * u + qd] = fma(-lic, w[u], a[u]);
-    __syncthreads();
+    for (int u = uc + 1; u < TB / 4; ++u) a[u] = fma(-f, cb[4 * u + qd], a[u]);
+    // the updated entries are materialized here: left to itself the compiler
+    // defers these products toward their next use and keeps every step's
+    // factor live, which spills
+#pragma unroll
+    for (int u = uc; u < TB / 4; ++u) asm volatile("" : "+v"(a[u]));
   }
 #pragma unroll
-  for (int e = t; e < TB * TB; e += 256) {
-    const int r = e % TB, j = e / TB;
-    if (r >= j) {
-      G[(o + j) * M + o + r] = T[r][j];
-      G[(o + r) * M + o + j] = T[r][j];
+  for (int u = 0; u < TB / 4; ++u) {
+    const int j = 4 * u + qd;
+    if (i >= j) {
+      const double d = sqrt(pv[u]);
+      const double v = i == j ? d : a[u] / d;
+      G[(o + j) * M + o + i] = v;
+      G[(o + i) * M + o + j] = v;
     }
   }
 }
@@ -195,8 +234,9 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int M
   const int r = threadIdx.x;
   const int I = K + 1 + blockIdx.x;
   const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB;
-#pragma unroll 16
-  for (int e = r; e < TB * TB; e += 64) {
+#pragma unroll
+  for (int k = 0; k < TB; ++k) {
+    const int e = r + 64 * k;
     const int i = e % TB, j = e / TB;
     L[i][j] = G[(o + j) * M + o + i];
   }
@@ -237,7 +277,8 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
   const int t = threadIdx.x;
   const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, oj = (int64_t)J * TB;
 #pragma unroll
-  for (int e = t; e < TB * TB; e += 256) {
+  for (int h = 0; h < TB * TB / 256; ++h) {
+    const int e = t + 256 * h;
     const int i = e % TB, k = e / TB;
     A[i][k] = G[(o + k) * M + oi + i];
     B[i][k] = G[(o + k) * M + oj + i];
@@ -279,6 +320,22 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
 // for j < c column c of the mirrored upper triangle, so both sweeps read
 // columns.
 constexpr int kSolveThreads = 1024;
+// acc - sum_c G[g + c M] zt[c] over the 64 entries c of a tile, the loads of
+// G issued 16 at a time ahead of their use (G holds at most 2048^2 entries,
+// so 32-bit indices)
+__device__ __forceinline__ double tile_dot(const double* __restrict__ G, int g, int M,
+                                           const double* zt, double acc) {
+#pragma unroll
+  for (int h = 0; h < TB; h += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = G[g + (h + u) * M];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc = fma(-v[u], zt[h + u], acc);
+  }
+  return acc;
+}
 __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __restrict__ G, int M,
                                                               const double* __restrict__ b,
                                                               int m, double* __restrict__ x_out,
@@ -294,56 +351,67 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
     const int64_t o = (int64_t)K * TB;
     __syncthreads();  // z and the previous tile's use of L are complete
 #pragma unroll
-    for (int e = t; e < TB * TB; e += kSolveThreads) {
+    for (int k = 0; k < TB * TB / kSolveThreads; ++k) {
+      const int e = t + kSolveThreads * k;
       const int i = e % TB, j = e / TB;
       L[i][j] = G[(o + j) * M + o + i];
     }
     __syncthreads();
     if (t < TB) {
       double zi = z[o + t];
-      for (int c = 0; c < TB; ++c) {
-        const double zc = __shfl(zi, c, 64) / L[c][c];
-        if (t == c) zi = zc;
-        else if (t > c) zi = fma(-L[t][c], zc, zi);
+      const double ri = 1.0 / L[t][t];
+      for (int c0 = 0; c0 < TB; c0 += 8) {
+        double lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lv[u] = L[t][c0 + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          // lane c's entry is final at step c; the others read it by readlane
+          const int c = c0 + u;
+          const double zc = readlane_d(zi * ri, c);
+          const double nz = fma(-lv[u], zc, zi);
+          zi = t == c ? zc : (t > c ? nz : zi);
+        }
       }
       z[o + t] = zi;
     }
     __syncthreads();
     // rows below the tile: z_i -= sum_c L_{i, o+c} z_{o+c}
-    for (int i = (int)o + TB + t; i < M; i += kSolveThreads) {
-      double acc = z[i];
-#pragma unroll 8
-      for (int c = 0; c < TB; ++c) acc = fma(-G[(o + c) * M + i], z[o + c], acc);
-      z[i] = acc;
-    }
+    for (int i = (int)o + TB + t; i < M; i += kSolveThreads)
+      z[i] = tile_dot(G, (int)o * M + i, M, z + o, z[i]);
   }
   // backward: tiles bottom to top, L^T
   for (int K = NT - 1; K >= 0; --K) {
     const int64_t o = (int64_t)K * TB;
     __syncthreads();
 #pragma unroll
-    for (int e = t; e < TB * TB; e += kSolveThreads) {
+    for (int k = 0; k < TB * TB / kSolveThreads; ++k) {
+      const int e = t + kSolveThreads * k;
       const int i = e % TB, j = e / TB;
       L[i][j] = G[(o + j) * M + o + i];
     }
     __syncthreads();
     if (t < TB) {
       double zi = z[o + t];
-      for (int c = TB - 1; c >= 0; --c) {
-        const double xc = __shfl(zi, c, 64) / L[c][c];
-        if (t == c) zi = xc;
-        else if (t < c) zi = fma(-L[c][t], xc, zi);
+      const double ri = 1.0 / L[t][t];
+      for (int c0 = TB - 8; c0 >= 0; c0 -= 8) {
+        double lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lv[u] = L[c0 + u][t];
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const int c = c0 + u;
+          const double xc = readlane_d(zi * ri, c);
+          const double nz = fma(-lv[u], xc, zi);
+          zi = t == c ? xc : (t < c ? nz : zi);
+        }
       }
       z[o + t] = zi;
     }
     __syncthreads();
     // rows above the tile: z_j -= sum_c L_{o+c, j} x_{o+c} (upper triangle)
-    for (int j = t; j < (int)o; j += kSolveThreads) {
-      double acc = z[j];
-#pragma unroll 8
-      for (int c = 0; c < TB; ++c) acc = fma(-G[(o + c) * M + j], z[o + c], acc);
-      z[j] = acc;
-    }
+    for (int j = t; j < (int)o; j += kSolveThreads)
+      z[j] = tile_dot(G, (int)o * M + j, M, z + o, z[j]);
   }
   __syncthreads();
   for (int i = t; i < m; i += kSolveThreads) x_out[i] = z[i];

@@ -225,39 +225,70 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M
   }
 }
 
+// value of lane Q of each group of four lanes, by a DPP quad permutation
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = Q | (Q << 2) | (Q << 4) | (Q << 6);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double quad_bcast(double v, int q) {
+  switch (q) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
+}
+
 // ---- tiles below the diagonal: L_IK = G_IK L_KK^{-T}, one block per tile
-// row I > K, one thread per row of the tile.
-__global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int M, int K,
+// row I > K, four threads per row of the tile: thread (r, q) holds the
+// entries x_c, c = q mod 4, of row r.  Right-looking: at step c the owner of
+// x_c divides it by L_cc, its three neighbours get it by a quad broadcast, and
+// every thread subtracts x_c L_jc from its entries j > c.  A row's four
+// threads are neighbouring lanes of one wavefront, so the steps need no
+// barrier.
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ G, int M, int K,
                                                    int32_t* info) {
-  __shared__ double L[TB][TB + 1];
+  __shared__ double Lt[TB][TB + 1];  // Lt[c][j] = L_jc
+  __shared__ double rd[TB];          // 1 / L_cc
   if (ws_failed(info)) return;
-  const int r = threadIdx.x;
+  const int t = threadIdx.x;
+  const int r = t >> 2, qd = t & 3;
   const int I = K + 1 + blockIdx.x;
   const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB;
 #pragma unroll
-  for (int k = 0; k < TB; ++k) {
-    const int e = r + 64 * k;
-    const int i = e % TB, j = e / TB;
-    L[i][j] = G[(o + j) * M + o + i];
+  for (int k = 0; k < TB * TB / 256; ++k) {
+    const int e = t + 256 * k;
+    const int j = e % TB, c = e / TB;
+    Lt[c][j] = G[(o + c) * M + o + j];
   }
-  __shared__ double rd[TB];  // 1 / L_cc
-  rd[r] = 1.0 / G[(o + r) * M + o + r];
+  if (t < TB) rd[t] = 1.0 / G[(o + t) * M + o + t];
+  double x[TB / 4];  // G_IK[r][4u + qd], then L_IK[r][4u + qd]
+#pragma unroll
+  for (int u = 0; u < TB / 4; ++u) x[u] = G[(o + 4 * u + qd) * M + oi + r];
   __syncthreads();
-  double x[TB];
-#pragma unroll
-  for (int c = 0; c < TB; ++c) x[c] = G[(o + c) * M + oi + r];
 #pragma unroll
   for (int c = 0; c < TB; ++c) {
-    // four partial sums shorten the dependent chain
-    double v[4] = {x[c], 0.0, 0.0, 0.0};
+    const int uc = c >> 2, qc = c & 3;
+    const double own = x[uc] * rd[c];  // meaningful on the owner, q = qc
+    if (qd == qc) x[uc] = own;
+    const double xc = quad_bcast(own, qc);
+    {
+      const double nv = fma(-xc, Lt[c][4 * uc + qd], x[uc]);
+      x[uc] = qd > qc ? nv : x[uc];
+    }
 #pragma unroll
-    for (int k = 0; k < c; ++k) v[k & 3] = fma(-x[k], L[c][k], v[k & 3]);
-    x[c] = ((v[0] + v[1]) + (v[2] + v[3])) * rd[c];
+    for (int u = uc + 1; u < TB / 4; ++u) x[u] = fma(-xc, Lt[c][4 * u + qd], x[u]);
+    // materialized here, as in the diagonal kernel
+#pragma unroll
+    for (int u = uc; u < TB / 4; ++u) asm volatile("" : "+v"(x[u]));
   }
 #pragma unroll
-  for (int c = 0; c < TB; ++c) {
-    G[(o + c) * M + oi + r] = x[c];
-    G[(oi + r) * M + o + c] = x[c];
+  for (int u = 0; u < TB / 4; ++u) {
+    G[(o + 4 * u + qd) * M + oi + r] = x[u];
+    G[(oi + r) * M + o + 4 * u + qd] = x[u];
   }
 }
 
@@ -276,6 +307,14 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
   const int J = K + 1 + jj, I = J + b;
   const int t = threadIdx.x;
   const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, oj = (int64_t)J * TB;
+  const int ta = t >> 4, tb = t & 15;
+  // this thread's 4 x 4 entries of G_IJ, read with the operands (a store
+  // after each read would keep the reads from overlapping)
+  double g[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[u][v] = G[(oj + tb * 4 + v) * M + oi + ta * 4 + u];
 #pragma unroll
   for (int h = 0; h < TB * TB / 256; ++h) {
     const int e = t + 256 * h;
@@ -284,7 +323,6 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
     B[i][k] = G[(o + k) * M + oj + i];
   }
   __syncthreads();
-  const int ta = t >> 4, tb = t & 15;
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -307,8 +345,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t idx = (oj + tb * 4 + v) * M + oi + ta * 4 + u;
-      G[idx] -= acc[u][v];
+      G[(oj + tb * 4 + v) * M + oi + ta * 4 + u] = g[u][v] - acc[u][v];
     }
 }
 
@@ -738,7 +775,7 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
     if (rc) return rc;
     const int T = NT - K - 1;
     if (T == 0) break;
-    hipLaunchKernelGGL(k_chol_panel, dim3(T), dim3(64), 0, s, G, M, K, info);
+    hipLaunchKernelGGL(k_chol_panel, dim3(T), dim3(256), 0, s, G, M, K, info);
     rc = ws_last("k_chol_panel");
     if (rc) return rc;
     hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, s, G, M, K, info);

@@ -36,14 +36,16 @@ constexpr int TB = 64;  // tile size
 
 __device__ __forceinline__ bool ws_failed(const int32_t* info) { return *info != 0; }
 
-// ---- Gram tiles: block (I, J), I >= J, computes G[I-tile rows][J-tile cols]
-// over all n rows; rows pass through LDS 32 at a time, the next 32 loaded into
-// registers while the current ones are used.  Padding entries get the
-// identity.
+// ---- Gram tiles: block (I, J, s), I >= J, computes G[I-tile rows][J-tile
+// cols] over the rows [s R, min(n, (s + 1) R)); rows pass through LDS 32 at a
+// time, the next 32 loaded into registers while the current ones are used.
+// With one split (gridDim.y = 1) the tile goes to G with the identity on the
+// padding; otherwise the raw partial sum goes to the split's own M x M slice
+// of out, and k_ws_gram_sum adds the slices.
 template <typename XT>
 __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64_t ldx, int n,
                                                  int p, const int32_t* __restrict__ W, int m,
-                                                 int M, double* __restrict__ G) {
+                                                 int M, int R, double* __restrict__ out) {
   constexpr int RC = 32;
   constexpr int NL = (RC * TB) / 256;  // loads per thread and operand per chunk
   __shared__ double A[RC][TB + 1], B[RC][TB + 1];
@@ -93,17 +95,18 @@ __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  load(0);
-  for (int r0 = 0; r0 < n; r0 += RC) {
+  const int rbeg = blockIdx.y * R, rend = min(n, rbeg + R);
+  load(rbeg);
+  for (int r0 = rbeg; r0 < rend; r0 += RC) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       const int e = t + 256 * i;
-      const bool in = r0 + rr[i] < n;
+      const bool in = r0 + rr[i] < rend;
       A[rr[i]][e / RC] = (oa[i] >= 0 && in) ? (double)va[i] : 0.0;
       B[rr[i]][e / RC] = (ob[i] >= 0 && in) ? (double)vb[i] : 0.0;
     }
     __syncthreads();
-    if (r0 + RC < n) load(r0 + RC);
+    if (r0 + RC < rend) load(r0 + RC);
 #pragma unroll 4
     for (int q = 0; q < RC; ++q) {
       double av[4], bv[4];
@@ -119,17 +122,46 @@ __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64
     }
     __syncthreads();
   }
+  const bool split = gridDim.y > 1;
+  double* G = out + (split ? (size_t)blockIdx.y * M * M : 0);
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ga = I * TB + ta * 4 + u, gb = J * TB + tb * 4 + v;
       double val = acc[u][v];
-      if (ga >= m || gb >= m) val = ga == gb ? 1.0 : 0.0;
+      if (!split && (ga >= m || gb >= m)) val = ga == gb ? 1.0 : 0.0;
       G[(int64_t)gb * M + ga] = val;
     }
 }
 
+// G = the sum of the S slices of P on the tiles I >= J, the identity on the
+// padding.
+__global__ void k_ws_gram_sum(const double* __restrict__ P, int S, int M, int m,
+                              double* __restrict__ G) {
+  const int64_t MM = (int64_t)M * M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MM;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % M), b = (int)(e / M);
+    if (a / TB < b / TB) continue;
+    double v;
+    if (a >= m || b >= m) {
+      v = a == b ? 1.0 : 0.0;
+    } else {
+      v = 0.0;
+      for (int k = 0; k < S; ++k) v += P[k * MM + e];
+    }
+    G[e] = v;
+  }
+}
+
+// row splits of the Gram product: enough blocks for the chip's 256 compute
+// units, at most 8, each split at least 64 rows
+int gram_splits(int NT, int n) {
+  const int ntile = NT * (NT + 1) / 2;
+  int S = std::max(1, std::min(8, 256 / ntile));
+  return std::max(1, std::min(S, n / 64));
+}
 // ---- right-hand side b_a = x_{W_a}^T y - lambda sigma_a (0 on the padding),
 // one wavefront per entry; an index outside [0, p) sets info = -1.
 template <typename XT>
@@ -734,9 +766,19 @@ int ws_last(const char* where) {
 
 }  // namespace
 
+// G (M x M), the right-hand side (M), then the Gram slices (S x M x M when
+// S > 1); the slices take the largest need of any set size up to m, so that a
+// workspace sized for a limit serves every smaller set
 size_t ws_solve_bytes(int m) {
-  const size_t M = (size_t)((m + TB - 1) / TB) * TB;
-  return (M * M + M) * sizeof(double) + 256;
+  const int NT = (m + TB - 1) / TB;
+  const size_t M = (size_t)NT * TB;
+  size_t slices = 0;
+  for (int nt = 1; nt <= NT; ++nt) {
+    const int S = gram_splits(nt, 1 << 30);
+    const size_t Mt = (size_t)nt * TB;
+    if (S > 1) slices = std::max(slices, (size_t)S * Mt * Mt);
+  }
+  return (M * M + M + slices) * sizeof(double) + 256;
 }
 
 int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y, const int32_t* W,
@@ -751,16 +793,19 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   if (rc) return rc;
   const int ntile = NT * (NT + 1) / 2;
   const int rgrid = (M + 3) / 4;
+  const int S = gram_splits(NT, n);
+  const int R = ((n + S - 1) / S + 31) / 32 * 32;  // rows per split, whole chunks of 32
+  double* gout = S > 1 ? rhs + M : G;
   if (dtype == GS_F32) {
-    hipLaunchKernelGGL(k_ws_gram<float>, dim3(ntile), dim3(256), 0, s,
-                       static_cast<const float*>(X), ldx, n, p, W, m, M, G);
+    hipLaunchKernelGGL(k_ws_gram<float>, dim3(ntile, S), dim3(256), 0, s,
+                       static_cast<const float*>(X), ldx, n, p, W, m, M, R, gout);
     rc = ws_last("k_ws_gram");
     if (rc) return rc;
     hipLaunchKernelGGL(k_ws_rhs<float>, dim3(rgrid), dim3(256), 0, s, static_cast<const float*>(X),
                        ldx, n, p, static_cast<const float*>(y), W, sigma, m, M, lambda, rhs, info);
   } else {
-    hipLaunchKernelGGL(k_ws_gram<double>, dim3(ntile), dim3(256), 0, s,
-                       static_cast<const double*>(X), ldx, n, p, W, m, M, G);
+    hipLaunchKernelGGL(k_ws_gram<double>, dim3(ntile, S), dim3(256), 0, s,
+                       static_cast<const double*>(X), ldx, n, p, W, m, M, R, gout);
     rc = ws_last("k_ws_gram");
     if (rc) return rc;
     hipLaunchKernelGGL(k_ws_rhs<double>, dim3(rgrid), dim3(256), 0, s,
@@ -769,6 +814,13 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   }
   rc = ws_last("k_ws_rhs");
   if (rc) return rc;
+  if (S > 1) {
+    const int64_t MM = (int64_t)M * M;
+    const int sgrid = (int)std::min<int64_t>((MM + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_ws_gram_sum, dim3(sgrid), dim3(256), 0, s, gout, S, M, m, G);
+    rc = ws_last("k_ws_gram_sum");
+    if (rc) return rc;
+  }
   for (int K = 0; K < NT; ++K) {
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, G, M, K, info);
     rc = ws_last("k_chol_diag");

@@ -26,6 +26,8 @@ LIB_PATH = os.path.join(_HERE, "libgapsafe.so")
 GS_F32, GS_F64 = 0, 1
 GS_OK, GS_NOT_CONVERGED = 0, 1
 GS_EINVAL, GS_EHIP, GS_EWORKSPACE, GS_EUNSUPPORTED, GS_ETOOLARGE = -1, -2, -3, -4, -5
+# the learned start's working-set limits (header enum)
+GS_WS_ROUNDS, GS_WS_ADD, GS_WS_DROPS, GS_WS_MAX = 4, 32, 4, 2047
 NOALLOC_SCRATCH_BYTES = 16 << 20  # GS_NOALLOC_SCRATCH_BYTES
 SCHEDULES = {"auto": 0, "narrow": 1, "wide": 2}
 CD_MODES = {"auto": 0, "residual": 1}

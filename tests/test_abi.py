@@ -269,3 +269,23 @@ def test_learned_warm_start_argument_checks(lib):
     big = _prob(n=4096, ldx=4096)
     assert lib.lasso_path_learned(ctypes.byref(big), ctypes.byref(o), fake, 50, None, fake,
                                   1 << 40, None) == gs.GS_EUNSUPPORTED
+
+
+def test_restricted_solve_workspace_size(lib):
+    """The restricted solve's workspace: 0 outside 1 <= m <= GS_WS_MAX, at
+    least the 8 M^2 bytes of the matrix (M = m rounded up to 64), at most
+    15 MB more (the row-split partial Gram sums), and never smaller for a
+    larger m -- the learned driver sizes one workspace for its largest
+    working set and runs every smaller solve in it."""
+    hdr = open(os.path.join(ROOT, "include", "gapsafe.h")).read()
+    for name in ("GS_WS_ROUNDS", "GS_WS_ADD", "GS_WS_DROPS", "GS_WS_MAX"):
+        assert re.search(r"\b%s = (\d+)" % name, hdr).group(1) == str(getattr(gs, name)), name
+    assert lib.gs_restricted_solve_workspace_size(0) == 0
+    assert lib.gs_restricted_solve_workspace_size(gs.GS_WS_MAX + 1) == 0
+    prev = 0
+    for m in range(1, gs.GS_WS_MAX + 1):
+        need = lib.gs_restricted_solve_workspace_size(m)
+        M = (m + 63) // 64 * 64
+        assert 8 * M * M <= need <= 8 * (M * M + M) + 15_000_000 + 256, m
+        assert need >= prev, m
+        prev = need

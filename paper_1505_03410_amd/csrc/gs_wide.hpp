@@ -32,6 +32,7 @@ constexpr int kSweepU = GS_SWEEP_U;
 constexpr int kTestTile = 2048;     // entries per test/compact block
 constexpr int kRefreshThreads = 1024;
 constexpr int kRefreshBatch = 8;    // rows of 64 positions per refresh scan step
+constexpr int kRefreshLoads = 32;   // column loads in flight per thread of the refresh
 constexpr int kMaxRowsDense = 2048; // largest n of a dense design on these kernels
 
 struct WideBufs {
@@ -321,7 +322,8 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
   __threadfence_block();
   // rho_i = y_i - sum_e beta_e x_{j_e, i} in ascending e, one thread per row;
   // the list passes through LDS a tile at a time and each thread keeps
-  // eight column loads in flight.
+  // kRefreshLoads column loads in flight (the one block's sum is a chain of
+  // load latencies, nnz / kRefreshLoads of them).
   constexpr int RT = (kMaxRowsDense + kRefreshThreads - 1) / kRefreshThreads;
   constexpr int TILE = kRefreshThreads;
   __shared__ int s_ix[TILE];
@@ -349,13 +351,14 @@ __global__ __launch_bounds__(kRefreshThreads) void k_wide_refresh(ProbDesc d, Wi
     for (int t = 0; t < RT; ++t) {
       if (threadIdx.x + t * kRefreshThreads >= d.n) continue;
       const XT* Xr = X + rr[t];
+      constexpr int NL = kRefreshLoads;
       int e = 0;
-      for (; e + 8 <= ne; e += 8) {
-        XT xv[8];
+      for (; e + NL <= ne; e += NL) {
+        XT xv[NL];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xv[u] = Xr[(int64_t)s_ix[e + u] * d.ldx];
+        for (int u = 0; u < NL; ++u) xv[u] = Xr[(int64_t)s_ix[e + u] * d.ldx];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[t] = fma(-s_v[e + u], (double)xv[u], v[t]);
+        for (int u = 0; u < NL; ++u) v[t] = fma(-s_v[e + u], (double)xv[u], v[t]);
       }
       for (; e < ne; ++e) v[t] = fma(-s_v[e], (double)Xr[(int64_t)s_ix[e] * d.ldx], v[t]);
     }

@@ -494,6 +494,44 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
 // conditions at beta_prev (|c_j| > lambda, c indexed by column) and whose
 // support logit o1 > taus[i], i < kWsTaus.
 constexpr int kWsTaus = 7;
+// chunks of 1024 positions per step of the single-block scans below: their
+// loads are issued together, so a step costs one or two memory latencies
+constexpr int kWsScan = 8;
+static_assert(kWsScan * 16 == 128, "two table entries per lane");
+// inclusive prefix sum over the 64 lanes of a wavefront
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(v, d, 64);
+    v += lane >= d ? o : 0;
+  }
+  return v;
+}
+// ordered compaction of those scans: with the kept count of every wave x and
+// chunk u in wc[u][x] (after a barrier), off[u] = base plus everything kept
+// before wave w's part of chunk u; returns base plus everything kept.  Each
+// wavefront scans the 128 counts in (u, x) order itself, two per lane.
+__device__ __forceinline__ int ws_chunk_offs(const int (*wc)[16], int w, int base,
+                                             int (&off)[kWsScan]) {
+  const int lane = threadIdx.x & 63;
+  const int v0 = wc[lane >> 4][lane & 15], v1 = wc[4 + (lane >> 4)][lane & 15];
+  const int s0 = wave_incl_scan(v0), s1 = wave_incl_scan(v1);
+  const int t0 = __builtin_amdgcn_readlane(s0, 63), t1 = __builtin_amdgcn_readlane(s1, 63);
+  const int e0 = s0 - v0, e1 = t0 + s1 - v1;  // exclusive prefixes
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+#pragma unroll
+  for (int u = 0; u < kWsScan; ++u) {
+    const int e = u * 16 + wu;
+    off[u] = base + (u < 4 ? __builtin_amdgcn_readlane(e0, e) : __builtin_amdgcn_readlane(e1, e - 64));
+  }
+  return base + t0 + t1;
+}
+// sum of the 128 entries of such a table, by every wavefront
+__device__ __forceinline__ int ws_table_sum(const int (*tb)[16]) {
+  const int lane = threadIdx.x & 63;
+  return wave_sum_i(tb[lane >> 4][lane & 15] + tb[4 + (lane >> 4)][lane & 15]);
+}
 struct WsTaus {
   float v[kWsTaus];
 };
@@ -507,14 +545,33 @@ __global__ __launch_bounds__(1024) void k_ws_count(const float* __restrict__ out
   if (t <= kWsTaus) acc[t] = 0;
   __syncthreads();
   int loc[1 + kWsTaus] = {};
-  for (int k = t; k < q; k += 1024) {
-    const int j = act[k];
-    if (bprev && bprev[j] != 0.0) {
-      ++loc[0];
-    } else if (fabs(c[j]) > lambda) {
-      const float o1 = out[2 * (int64_t)j + 1];
+  for (int base = 0; base < q; base += 1024 * kWsScan) {
+    // every load of the step issued before the first is used (positions
+    // past the end clamped to the last one and not counted)
+    int jv[kWsScan];
+    double bp[kWsScan], cj[kWsScan];
+    float o1[kWsScan];
 #pragma unroll
-      for (int i = 0; i < kWsTaus; ++i) loc[1 + i] += o1 > taus.v[i] ? 1 : 0;
+    for (int u = 0; u < kWsScan; ++u) jv[u] = act[min(base + 1024 * u + t, q - 1)];
+    // without a previous point the load reads c (a valid column-indexed
+    // array) and the value is discarded: no branch between the loads
+    const double* bsrc = bprev ? bprev : c;
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      const double bl = bsrc[jv[u]];
+      bp[u] = bprev ? bl : 0.0;
+      cj[u] = c[jv[u]];
+      o1[u] = out[2 * (int64_t)jv[u] + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      if (base + 1024 * u + t >= q) continue;
+      if (bp[u] != 0.0) {
+        ++loc[0];
+      } else if (fabs(cj[u]) > lambda) {
+#pragma unroll
+        for (int i = 0; i < kWsTaus; ++i) loc[1 + i] += o1[u] > taus.v[i] ? 1 : 0;
+      }
     }
   }
 #pragma unroll
@@ -538,43 +595,70 @@ __global__ __launch_bounds__(1024) void k_ws_select(const float* __restrict__ ou
                                                     double* __restrict__ sigma,
                                                     int32_t* __restrict__ mark,
                                                     int32_t* __restrict__ cnt) {
-  __shared__ int wc[16];
-  __shared__ int nw[16];
+  __shared__ int wc[kWsScan][16];
+  __shared__ int nw[kWsScan][16];
+  // the selection is staged here and written out after the scan: a global
+  // store in the loop would have to complete before each barrier
+  __shared__ int32_t sW[kWsMaxSet];
+  __shared__ double sS[kWsMaxSet];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  cap = min(cap, kWsMaxSet);
   int base_off = 0, new_tot = 0;
-  for (int base = 0; base < q; base += 1024) {
-    const int k = base + t;
-    int j = 0;
-    bool in = false, fresh = false;
-    if (k < q) {
-      j = act[k];
-      const bool prev = bprev && bprev[j] != 0.0;
-      fresh = !prev && fabs(c[j]) > lambda && out[2 * (int64_t)j + 1] > tau;
-      in = prev || fresh;
+  for (int base = 0; base < q; base += 1024 * kWsScan) {
+    int jv[kWsScan];
+    double bp[kWsScan], cj[kWsScan];
+    float o1[kWsScan];
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) jv[u] = act[min(base + 1024 * u + t, q - 1)];
+    // without a previous point the load reads c (a valid column-indexed
+    // array) and the value is discarded: no branch between the loads
+    const double* bsrc = bprev ? bprev : c;
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      const double bl = bsrc[jv[u]];
+      bp[u] = bprev ? bl : 0.0;
+      cj[u] = c[jv[u]];
+      o1[u] = out[2 * (int64_t)jv[u] + 1];
     }
-    const uint64_t fm = ballot(fresh);
-    if (lane == 0) nw[w] = __popcll(fm);
-    const uint64_t m = ballot(in);
-    if (lane == 0) wc[w] = __popcll(m);
-    __syncthreads();
-    int off = base_off, tot = 0;
-    for (int v = 0; v < 16; ++v) {
-      if (v < w) off += wc[v];
-      tot += wc[v];
-      new_tot += nw[v];
-    }
-    if (in) {
-      const int pos = off + __popcll(m & lt);
-      if (pos < cap) {
-        W[pos] = j;
-        const double bp = bprev ? bprev[j] : 0.0;
-        sigma[pos] = bp != 0.0 ? (bp > 0.0 ? 1.0 : -1.0) : (c[j] >= 0.0 ? 1.0 : -1.0);
-        mark[j] = 1;
+    bool in[kWsScan];
+    uint64_t m[kWsScan];
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      const bool v = base + 1024 * u + t < q;
+      const bool prev = v && bp[u] != 0.0;
+      const bool fresh = v && !prev && fabs(cj[u]) > lambda && o1[u] > tau;
+      in[u] = prev || fresh;
+      const uint64_t fm = ballot(fresh);
+      m[u] = ballot(in[u]);
+      if (lane == 0) {
+        nw[u][w] = __popcll(fm);
+        wc[u][w] = __popcll(m[u]);
       }
     }
-    base_off += tot;
     __syncthreads();
+    int off[kWsScan];
+    const int next_off = ws_chunk_offs(wc, w, base_off, off);
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      if (in[u]) {
+        const int pos = off[u] + __popcll(m[u] & lt);
+        if (pos < cap) {
+          sW[pos] = jv[u];
+          sS[pos] = bp[u] != 0.0 ? (bp[u] > 0.0 ? 1.0 : -1.0) : (cj[u] >= 0.0 ? 1.0 : -1.0);
+        }
+      }
+    }
+    base_off = next_off;
+    new_tot += ws_table_sum(nw);
+    __syncthreads();
+  }
+  const int ns = min(base_off, cap);
+  for (int a = t; a < ns; a += 1024) {
+    const int j = sW[a];
+    W[a] = j;
+    sigma[a] = sS[a];
+    mark[j] = 1;
   }
   if (t == 0) {
     cnt[0] = base_off;  // may exceed cap: the caller checks
@@ -655,7 +739,7 @@ __global__ __launch_bounds__(1024) void k_ws_add(const int32_t* __restrict__ act
                                                  double* __restrict__ sigma,
                                                  int32_t* __restrict__ mark,
                                                  int32_t* __restrict__ cnt) {
-  __shared__ int wc[16];
+  __shared__ int wc[kWsScan][16];
   __shared__ double sv[kWsCand];
   __shared__ int32_t sk[kWsCand];
   __shared__ double rv[16];
@@ -663,31 +747,41 @@ __global__ __launch_bounds__(1024) void k_ws_add(const int32_t* __restrict__ act
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int nc = 0;
-  for (int base = 0; base < q && nc < kWsCand; base += 1024) {
-    const int k = base + t;
-    double v = 0.0;
-    bool f = false;
-    if (k < q) {
-      const int j = act[k];
-      v = fabs(c[k]) - lambda;
-      f = v > 0.0 && mark[j] == 0;
+  for (int base = 0; base < q && nc < kWsCand; base += 1024 * kWsScan) {
+    int jv[kWsScan], mk[kWsScan];
+    double cv[kWsScan];
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      const int kk = min(base + 1024 * u + t, q - 1);
+      jv[u] = act[kk];
+      cv[u] = c[kk];
     }
-    const uint64_t msk = ballot(f);
-    if (lane == 0) wc[w] = __popcll(msk);
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) mk[u] = mark[jv[u]];
+    bool f[kWsScan];
+    double v[kWsScan];
+    uint64_t msk[kWsScan];
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      v[u] = fabs(cv[u]) - lambda;
+      f[u] = base + 1024 * u + t < q && v[u] > 0.0 && mk[u] == 0;
+      msk[u] = ballot(f[u]);
+      if (lane == 0) wc[u][w] = __popcll(msk[u]);
+    }
     __syncthreads();
-    int off = nc, tot = 0;
-    for (int u = 0; u < 16; ++u) {
-      if (u < w) off += wc[u];
-      tot += wc[u];
-    }
-    if (f) {
-      const int pos = off + __popcll(msk & lt);
-      if (pos < kWsCand) {
-        sv[pos] = v;
-        sk[pos] = k;
+    int off[kWsScan];
+    const int next_nc = ws_chunk_offs(wc, w, nc, off);
+#pragma unroll
+    for (int u = 0; u < kWsScan; ++u) {
+      if (f[u]) {
+        const int pos = off[u] + __popcll(msk[u] & lt);
+        if (pos < kWsCand) {
+          sv[pos] = v[u];
+          sk[pos] = base + 1024 * u + t;
+        }
       }
     }
-    nc = min(kWsCand, nc + tot);
+    nc = min(kWsCand, next_nc);
     __syncthreads();
   }
   int m = cnt[0];

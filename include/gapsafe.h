@@ -490,9 +490,9 @@ int lasso_path_learned(const gs_problem* prob, const gs_opts* opts, const float*
  * b_out [device] m doubles; info_out [device] 1 int32: 0 on success, k >= 1
  * when the k-th pivot was not a positive normal number (X_W numerically rank
  * deficient; b_out is then not written), -1 for an index of W outside [0, p).
- * workspace: gs_restricted_solve_workspace_size(m) bytes (8 M^2 for the
- * matrix, M = m rounded up to 64, plus at most 15 MB of partial sums of the
- * Gram product split over rows), or
+ * workspace: gs_restricted_solve_workspace_size(m) bytes (8 M (M + 64) for
+ * the matrix and its right-hand-side tile row, M = m rounded up to 64, plus
+ * at most 15 MB of partial sums of the Gram product split over rows), or
  * 0 for an m out of range.  Asynchronous on `stream`.  GS_EINVAL for a bad
  * size, pointer or value, GS_EWORKSPACE for a small workspace. */
 size_t gs_restricted_solve_workspace_size(int32_t m);

@@ -9,10 +9,14 @@
 // Cholesky factorization (64 x 64 tiles): the Gram matrix of W (products of
 // the stored values, exact in FP64), then per tile column a factorization of
 // the diagonal tile, a triangular solve of the tiles below it and an update of
-// the trailing tiles, then two triangular solves.  The matrix is M x M column
-// major with M = m rounded up to 64 and the identity on the padding; the
-// factor L lives in the lower triangle and its transpose is mirrored into the
-// upper triangle so that both triangular solves read columns.
+// the trailing tiles, then the backward triangular solve.  The matrix is M x M
+// with M = m rounded up to 64 and the identity on the padding, stored column
+// major with M + 64 rows: the right-hand side b is row M (rows M + 1 .. M + 63
+// are zero), an extra tile row that the factorization treats like the others,
+// so that it leaves z = L^{-1} b in that row (the forward substitution comes
+// with the panel and update steps).  The factor L lives in the lower triangle
+// and its transpose is mirrored into the upper triangle so that the backward
+// solve reads columns.
 //
 // Around it, the working-set kernels of the learned path driver: the initial
 // set from the network's support logits, dropping coordinates whose sign
@@ -124,6 +128,7 @@ __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64
   }
   const bool split = gridDim.y > 1;
   double* G = out + (split ? (size_t)blockIdx.y * M * M : 0);
+  const int64_t ldo = split ? M : M + TB;  // slices are M x M, G has M + 64 rows
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -131,12 +136,12 @@ __global__ __launch_bounds__(256) void k_ws_gram(const XT* __restrict__ X, int64
       const int ga = I * TB + ta * 4 + u, gb = J * TB + tb * 4 + v;
       double val = acc[u][v];
       if (!split && (ga >= m || gb >= m)) val = ga == gb ? 1.0 : 0.0;
-      G[(int64_t)gb * M + ga] = val;
+      G[gb * ldo + ga] = val;
     }
 }
 
-// G = the sum of the S slices of P on the tiles I >= J, the identity on the
-// padding.
+// G (M + 64 rows) = the sum of the S slices of P (M x M each) on the tiles
+// I >= J, the identity on the padding.
 __global__ void k_ws_gram_sum(const double* __restrict__ P, int S, int M, int m,
                               double* __restrict__ G) {
   const int64_t MM = (int64_t)M * M;
@@ -151,7 +156,7 @@ __global__ void k_ws_gram_sum(const double* __restrict__ P, int S, int M, int m,
       v = 0.0;
       for (int k = 0; k < S; ++k) v += P[k * MM + e];
     }
-    G[e] = v;
+    G[(int64_t)b * (M + TB) + a] = v;
   }
 }
 
@@ -162,20 +167,23 @@ int gram_splits(int NT, int n) {
   int S = std::max(1, std::min(8, 256 / ntile));
   return std::max(1, std::min(S, n / 64));
 }
-// ---- right-hand side b_a = x_{W_a}^T y - lambda sigma_a (0 on the padding),
-// one wavefront per entry; an index outside [0, p) sets info = -1.
+// ---- right-hand side b_a = x_{W_a}^T y - lambda sigma_a (0 on the padding)
+// into row M of G, with rows M + 1 .. M + 63 of column a set to zero; one
+// wavefront per entry; an index outside [0, p) sets info = -1.
 template <typename XT>
 __global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_t ldx, int n, int p,
                                                 const XT* __restrict__ y,
                                                 const int32_t* __restrict__ W,
                                                 const double* __restrict__ sigma, int m, int M,
-                                                double lambda, double* __restrict__ b,
+                                                double lambda, double* __restrict__ G,
                                                 int32_t* info) {
   const int lane = threadIdx.x & 63;
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (a >= M) return;
+  double* b = G + (int64_t)a * (M + TB) + M;  // rows M .. M + 63 of column a
+  if (lane > 0) b[lane] = 0.0;
   if (a >= m) {
-    if (lane == 0) b[a] = 0.0;
+    if (lane == 0) b[0] = 0.0;
     return;
   }
   const int j0 = W[a];
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(256) void k_ws_rhs(const XT* __restrict__ X, int64_
   double s = 0.0;
   for (int i = lane; i < n; i += 64) s = fma((double)col[i], (double)y[i], s);
   s = wave_sum(s);
-  if (lane == 0) b[a] = s - lambda * sigma[a];
+  if (lane == 0) b[0] = s - lambda * sigma[a];
 }
 
 // ---- factorization of the diagonal tile K (unblocked, right-looking) by 256
@@ -206,12 +214,12 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M
   if (ws_failed(info)) return;
   const int t = threadIdx.x;
   const int i = t >> 2, qd = t & 3;
-  const int64_t o = (int64_t)K * TB;
+  const int64_t o = (int64_t)K * TB, ld = M + TB;
   double a[TB / 4];   // T_{i, 4u + qd}
   double pv[TB / 4];  // the unscaled pivot T_jj of each column j = 4u + qd
 #pragma unroll
   for (int u = 0; u < TB / 4; ++u) {
-    a[u] = G[(o + 4 * u + qd) * M + o + i];
+    a[u] = G[(o + 4 * u + qd) * ld + o + i];
     pv[u] = 1.0;
   }
 #pragma unroll
@@ -251,8 +259,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int M
     if (i >= j) {
       const double d = sqrt(pv[u]);
       const double v = i == j ? d : a[u] / d;
-      G[(o + j) * M + o + i] = v;
-      G[(o + i) * M + o + j] = v;
+      G[(o + j) * ld + o + i] = v;
+      G[(o + i) * ld + o + j] = v;
     }
   }
 }
@@ -275,7 +283,8 @@ __device__ __forceinline__ double quad_bcast(double v, int q) {
 }
 
 // ---- tiles below the diagonal: L_IK = G_IK L_KK^{-T}, one block per tile
-// row I > K, four threads per row of the tile: thread (r, q) holds the
+// row I > K up to the right-hand side's tile row I = M / 64 (which has no
+// mirror in the upper triangle), four threads per row of the tile: thread (r, q) holds the
 // entries x_c, c = q mod 4, of row r.  Right-looking: at step c the owner of
 // x_c divides it by L_cc, its three neighbours get it by a quad broadcast, and
 // every thread subtracts x_c L_jc from its entries j > c.  A row's four
@@ -289,17 +298,18 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ G, int 
   const int t = threadIdx.x;
   const int r = t >> 2, qd = t & 3;
   const int I = K + 1 + blockIdx.x;
-  const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB;
+  const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, ld = M + TB;
+  const bool mirror = oi < M;
 #pragma unroll
   for (int k = 0; k < TB * TB / 256; ++k) {
     const int e = t + 256 * k;
     const int j = e % TB, c = e / TB;
-    Lt[c][j] = G[(o + c) * M + o + j];
+    Lt[c][j] = G[(o + c) * ld + o + j];
   }
-  if (t < TB) rd[t] = 1.0 / G[(o + t) * M + o + t];
+  if (t < TB) rd[t] = 1.0 / G[(o + t) * ld + o + t];
   double x[TB / 4];  // G_IK[r][4u + qd], then L_IK[r][4u + qd]
 #pragma unroll
-  for (int u = 0; u < TB / 4; ++u) x[u] = G[(o + 4 * u + qd) * M + oi + r];
+  for (int u = 0; u < TB / 4; ++u) x[u] = G[(o + 4 * u + qd) * ld + oi + r];
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < TB; ++c) {
@@ -319,26 +329,34 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ G, int 
   }
 #pragma unroll
   for (int u = 0; u < TB / 4; ++u) {
-    G[(o + 4 * u + qd) * M + oi + r] = x[u];
-    G[(oi + r) * M + o + 4 * u + qd] = x[u];
+    G[(o + 4 * u + qd) * ld + oi + r] = x[u];
+    if (mirror) G[(oi + r) * ld + o + 4 * u + qd] = x[u];
   }
 }
 
-// ---- trailing update G_IJ -= L_IK L_JK^T for K < J <= I, one block per tile.
+// ---- trailing update G_IJ -= L_IK L_JK^T for K < J <= I < M / 64, one block
+// per tile, then the right-hand side's tiles I = M / 64, K < J < M / 64.
 __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int M, int K,
                                                      int32_t* info) {
   __shared__ double A[TB][TB + 1], B[TB][TB + 1];
   if (ws_failed(info)) return;
   const int NT = M / TB;
   const int T = NT - K - 1;
-  int b = blockIdx.x, jj = 0;
-  while (b >= T - jj) {
-    b -= T - jj;
-    ++jj;
+  int b = blockIdx.x, I, J;
+  if (b >= T * (T + 1) / 2) {
+    I = NT;
+    J = K + 1 + (b - T * (T + 1) / 2);
+  } else {
+    int jj = 0;
+    while (b >= T - jj) {
+      b -= T - jj;
+      ++jj;
+    }
+    J = K + 1 + jj;
+    I = J + b;
   }
-  const int J = K + 1 + jj, I = J + b;
   const int t = threadIdx.x;
-  const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, oj = (int64_t)J * TB;
+  const int64_t o = (int64_t)K * TB, oi = (int64_t)I * TB, oj = (int64_t)J * TB, ld = M + TB;
   const int ta = t >> 4, tb = t & 15;
   // this thread's 4 x 4 entries of G_IJ, read with the operands (a store
   // after each read would keep the reads from overlapping)
@@ -346,13 +364,13 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) g[u][v] = G[(oj + tb * 4 + v) * M + oi + ta * 4 + u];
+    for (int v = 0; v < 4; ++v) g[u][v] = G[(oj + tb * 4 + v) * ld + oi + ta * 4 + u];
 #pragma unroll
   for (int h = 0; h < TB * TB / 256; ++h) {
     const int e = t + 256 * h;
     const int i = e % TB, k = e / TB;
-    A[i][k] = G[(o + k) * M + oi + i];
-    B[i][k] = G[(o + k) * M + oj + i];
+    A[i][k] = G[(o + k) * ld + oi + i];
+    B[i][k] = G[(o + k) * ld + oj + i];
   }
   __syncthreads();
   double acc[4][4];
@@ -377,28 +395,27 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      G[(oj + tb * 4 + v) * M + oi + ta * 4 + u] = g[u][v] - acc[u][v];
+      G[(oj + tb * 4 + v) * ld + oi + ta * 4 + u] = g[u][v] - acc[u][v];
     }
 }
 
-// ---- L z = b, then L^T x = z, one block; x_out gets the first m entries.
-// Blocked by tiles of 64: the diagonal tile's 64 steps run on wavefront 0
-// (lane i owns entry i of the tile, the tile of L in LDS), then every thread
-// applies the tile's columns to the entries below (forward) or above
-// (backward) it.  L_ic for i > c is column c of the lower triangle, and L_cj
-// for j < c column c of the mirrored upper triangle, so both sweeps read
-// columns.
+// ---- L^T x = z, one block, with z = L^{-1} b left in row M by the
+// factorization; x_out gets the first m entries.  Blocked by tiles of 64,
+// bottom to top: the diagonal tile's 64 steps run on wavefront 0 (lane i owns
+// entry i of the tile, the tile of L in LDS), then every thread applies the
+// tile's columns to the entries above it.  L_cj for j < c is column c of the
+// mirrored upper triangle, so the sweep reads columns.
 constexpr int kSolveThreads = 1024;
-// acc - sum_c G[g + c M] zt[c] over the 64 entries c of a tile, the loads of
-// G issued 16 at a time ahead of their use (G holds at most 2048^2 entries,
-// so 32-bit indices)
-__device__ __forceinline__ double tile_dot(const double* __restrict__ G, int g, int M,
+// acc - sum_c G[g + c ld] zt[c] over the 64 entries c of a tile, the loads of
+// G issued 16 at a time ahead of their use (G holds at most 2048 x 2112
+// entries, so 32-bit indices)
+__device__ __forceinline__ double tile_dot(const double* __restrict__ G, int g, int ld,
                                            const double* zt, double acc) {
 #pragma unroll
   for (int h = 0; h < TB; h += 16) {
     double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = G[g + (h + u) * M];
+    for (int u = 0; u < 16; ++u) v[u] = G[g + (h + u) * ld];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc = fma(-v[u], zt[h + u], acc);
@@ -406,7 +423,6 @@ __device__ __forceinline__ double tile_dot(const double* __restrict__ G, int g, 
   return acc;
 }
 __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __restrict__ G, int M,
-                                                              const double* __restrict__ b,
                                                               int m, double* __restrict__ x_out,
                                                               int32_t* info) {
   __shared__ double z[2048];
@@ -414,50 +430,16 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
   if (ws_failed(info)) return;
   const int t = threadIdx.x;
   const int NT = M / TB;
-  for (int i = t; i < M; i += kSolveThreads) z[i] = b[i];
-  // forward: tiles top to bottom
-  for (int K = 0; K < NT; ++K) {
+  const int ld = M + TB;
+  for (int i = t; i < M; i += kSolveThreads) z[i] = G[(int64_t)i * ld + M];
+  for (int K = NT - 1; K >= 0; --K) {
     const int64_t o = (int64_t)K * TB;
     __syncthreads();  // z and the previous tile's use of L are complete
 #pragma unroll
     for (int k = 0; k < TB * TB / kSolveThreads; ++k) {
       const int e = t + kSolveThreads * k;
       const int i = e % TB, j = e / TB;
-      L[i][j] = G[(o + j) * M + o + i];
-    }
-    __syncthreads();
-    if (t < TB) {
-      double zi = z[o + t];
-      const double ri = 1.0 / L[t][t];
-      for (int c0 = 0; c0 < TB; c0 += 8) {
-        double lv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) lv[u] = L[t][c0 + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          // lane c's entry is final at step c; the others read it by readlane
-          const int c = c0 + u;
-          const double zc = readlane_d(zi * ri, c);
-          const double nz = fma(-lv[u], zc, zi);
-          zi = t == c ? zc : (t > c ? nz : zi);
-        }
-      }
-      z[o + t] = zi;
-    }
-    __syncthreads();
-    // rows below the tile: z_i -= sum_c L_{i, o+c} z_{o+c}
-    for (int i = (int)o + TB + t; i < M; i += kSolveThreads)
-      z[i] = tile_dot(G, (int)o * M + i, M, z + o, z[i]);
-  }
-  // backward: tiles bottom to top, L^T
-  for (int K = NT - 1; K >= 0; --K) {
-    const int64_t o = (int64_t)K * TB;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < TB * TB / kSolveThreads; ++k) {
-      const int e = t + kSolveThreads * k;
-      const int i = e % TB, j = e / TB;
-      L[i][j] = G[(o + j) * M + o + i];
+      L[i][j] = G[(o + j) * ld + o + i];
     }
     __syncthreads();
     if (t < TB) {
@@ -469,6 +451,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
         for (int u = 0; u < 8; ++u) lv[u] = L[c0 + u][t];
 #pragma unroll
         for (int u = 7; u >= 0; --u) {
+          // lane c's entry is final at step c; the others read it by readlane
           const int c = c0 + u;
           const double xc = readlane_d(zi * ri, c);
           const double nz = fma(-lv[u], xc, zi);
@@ -480,7 +463,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol_solve(const double* __re
     __syncthreads();
     // rows above the tile: z_j -= sum_c L_{o+c, j} x_{o+c} (upper triangle)
     for (int j = t; j < (int)o; j += kSolveThreads)
-      z[j] = tile_dot(G, (int)o * M + j, M, z + o, z[j]);
+      z[j] = tile_dot(G, (int)o * ld + j, ld, z + o, z[j]);
   }
   __syncthreads();
   for (int i = t; i < m; i += kSolveThreads) x_out[i] = z[i];
@@ -860,9 +843,9 @@ int ws_last(const char* where) {
 
 }  // namespace
 
-// G (M x M), the right-hand side (M), then the Gram slices (S x M x M when
-// S > 1); the slices take the largest need of any set size up to m, so that a
-// workspace sized for a limit serves every smaller set
+// G with its right-hand-side tile row ((M + 64) x M), then the Gram slices
+// (S x M x M when S > 1); the slices take the largest need of any set size up
+// to m, so that a workspace sized for a limit serves every smaller set
 size_t ws_solve_bytes(int m) {
   const int NT = (m + TB - 1) / TB;
   const size_t M = (size_t)NT * TB;
@@ -872,7 +855,7 @@ size_t ws_solve_bytes(int m) {
     const size_t Mt = (size_t)nt * TB;
     if (S > 1) slices = std::max(slices, (size_t)S * Mt * Mt);
   }
-  return (M * M + M + slices) * sizeof(double) + 256;
+  return ((M + TB) * M + slices) * sizeof(double) + 256;
 }
 
 int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y, const int32_t* W,
@@ -881,7 +864,7 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   const int M = (m + TB - 1) / TB * TB;
   const int NT = M / TB;
   double* G = static_cast<double*>(workspace);
-  double* rhs = G + (size_t)M * M;
+  double* gend = G + (size_t)(M + TB) * M;
   hipLaunchKernelGGL(k_ws_info0, dim3(1), dim3(64), 0, s, info);
   int rc = ws_last("k_ws_info0");
   if (rc) return rc;
@@ -889,14 +872,14 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
   const int rgrid = (M + 3) / 4;
   const int S = gram_splits(NT, n);
   const int R = ((n + S - 1) / S + 31) / 32 * 32;  // rows per split, whole chunks of 32
-  double* gout = S > 1 ? rhs + M : G;
+  double* gout = S > 1 ? gend : G;
   if (dtype == GS_F32) {
     hipLaunchKernelGGL(k_ws_gram<float>, dim3(ntile, S), dim3(256), 0, s,
                        static_cast<const float*>(X), ldx, n, p, W, m, M, R, gout);
     rc = ws_last("k_ws_gram");
     if (rc) return rc;
     hipLaunchKernelGGL(k_ws_rhs<float>, dim3(rgrid), dim3(256), 0, s, static_cast<const float*>(X),
-                       ldx, n, p, static_cast<const float*>(y), W, sigma, m, M, lambda, rhs, info);
+                       ldx, n, p, static_cast<const float*>(y), W, sigma, m, M, lambda, G, info);
   } else {
     hipLaunchKernelGGL(k_ws_gram<double>, dim3(ntile, S), dim3(256), 0, s,
                        static_cast<const double*>(X), ldx, n, p, W, m, M, R, gout);
@@ -904,7 +887,7 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
     if (rc) return rc;
     hipLaunchKernelGGL(k_ws_rhs<double>, dim3(rgrid), dim3(256), 0, s,
                        static_cast<const double*>(X), ldx, n, p, static_cast<const double*>(y), W,
-                       sigma, m, M, lambda, rhs, info);
+                       sigma, m, M, lambda, G, info);
   }
   rc = ws_last("k_ws_rhs");
   if (rc) return rc;
@@ -919,16 +902,17 @@ int ws_solve(int n, int p, int64_t ldx, int dtype, const void* X, const void* y,
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, G, M, K, info);
     rc = ws_last("k_chol_diag");
     if (rc) return rc;
+    // the tile rows below K, the right-hand side's included
     const int T = NT - K - 1;
-    if (T == 0) break;
-    hipLaunchKernelGGL(k_chol_panel, dim3(T), dim3(256), 0, s, G, M, K, info);
+    hipLaunchKernelGGL(k_chol_panel, dim3(T + 1), dim3(256), 0, s, G, M, K, info);
     rc = ws_last("k_chol_panel");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, s, G, M, K, info);
+    if (T == 0) break;
+    hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2 + T), dim3(256), 0, s, G, M, K, info);
     rc = ws_last("k_chol_update");
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kSolveThreads), 0, s, G, M, rhs, m, b_out, info);
+  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kSolveThreads), 0, s, G, M, m, b_out, info);
   return ws_last("k_chol_solve");
 }
 

@@ -273,8 +273,9 @@ def test_learned_warm_start_argument_checks(lib):
 
 def test_restricted_solve_workspace_size(lib):
     """The restricted solve's workspace: 0 outside 1 <= m <= GS_WS_MAX, at
-    least the 8 M^2 bytes of the matrix (M = m rounded up to 64), at most
-    15 MB more (the row-split partial Gram sums), and never smaller for a
+    least the 8 M (M + 64) bytes of the matrix and its right-hand-side tile
+    row (M = m rounded up to 64), at most 15 MB more (the row-split partial
+    Gram sums), and never smaller for a
     larger m -- the learned driver sizes one workspace for its largest
     working set and runs every smaller solve in it."""
     hdr = open(os.path.join(ROOT, "include", "gapsafe.h")).read()
@@ -286,6 +287,6 @@ def test_restricted_solve_workspace_size(lib):
     for m in range(1, gs.GS_WS_MAX + 1):
         need = lib.gs_restricted_solve_workspace_size(m)
         M = (m + 63) // 64 * 64
-        assert 8 * M * M <= need <= 8 * (M * M + M) + 15_000_000 + 256, m
+        assert 8 * M * (M + 64) <= need <= 8 * M * (M + 64) + 15_000_000 + 256, m
         assert need >= prev, m
         prev = need
